@@ -1,0 +1,205 @@
+"""Pins for the oracle's force sweeps (CPU only).
+
+The fixed-point link-cell sweep is pinned to brute force (bit-exact), the
+FP64 brute force to an independent numpy transcription of the pair sum, and
+all of them to closed forms: the two-body Lennard-Jones force, the FCC
+lattice energy, and momentum conservation.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1401_4441_amd import synth
+
+S = O.SCALE
+
+
+def _tiny(n=400, rho=0.8, seed=5):
+    return synth.fcc(n, rho, rc=2.5, seed=seed)
+
+
+def test_two_body_closed_form():
+    """|F| = 24 (2 r^-13 - r^-7) along the separation; zero at r = 2^(1/6)."""
+    L = np.array([20.0, 20.0, 20.0])
+    for r in (0.95, 1.0, 2 ** (1 / 6), 1.5, 2.2, 2.49):
+        pos = np.array([[5.0, 5.0 + r], [7.0, 7.0], [9.0, 9.0]])
+        want = O.lj_pair_force_magnitude(r)
+        F, mag, U, W, npairs = O.forces_brute_f64(pos, L, 2.5)
+        assert npairs == 1
+        # force on particle 1 points away from 0 when repulsive
+        assert F[0, 1] == pytest.approx(want, rel=1e-12, abs=1e-12)
+        assert F[0, 0] == pytest.approx(-want, rel=1e-12, abs=1e-12)
+        assert W == pytest.approx(want * r, rel=1e-12, abs=1e-12)
+        uc = 4 * (2.5 ** -12 - 2.5 ** -6)
+        assert U == pytest.approx(4 * (r ** -12 - r ** -6) - uc, rel=1e-12, abs=1e-13)
+        u = O.canonical(pos, L)
+        Fq, Eq, Wq, _ = O.forces_brute_fx(u, L, 2.5)
+        assert Fq[0, 1] / S == pytest.approx(want, rel=2e-6, abs=1e-8)
+        assert Fq[0, 1] == -Fq[0, 0]
+    pos = np.array([[5.0, 5.0 + 2 ** (1 / 6)], [7.0, 7.0], [9.0, 9.0]])
+    F, *_ = O.forces_brute_f64(pos, L, 2.5)
+    assert abs(F[0, 1]) < 1e-12
+
+
+def test_cutoff_is_strict():
+    L = np.array([20.0, 20.0, 20.0])
+    pos = np.array([[5.0, 7.5], [7.0, 7.0], [9.0, 9.0]])
+    assert O.forces_brute_f64(pos, L, 2.5)[4] == 0
+    assert O.forces_brute_fx(O.canonical(pos, L), L, 2.5)[3] == 0
+
+
+def test_minimum_image_across_boundary():
+    """A pair split by the periodic boundary interacts through the wrap."""
+    L = np.array([10.0, 10.0, 10.0])
+    pos = np.array([[0.4, 9.1], [5.0, 5.0], [5.0, 5.0]])  # 1.3 apart via wrap
+    F, _, _, _, npairs = O.forces_brute_f64(pos, L, 2.5)
+    want = O.lj_pair_force_magnitude(1.3)
+    assert npairs == 1
+    assert F[0, 0] == pytest.approx(want, rel=1e-12)
+    Fq, _, _, _ = O.forces_brute_fx(O.canonical(pos, L), L, 2.5)
+    assert Fq[0, 0] / S == pytest.approx(want, rel=2e-6)
+
+
+def test_brute_f64_matches_numpy_definition():
+    b = _tiny(300)
+    F, mag, U, W, npairs = O.forces_brute_f64(b.pos, b.L, b.rc)
+    F2, U2, np2 = O.brute_numpy_f64(b.pos, b.L, b.rc)
+    assert npairs == np2
+    scale = np.abs(F2).max()
+    assert np.abs(F - F2).max() <= 1e-12 * scale
+    assert U == pytest.approx(U2, rel=1e-12)
+
+
+def test_lc_fixed_point_bit_exact_vs_brute():
+    b = _tiny(500, seed=11)
+    u = O.canonical(b.pos, b.L)
+    nc = O.grid_dims(b.L, b.rc)
+    assert (nc >= 3).all()
+    Fb, Eb, Wb, npb = O.forces_brute_fx(u, b.L, b.rc)
+    Fl, El, Wl, npl = O.forces_lc_fx(u, b.L, b.rc, nc)
+    assert npb == npl
+    assert (Fb == Fl).all()
+    assert (Eb, Wb) == (El, Wl)
+
+
+def test_lc_f64_matches_brute():
+    b = _tiny(500, seed=12)
+    u = O.canonical(b.pos, b.L)
+    nc = O.grid_dims(b.L, b.rc)
+    Fb, _, Ub, Wb, npb = O.forces_brute_f64(b.pos, b.L, b.rc)
+    Fl, Ul, Wl, npl = O.forces_lc_f64(b.pos, u, b.L, b.rc, nc)
+    assert npb == npl
+    assert np.abs(Fb - Fl).max() <= 1e-12 * np.abs(Fb).max()
+    assert Ul == pytest.approx(Ub, rel=1e-12)
+
+
+def test_stencil_choice_does_not_change_forces():
+    """Any half shell covers each neighbouring cell pair once (Fig. 3 reading
+    only matters for scheduling): H3, its mirror and a z-major half shell
+    give identical bits."""
+    b = _tiny(500, seed=13)
+    u = O.canonical(b.pos, b.L)
+    nc = O.grid_dims(b.L, b.rc)
+    ref = O.forces_lc_fx(u, b.L, b.rc, nc, O.H3)
+    mirror = [(-x, -y, -z) for x, y, z in O.H3]
+    zmajor = [(x, y, 1) for y in (-1, 0, 1) for x in (-1, 0, 1)] + \
+             [(x, 1, 0) for x in (-1, 0, 1)] + [(1, 0, 0)]
+    for st in (mirror, zmajor):
+        out = O.forces_lc_fx(u, b.L, b.rc, nc, st)
+        assert (out[0] == ref[0]).all() and out[1:] == ref[1:]
+
+
+def test_momentum_conservation():
+    b = _tiny(500, seed=14)
+    u = O.canonical(b.pos, b.L)
+    Fq, *_ = O.forces_lc_fx(u, b.L, b.rc, O.grid_dims(b.L, b.rc))
+    assert (Fq.sum(axis=1) == 0).all()
+    F, mag, *_ = O.forces_brute_f64(b.pos, b.L, b.rc)
+    assert np.abs(F.sum(axis=1)).max() <= 1e-12 * mag.sum()
+
+
+def test_permutation_invariance():
+    b = _tiny(500, seed=15)
+    u = O.canonical(b.pos, b.L)
+    nc = O.grid_dims(b.L, b.rc)
+    Fq, E, W, npairs = O.forces_lc_fx(u, b.L, b.rc, nc)
+    perm = np.random.default_rng(0).permutation(b.n)
+    Fp, Ep, Wp, npp = O.forces_lc_fx(u[:, perm], b.L, b.rc, nc)
+    assert (Fp == Fq[:, perm]).all() and (E, W, npairs) == (Ep, Wp, npp)
+
+
+def test_fcc_lattice_sums():
+    """Perfect FCC at density 0.8: shells of 12, 6, 24, 12 neighbours at
+    a/sqrt2, a, a sqrt(3/2), a sqrt2 lie inside rc = 2.5 (27 pairs per
+    particle); U/N = 1/2 sum z_s (u(r_s) - u(rc)); net forces vanish."""
+    b = synth.fcc(864, 0.8, rc=2.5, jitter=0.0, seed=1)  # 6^3 unit cells
+    a = b.meta["a"]
+    shells = [(12, a / math.sqrt(2)), (6, a), (24, a * math.sqrt(1.5)),
+              (12, a * math.sqrt(2))]
+    assert shells[-1][1] < 2.5 < a * math.sqrt(2.5)
+    uc = 4 * (2.5 ** -12 - 2.5 ** -6)
+    u_per = 0.5 * sum(z * (4 * (r ** -12 - r ** -6) - uc) for z, r in shells)
+    F, mag, U, W, npairs = O.forces_brute_f64(b.pos, b.L, b.rc)
+    assert npairs == 27 * b.n
+    assert U / b.n == pytest.approx(u_per, rel=1e-12)
+    assert np.abs(F).max() <= 1e-10
+    u = O.canonical(b.pos, b.L)
+    Fq, Eq, _, npq = O.forces_brute_fx(u, b.L, b.rc)
+    assert npq == 27 * b.n
+    assert Eq / S / b.n == pytest.approx(u_per, rel=1e-6)
+    assert np.abs(Fq).max() / S <= 1e-4
+
+
+def test_fixed_point_within_1e5_of_fp64():
+    """FP32 pair math with int64 accumulation: normwise error against FP64
+    over the same pair set <= 1e-5, and per particle <= 1e-5 sum_j |f_ij|."""
+    b = synth.fcc(4000, 0.8, rc=2.5, seed=1001)
+    u = O.canonical(b.pos, b.L)
+    nc = O.grid_dims(b.L, b.rc)
+    Fq, Eq, Wq, npq = O.forces_lc_fx(u, b.L, b.rc, nc)
+    F, mag, U, W, np64 = O.forces_brute_f64(b.pos, b.L, b.rc, u=u)
+    assert npq == np64
+    Fx = Fq / S
+    err = np.linalg.norm(Fx - F) / np.linalg.norm(F)
+    assert err <= 1e-5
+    assert (np.abs(Fx - F).max(axis=0) <= 1e-5 * mag).all()
+    assert Eq / S == pytest.approx(U, rel=1e-5)
+    assert Wq / S == pytest.approx(W, rel=1e-5)
+
+
+def test_canonical_coordinates():
+    L = np.array([10.0, 10.0, 10.0])
+    pos = np.array([[0.0, 5.0, 9.999999, -0.25, 10.25],
+                    [1.0, 1.0, 1.0, 1.0, 1.0],
+                    [2.0, 2.0, 2.0, 2.0, 2.0]])
+    u = O.canonical(pos, L)
+    assert u[0, 0] == 0
+    assert u[0, 1] == 2 ** 31
+    # x and x + L map to the same fraction, x - L/40 wraps below 2^32
+    assert u[0, 4] == O.canonical(np.array([[0.25], [1.0], [2.0]]), L)[0, 0]
+    assert u[0, 3] == O.canonical(np.array([[9.75], [1.0], [2.0]]), L)[0, 0]
+
+
+def test_cell_start_counts():
+    b = _tiny(500, seed=16)
+    u = O.canonical(b.pos, b.L)
+    nc = O.grid_dims(b.L, b.rc)
+    cs = O.cell_start(u, nc)
+    assert cs[0] == 0 and cs[-1] == b.n
+    assert (np.diff(cs) >= 0).all()
+    # each particle's box fraction lies inside its cell's range
+    cid = O.cell_ids(u, nc)
+    cx = cid % nc[0]
+    lo = np.ceil(cx * 2.0 ** 32 / nc[0])
+    assert (u[0] >= lo).all()
+
+
+def test_grid_rejects_small_or_tight_cells():
+    b = _tiny(400)
+    u = O.canonical(b.pos, b.L)
+    with pytest.raises(O.OracleError):
+        O.forces_lc_fx(u, b.L, b.rc, (2, 3, 3))
+    with pytest.raises(O.OracleError):
+        O.forces_lc_fx(u, b.L, b.L[0] / 3, (3, 3, 3))  # side == rc, no margin
