@@ -1,0 +1,285 @@
+/*
+ * lc.h -- C-ABI of the MI355X link-cell force sweep with conflict-free cell
+ * schedules.
+ *
+ * The method (Niethammer, Glass, Gracia, "Avoiding Serialization Effects in
+ * Data / Dependency aware Task Parallel Algorithms for Spatial
+ * Decomposition"):
+ *   - Sec. IV: link-cell (LC) method -- the periodic box is cut into cells of
+ *     side >= rc; with Newton's third law every pair is evaluated once and
+ *     both particles are updated, so a cell only visits the half stencil of
+ *     Fig. 3 (13 neighbour cells in 3D) plus itself.  One task = one
+ *     cell-cell interaction, and it writes into BOTH cells.
+ *   - Sec. V: because tasks that write a common cell are serialised, the
+ *     ORDER in which tasks are created fixes the critical path of the task
+ *     DAG and hence the attainable speedup S = t_s / t_cp (Eq. 1), modelled by
+ *     S(Delta, k, n) = n k / (n + Delta (k - 1)) (Eq. 2, 3, 4).
+ *   - Sec. VI: remedies -- loop exchange with two-strided colouring
+ *     (strategy 1), nested tasks (2), buffer + reduce (3).
+ *
+ * Conventions
+ *   - Every function returns an int status: LC_OK (0) or a negative LC_E*
+ *     code; lc_last_error() gives a thread-local message for the last error.
+ *     No C++ exception crosses this boundary.
+ *   - Device pointers (marked [device]) are caller-owned HIP device memory;
+ *     the library never frees them.  Host pointers are marked [host].
+ *     Opaque handles (lc_schedule, lc_workspace) are created and destroyed by
+ *     the library and belong to the device that was current at creation.
+ *   - Particle arrays are SoA "3 x N": all x, then all y, then all z, each
+ *     row N elements long and contiguous.
+ *   - Device work is enqueued asynchronously on `stream` (a hipStream_t,
+ *     NULL = the null stream); no call below synchronises unless it says so.
+ *   - Fixed point: forces, energies and virials are int64 in units of 2^-32
+ *     (multiply by 2^-32 to get reduced LJ units).  Integer sums commute, so
+ *     every schedule yields the same bits.
+ *
+ * Canonical pair arithmetic (the definition the GPU and any checker share):
+ *   box fraction   u_d = floor((x_d * (1/L_d)) * 2^32) mod 2^32   (FP64)
+ *   separation     d_d = (float)(int32)(u_d[j] - u_d[i]) * s_d,
+ *                  s_d = (float)(L_d * 2^-32)   -- minimum image for free
+ *   then in FP32, rounding after every operation (no FMA):
+ *     r2 = (dx*dx + dy*dy) + dz*dz;   pair used iff r2 < (float)(rc*rc)
+ *     inv = 1/r2 (correctly rounded); s6 = (inv*inv)*inv
+ *     fs = ((24*inv)*s6)*((2*s6) - 1);    force on j = +fs*d, on i = -fs*d
+ *     e  = ((4*s6)*(s6 - 1)) - e_c        (e_c: same sequence at r2 = rc2)
+ *     w  = fs*r2
+ *   each of fs*d_x, fs*d_y, fs*d_z, e, w rounded to nearest-even int64 at
+ *   scale 2^32.
+ */
+#ifndef LC_H
+#define LC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define LC_OK 0
+#define LC_EINVAL (-1)    /* bad argument (sizes, null pointers, grid)      */
+#define LC_ENOMEM (-2)    /* host or device allocation failed               */
+#define LC_EHIP (-3)      /* a HIP runtime call failed                      */
+#define LC_ESCHED (-4)    /* schedule validator: a phase has shared writes  */
+#define LC_EOVERFLOW (-5) /* fixed-point range exceeded (device flag)       */
+#define LC_EDISP (-6)     /* a particle moved more than skin/2 (device flag)*/
+#define LC_ECAPACITY (-7) /* a size exceeds a documented maximum            */
+
+/* Device status flags (lc_workspace_status). */
+#define LC_FLAG_OVERFLOW 1u  /* |quantised term| >= 2^62 or r2 == 0          */
+#define LC_FLAG_DISP 2u      /* displacement since rebuild > skin / 2        */
+#define LC_FLAG_FALLBACK 4u  /* a cell group exceeded the LDS tile and ran
+                                through the global-memory path (info only)   */
+
+/* Last error message of the calling thread (never NULL). */
+const char *lc_last_error(void);
+
+/* ---- grid --------------------------------------------------------------- */
+
+#define LC_GRID_EVEN 1 /* round the cell count per axis down to even       */
+
+/* Periodic cell grid (Sec. IV: cells of side >= rc).  Filled by
+ * lc_make_grid; plain data, may be copied. */
+typedef struct lc_grid {
+    double box[3];     /* edge lengths L_d                                  */
+    double inv_box[3]; /* 1 / L_d                                           */
+    double rc;         /* cutoff radius                                     */
+    double skin;       /* extra cell width for delayed rebuilds             */
+    int32_t nc[3];     /* cells per axis, each >= 3                         */
+    int32_t ncell;     /* nc[0] * nc[1] * nc[2]                             */
+    float scale[3];    /* (float)(L_d * 2^-32)                              */
+    float rc2;         /* (float)(rc * rc)                                  */
+    float ecut;        /* canonical pair energy at r2 = rc2                 */
+    int32_t pad;
+} lc_grid;
+
+/* [host] nc_d = floor(L_d / (rc * (1 + 2^-12) + skin)), the largest count
+ * whose cell side covers rc plus the skin with a margin that FP32 rounding of
+ * r2 cannot cross.  flags: LC_GRID_EVEN.  Returns LC_EINVAL when an axis gets
+ * fewer than 3 cells (pairs would be visited twice) or ncell >= 2^31. */
+int lc_make_grid(const double box[3], double rc, double skin, int flags,
+                 lc_grid *out);
+
+/* ---- workspace ---------------------------------------------------------- */
+
+typedef struct lc_workspace lc_workspace;
+
+/* [host] Device scratch for up to max_n particles and max_cells cells
+ * (cell ids, per-cell counters, scan partials, status flags, Verlet
+ * reference positions and staging).  Allocates with hipMalloc on the
+ * current device. */
+int lc_workspace_create(int64_t max_n, int64_t max_cells, lc_workspace **out);
+void lc_workspace_destroy(lc_workspace *ws);
+
+/* Clear the device status flags (async on stream). */
+int lc_workspace_clear_status(lc_workspace *ws, void *stream);
+/* Synchronise `stream` and return the device status flags (LC_FLAG_*). */
+int lc_workspace_status(lc_workspace *ws, void *stream, uint32_t *flags);
+
+/* ---- a1: cell build (Sec. IV) ------------------------------------------- */
+
+/* Counting sort of N particles into the cells of g.
+ *   pos      [device] double 3 x N, any real coordinates (wrapped here)
+ *   cell_start [device] int32 ncell + 1: particles of cell c are sorted
+ *            slots cell_start[c] .. cell_start[c+1]-1 (cells x fastest)
+ *   perm     [device] int32 N: sorted slot k holds input particle perm[k]
+ *   coord    [device] uint32 3 x N: box fractions u of the sorted particles
+ * Order inside a cell is unspecified (atomic ranks); forces do not depend on
+ * it.  Needs a workspace created with max_n >= N, max_cells >= ncell. */
+int lc_build_cells(const lc_grid *g, const double *pos, int64_t n,
+                   int32_t *cell_start, int32_t *perm, uint32_t *coord,
+                   lc_workspace *ws, void *stream);
+
+/* Gather rows of a double 3 x N array (and an optional int32 N array) by
+ * perm: out[:, k] = in[:, perm[k]].  [device] buffers, in != out. */
+int lc_gather(const int32_t *perm, int64_t n, const double *in3, double *out3,
+              const int32_t *in_ids, int32_t *out_ids, void *stream);
+
+/* ---- a2: schedules (Sec. V, Sec. VI strategy 1) ------------------------- */
+
+/* Creation orders / execution strategies. */
+#define LC_SCHED_LEX 0          /* basic order: per cell (x, y, z fastest to
+                                   slowest) intra then the 13 offsets in
+                                   ascending (dz, dy, dx); run as the levels
+                                   of its task DAG                          */
+#define LC_SCHED_OPT 1          /* x neighbour first, intra last (Delta = 1)*/
+#define LC_SCHED_BEST 2         /* intra, x neighbour, rest (Delta = 2)     */
+#define LC_SCHED_BAD 3          /* intra first, x neighbour last (Delta=14) */
+#define LC_SCHED_LOOPEX 4       /* loop exchange + 2-strided colouring
+                                   (offset-major, 2x2x2 colours; needs even
+                                   cell counts); run as DAG levels (27)     */
+#define LC_SCHED_BLOCK8 5       /* 2x2x2-coloured blocks of 2-3 cells per
+                                   axis: 8 conflict-free phases, one work-
+                                   group per block, LDS accumulation, plain
+                                   read-modify-write                        */
+#define LC_SCHED_ATOMIC_TILE 6  /* BLOCK8's groups in ONE phase with global
+                                   int64 atomic write-back                  */
+#define LC_SCHED_ATOMIC_PAIR 7  /* one phase, one group per home cell, every
+                                   pair adds into both particles with global
+                                   int64 atomics (the plain atomics baseline)*/
+#define LC_SCHED_CUSTOM 8       /* basic order with a caller-given stencil
+                                   order (offsets argument)                 */
+#define LC_SCHED_COUNT 9
+
+typedef struct lc_schedule lc_schedule;
+
+typedef struct lc_schedule_info {
+    int32_t kind;
+    int32_t nphase;   /* kernel launches per force evaluation               */
+    int64_t ntask;    /* cell-cell interactions (14 per cell)               */
+    int64_t ngroup;   /* work-groups over all phases                        */
+    int32_t max_group_tasks;
+    int32_t max_group_cells;
+    int32_t write_mode; /* 0 plain RMW, 1 atomic tile, 2 atomic per pair    */
+    int32_t pad;
+} lc_schedule_info;
+
+/* [host] Build the task list of `kind` for grid g, split it into phases
+ * whose work-groups write disjoint cells (validated: LC_ESCHED otherwise),
+ * and upload it to the current device.  offsets/n: for LC_SCHED_CUSTOM the
+ * stencil order (n x 3 int8, (0,0,0) = intra, the other n-1 entries one of
+ * d / -d for every neighbour d); ignored (may be NULL) for other kinds. */
+int lc_make_schedule(const lc_grid *g, int kind, const int8_t *offsets, int n,
+                     lc_schedule **out);
+int lc_schedule_info_get(const lc_schedule *s, lc_schedule_info *out);
+void lc_schedule_free(lc_schedule *s);
+
+/* [host only] Build and validate the schedule of `kind` like
+ * lc_make_schedule, without touching a device; fills *out. */
+int lc_schedule_plan(const lc_grid *g, int kind, const int8_t *offsets, int n,
+                     lc_schedule_info *out);
+
+/* [host only] The schedule validator on an explicit phase list: phase p runs
+ * work-groups phase_grp[p] .. phase_grp[p+1]-1, group k writes the cells
+ * foot_cells[grp_foot[k] .. grp_foot[k+1]-1].  Returns LC_OK when every
+ * phase's groups write pairwise disjoint cells (so plain read-modify-write
+ * is race-free), LC_ESCHED otherwise, LC_EINVAL on malformed input. */
+int lc_validate_phases(int64_t ncell, int32_t nphase, const int32_t *phase_grp,
+                       const int32_t *grp_foot, const int32_t *foot_cells);
+
+/* ---- a3: serialisation degree (Sec. V, Eq. 1-4) ------------------------- */
+
+typedef struct lc_sd_result {
+    int64_t tasks;    /* T                                                  */
+    int64_t cp;       /* critical path, in tasks (unit durations)           */
+    double speedup;   /* S = T / cp  (Eq. 1)                                */
+    double degree;    /* cp / T, 1 = fully serial                           */
+    int32_t n;        /* tasks per stencil                                  */
+    int32_t delta;    /* stencil displacement Delta (0 for LC_SCHED_LOOPEX) */
+    double s_eq2;     /* Eq. 2 with k = number of cells                     */
+    double s_max;     /* Eq. 3: n / Delta                                   */
+} lc_sd_result;
+
+/* [host only] Critical path of the task DAG of a creation order under the
+ * StarSs inout rule (consecutive tasks touching a cell are dependent).
+ *   dims  cells per axis; dims[2] == 1 selects the 2D stencil of Fig. 3(a)
+ *   kind  LC_SCHED_LEX/OPT/BEST/BAD/LOOPEX/CUSTOM (2D presets: Fig. 5 naive,
+ *         optimal, best basic, bad)
+ *   level_hist [host, optional] int64 array of length hist_len: tasks per
+ *         DAG level (level l at index l-1); entries beyond cp are zeroed.
+ * O(T) time (last-writer recurrence). */
+int lc_serialization_degree(const int32_t dims[3], int kind,
+                            const int8_t *offsets, int n, int64_t *level_hist,
+                            int64_t hist_len, lc_sd_result *out);
+
+/* ---- a4-a6: force sweep ------------------------------------------------- */
+
+#define LC_PREC_FP32 0 /* canonical FP32 pair arithmetic (bit-exact)        */
+#define LC_PREC_FP64 1 /* FP64 pair arithmetic from the same box fractions,
+                          same pair set (the FP32 cutoff test), same int64
+                          quantisation -- a precision reference             */
+
+/* One Lennard-Jones force evaluation over all cell-cell tasks of s, phase by
+ * phase.  Inputs come from lc_build_cells on the same grid:
+ *   cell_start [device] int32 ncell+1;  coord [device] uint32 3 x N
+ *   F   [device] int64 3 x N, cell-sorted order, OVERWRITTEN with the force
+ *   ew  [device] int64 [3]: OVERWRITTEN with {energy, virial, pairs in
+ *       cutoff} (energy/virial in units of 2^-32)
+ * Status flags (overflow, fallback) accumulate in ws. */
+int lc_compute_forces(const lc_grid *g, const lc_schedule *s,
+                      const int32_t *cell_start, const uint32_t *coord,
+                      int64_t n, int64_t *F, int64_t *ew, int precision,
+                      lc_workspace *ws, void *stream);
+
+/* Profiling variant of lc_compute_forces: the same launches, each sweep
+ * phase bracketed by HIP events on `stream`; synchronises and returns the
+ * summed device time of the sweep kernels in *sweep_ms (the zero-fill of F
+ * and ew is not included) and, if phase_ms is not NULL, the time of each
+ * phase (host array of nphase doubles). */
+int lc_compute_forces_profiled(const lc_grid *g, const lc_schedule *s,
+                               const int32_t *cell_start, const uint32_t *coord,
+                               int64_t n, int64_t *F, int64_t *ew, int precision,
+                               lc_workspace *ws, void *stream, double *sweep_ms,
+                               double *phase_ms);
+
+/* ---- a7: velocity Verlet ------------------------------------------------ */
+
+/* nsteps kick-drift-kick steps (unit mass) on a cell-sorted state:
+ *   pos, vel [device] double 3 x N; ids [device] int32 N (particle identity,
+ *   permuted along at every rebuild, may be NULL); F [device] int64 3 x N;
+ *   cell_start [device] int32 ncell+1, perm [device] int32 N, coord
+ *   [device] uint32 3 x N as in lc_build_cells.
+ * Step: a = F*2^-32; v = v + (0.5 dt)*a; x = x + dt*v; every rebuild_every
+ * steps rebuild cells and reorder pos/vel/ids; F = forces(x);
+ * v = v + (0.5 dt)*a.  trace receives {KE, PE} in
+ * units of 2^-32, KE = sum_i rint(0.5*((vx^2+vy^2)+vz^2)
+ * * 2^32).  A displacement beyond skin/2 since the last rebuild raises
+ * LC_FLAG_DISP (check with lc_workspace_status).  The call starts by sorting
+ * into cells and evaluating forces at the given positions, so pos/vel/ids may
+ * come in any order and F/cell_start/perm/coord are outputs; trace [device]
+ * int64 (nsteps+1) x 2, row 0 being the initial state. */
+int lc_verlet_step(const lc_grid *g, const lc_schedule *s, double *pos,
+                   double *vel, int32_t *ids, int64_t n, int64_t *F,
+                   int32_t *cell_start, int32_t *perm, uint32_t *coord,
+                   double dt, int nsteps, int rebuild_every, int64_t *trace,
+                   lc_workspace *ws, void *stream);
+
+/* Kinetic energy {sum of rint(0.5 v^2 2^32)} into ke[0] (device int64). */
+int lc_kinetic_energy(const double *vel, int64_t n, int64_t *ke,
+                      void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LC_H */

@@ -1,0 +1,1206 @@
+// lc.hip -- MI355X (gfx950) kernels and C-ABI of the link-cell force sweep.
+//
+// Kernels
+//   k_fill64 / k_fill32     zero-fill (used instead of hipMemsetAsync so the
+//                           whole path can sit inside a captured graph)
+//   k_bin                   cell of each particle + atomic rank in its cell
+//   k_scan_*                exclusive scan of per-cell counts -> cell_start
+//   k_scatter               counting-sort scatter: perm + sorted box fractions
+//   k_sweep<CAP,WMODE,F64>  one phase of cell-cell tasks (Sec. IV): per
+//                           work-group a group of tasks whose footprint cells
+//                           are staged in LDS; lanes own j particles, loop over
+//                           i; in-cutoff pairs are compacted into a per-wave
+//                           queue and evaluated 64 at a time; int64 forces
+//                           accumulate in LDS and are written back with plain
+//                           read-modify-write (conflict-free phase) or global
+//                           atomics
+//   k_kick_drift / k_kick_ke  velocity Verlet halves (FP64)
+//   k_gather                reorder SoA rows by a permutation
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lc.h"
+#include "lc_sched.h"
+
+#pragma clang fp contract(off)
+
+// ---------------------------------------------------------------------------
+// error handling
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(call)                                                           \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return fail(LC_EHIP, "%s: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+#define LAUNCHCHK(what)                                                        \
+    do {                                                                       \
+        hipError_t e_ = hipGetLastError();                                     \
+        if (e_ != hipSuccess)                                                  \
+            return fail(LC_EHIP, "launch %s: %s", what, hipGetErrorString(e_));\
+    } while (0)
+
+extern "C" const char *lc_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+
+struct lc_workspace {
+    int device = 0;
+    int64_t max_n = 0, max_cells = 0;
+    int32_t *cid = nullptr;      // N: cell of particle
+    int32_t *rank = nullptr;     // N: rank inside its cell
+    int32_t *counts = nullptr;   // max_cells: per-cell counters
+    int32_t *partial = nullptr;  // scan block totals
+    uint32_t *flags = nullptr;   // device status flags
+    int64_t *ew = nullptr;       // 3: energy, virial, pairs
+    int64_t *ke = nullptr;       // 1
+    double *xref = nullptr;      // 3N positions at the last rebuild
+    double *tmp3 = nullptr;      // 3N staging for reorders
+    int32_t *tmpi = nullptr;     // N staging for ids
+};
+
+struct lc_schedule {
+    int device = 0;
+    int32_t nc[3] = {0, 0, 0};
+    lcs::HostSchedule h;
+    int32_t *grp_task = nullptr, *grp_foot = nullptr, *foot_cells = nullptr;
+    uint32_t *task_ab = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+constexpr int kWG = 512;            // threads per sweep work-group
+constexpr int kNW = kWG / 64;       // waves per sweep work-group
+constexpr int kQ = 128;             // per-wave pair queue (>= 64 + 63)
+constexpr int kMaxT = lcs::kMaxGroupTasks;
+constexpr int kMaxF = lcs::kMaxGroupCells;
+
+static_assert(kMaxT <= kWG && kMaxF <= kWG, "tables scanned one item per thread");
+
+struct PairParams {
+    float s[3];    // (float)(L * 2^-32)
+    float rc2;     // (float)(rc * rc)
+    float ecut;    // canonical pair energy at rc2
+    double sd[3];  // L * 2^-32 (exact) for the FP64 variant
+    double rc2d;   // rc * rc
+    double ecutd;  // FP64 pair energy at rc
+};
+
+// Box fraction of one coordinate: floor((x * (1/L)) * 2^32) mod 2^32.
+__device__ __forceinline__ uint32_t canon(double x, double inv) {
+    double s = x * inv;
+    double f = floor(s * 4294967296.0);
+    return (uint32_t)(long long)f;
+}
+
+__device__ __forceinline__ int cell_of(uint32_t u, int nc) {
+    return (int)(((unsigned long long)u * (unsigned long long)nc) >> 32);
+}
+
+// Round-to-nearest-even of v * 2^32 as int64; flags |q| >= 2^62 and NaN.
+__device__ __forceinline__ long long q32f(float v, uint32_t &ovf) {
+    float s = v * 4294967296.0f;  // exact scaling by a power of two
+    if (!(fabsf(s) < 4611686018427387904.0f)) {
+        ovf = 1u;
+        return 0;
+    }
+    return (long long)rintf(s);
+}
+
+__device__ __forceinline__ long long q32d(double v, uint32_t &ovf) {
+    double s = v * 4294967296.0;
+    if (!(fabs(s) < 4611686018427387904.0)) {
+        ovf = 1u;
+        return 0;
+    }
+    return (long long)rint(s);
+}
+
+__device__ __forceinline__ float canon_d(uint32_t uj, uint32_t ui, float s) {
+    return (float)(int)(uj - ui) * s;
+}
+
+// Canonical FP32 cutoff test (identical in both precisions).
+__device__ __forceinline__ float canon_r2(uint32_t ix, uint32_t iy, uint32_t iz,
+                                          uint32_t jx, uint32_t jy, uint32_t jz,
+                                          const PairParams &p) {
+    float dx = canon_d(jx, ix, p.s[0]);
+    float dy = canon_d(jy, iy, p.s[1]);
+    float dz = canon_d(jz, iz, p.s[2]);
+    float r2 = dx * dx + dy * dy;
+    return r2 + dz * dz;
+}
+
+// One pair: returns false when outside the cutoff.  q* receive the
+// quantised force on j (i gets the negation), energy and virial.
+template <bool F64>
+__device__ __forceinline__ bool pair_terms(uint32_t ix, uint32_t iy, uint32_t iz,
+                                           uint32_t jx, uint32_t jy, uint32_t jz,
+                                           const PairParams &p, long long &qx,
+                                           long long &qy, long long &qz,
+                                           long long &qe, long long &qw,
+                                           uint32_t &ovf) {
+    float dx = canon_d(jx, ix, p.s[0]);
+    float dy = canon_d(jy, iy, p.s[1]);
+    float dz = canon_d(jz, iz, p.s[2]);
+    float r2 = dx * dx + dy * dy;
+    r2 = r2 + dz * dz;
+    if (!(r2 < p.rc2)) return false;
+    if constexpr (!F64) {
+        float inv = 1.0f / r2;
+        float s6 = inv * inv;
+        s6 = s6 * inv;
+        float t = 24.0f * inv;
+        t = t * s6;
+        float g = 2.0f * s6;
+        g = g - 1.0f;
+        float fs = t * g;
+        qx = q32f(fs * dx, ovf);
+        qy = q32f(fs * dy, ovf);
+        qz = q32f(fs * dz, ovf);
+        float e = 4.0f * s6;
+        e = e * (s6 - 1.0f);
+        e = e - p.ecut;
+        qe = q32f(e, ovf);
+        qw = q32f(fs * r2, ovf);
+    } else {
+        double ddx = (double)(int)(jx - ix) * p.sd[0];
+        double ddy = (double)(int)(jy - iy) * p.sd[1];
+        double ddz = (double)(int)(jz - iz) * p.sd[2];
+        double r2d = ddx * ddx + ddy * ddy + ddz * ddz;
+        double inv = 1.0 / r2d;
+        double s6 = inv * inv * inv;
+        double fs = 24.0 * inv * s6 * (2.0 * s6 - 1.0);
+        qx = q32d(fs * ddx, ovf);
+        qy = q32d(fs * ddy, ovf);
+        qz = q32d(fs * ddz, ovf);
+        qe = q32d(4.0 * s6 * (s6 - 1.0) - p.ecutd, ovf);
+        qw = q32d(fs * r2d, ovf);
+    }
+    return true;
+}
+
+__device__ __forceinline__ long long wave_sum64(long long v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ int wave_max32(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Exclusive scan of one int per thread over a work-group of NT threads.
+template <int NT>
+__device__ int block_scan_excl(int v, int *s_w, int &total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int k = 0; k < NT / 64; ++k) {
+            int t = s_w[k];
+            s_w[k] = acc;
+            acc += t;
+        }
+        s_w[NT / 64] = acc;
+    }
+    __syncthreads();
+    total = s_w[NT / 64];
+    int r = x - v + s_w[w];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// fills
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill64(long long *p, int64_t n, long long v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += st) p[i] = v;
+}
+
+__global__ void k_fill32(int *p, int64_t n, int v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += st) p[i] = v;
+}
+
+static int grid_for(int64_t n, int bs) {
+    int64_t b = (n + bs - 1) / bs;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+static int fill64(long long *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return LC_OK;
+    hipLaunchKernelGGL(k_fill64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, 0LL);
+    LAUNCHCHK("fill64");
+    return LC_OK;
+}
+
+static int fill32(int *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return LC_OK;
+    hipLaunchKernelGGL(k_fill32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, 0);
+    LAUNCHCHK("fill32");
+    return LC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// a1: cell build
+// ---------------------------------------------------------------------------
+
+struct GridArgs {
+    double inv[3];
+    int nc[3];
+};
+
+__global__ void k_bin(const double *__restrict__ pos, int64_t n, GridArgs ga,
+                      int *__restrict__ cid, int *__restrict__ rank,
+                      int *__restrict__ counts) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c[3];
+    for (int d = 0; d < 3; ++d) c[d] = cell_of(canon(pos[d * n + i], ga.inv[d]), ga.nc[d]);
+    int cc = c[0] + ga.nc[0] * (c[1] + ga.nc[1] * c[2]);
+    cid[i] = cc;
+    rank[i] = atomicAdd(&counts[cc], 1);
+}
+
+constexpr int kScanBS = 256, kScanIPT = 4, kScanTile = kScanBS * kScanIPT;
+
+__global__ __launch_bounds__(kScanBS) void k_scan_reduce(const int *__restrict__ in, int64_t m,
+                                                         int *__restrict__ partial) {
+    __shared__ int s_w[kScanBS / 64 + 1];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanIPT;
+    int v = 0;
+    for (int k = 0; k < kScanIPT; ++k)
+        if (base + k < m) v += in[base + k];
+    int total;
+    block_scan_excl<kScanBS>(v, s_w, total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanBS) void k_scan_top(int *__restrict__ partial, int nb) {
+    __shared__ int s_w[kScanBS / 64 + 1];
+    int carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += kScanBS) {
+        int k = b0 + threadIdx.x;
+        int v = k < nb ? partial[k] : 0;
+        int total;
+        int e = block_scan_excl<kScanBS>(v, s_w, total);
+        if (k < nb) partial[k] = e + carry;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kScanBS) void k_scan_final(const int *__restrict__ in, int64_t m,
+                                                        const int *__restrict__ partial,
+                                                        int *__restrict__ out) {
+    __shared__ int s_w[kScanBS / 64 + 1];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanIPT;
+    int v[kScanIPT];
+    int sum = 0;
+    for (int k = 0; k < kScanIPT; ++k) {
+        v[k] = base + k < m ? in[base + k] : 0;
+        sum += v[k];
+    }
+    int total;
+    int e = block_scan_excl<kScanBS>(sum, s_w, total) + partial[blockIdx.x];
+    for (int k = 0; k < kScanIPT; ++k) {
+        if (base + k < m) out[base + k] = e;
+        e += v[k];
+    }
+    // the end marker: total particle count
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[m] = partial[blockIdx.x] + total;
+}
+
+__global__ void k_scatter(const double *__restrict__ pos, int64_t n, GridArgs ga,
+                          const int *__restrict__ cid, const int *__restrict__ rank,
+                          const int *__restrict__ cell_start, int *__restrict__ perm,
+                          uint32_t *__restrict__ coord) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t dst = (int64_t)cell_start[cid[i]] + rank[i];
+    perm[dst] = (int)i;
+    for (int d = 0; d < 3; ++d) coord[d * n + dst] = canon(pos[d * n + i], ga.inv[d]);
+}
+
+static int build_cells_impl(const lc_grid *g, const double *pos, int64_t n, int32_t *cell_start,
+                            int32_t *perm, uint32_t *coord, lc_workspace *ws, hipStream_t st) {
+    const int64_t m = g->ncell;
+    GridArgs ga;
+    for (int d = 0; d < 3; ++d) {
+        ga.inv[d] = g->inv_box[d];
+        ga.nc[d] = g->nc[d];
+    }
+    int rc = fill32(ws->counts, m, st);
+    if (rc) return rc;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_bin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n, ga,
+                           ws->cid, ws->rank, ws->counts);
+        LAUNCHCHK("k_bin");
+    }
+    const int nb = (int)((m + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBS), 0, st, ws->counts, m, ws->partial);
+    LAUNCHCHK("k_scan_reduce");
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBS), 0, st, ws->partial, nb);
+    LAUNCHCHK("k_scan_top");
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanBS), 0, st, ws->counts, m, ws->partial,
+                       cell_start);
+    LAUNCHCHK("k_scan_final");
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n,
+                           ga, ws->cid, ws->rank, cell_start, perm, coord);
+        LAUNCHCHK("k_scatter");
+    }
+    return LC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// a4/a5: the tile sweep
+// ---------------------------------------------------------------------------
+
+struct SweepArgs {
+    const int *grp_task;
+    const int *grp_foot;
+    const int *foot_cells;
+    const uint32_t *task_ab;
+    int grp_base;
+    const int *cell_start;
+    const uint32_t *coord;
+    int64_t n;
+    long long *F;
+    long long *ew;
+    uint32_t *flags;
+    PairParams pp;
+};
+
+// WMODE: 0 = accumulate in LDS, plain read-modify-write of the footprint
+//        (the phase must be conflict-free); 1 = accumulate in LDS, global
+//        atomic write-back; 2 = every pair adds into global memory with
+//        atomics.
+template <int CAP, int WMODE, bool F64>
+__global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
+    __shared__ uint32_t s_u[3][CAP];
+    __shared__ long long s_acc[WMODE == 2 ? 1 : 3][WMODE == 2 ? 1 : CAP];
+    __shared__ int s_fg[kMaxF];          // global first slot of footprint cell
+    __shared__ int s_fl[kMaxF + 1];      // local first slot (prefix)
+    __shared__ int s_taoff[kMaxT];       // local first slot of cell A
+    __shared__ int s_tna[kMaxT];         // particles in A
+    __shared__ int s_tboff[kMaxT];       // local first slot of cell B (bit 31: intra)
+    __shared__ int s_tslot[kMaxT + 1];   // prefix of |B| over tasks
+    __shared__ uint32_t s_q[kNW][kQ];
+    __shared__ int s_w[kNW + 1];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = a.grp_base + blockIdx.x;
+    const int t0 = a.grp_task[g], nt = a.grp_task[g + 1] - t0;
+    const int f0 = a.grp_foot[g], nf = a.grp_foot[g + 1] - f0;
+    const int64_t n = a.n;
+
+    // footprint table and local layout
+    int cnt = 0;
+    if (tid < nf) {
+        const int c = a.foot_cells[f0 + tid];
+        const int gs = a.cell_start[c];
+        cnt = a.cell_start[c + 1] - gs;
+        s_fg[tid] = gs;
+    }
+    int total;
+    const int lofs = block_scan_excl<kWG>(cnt, s_w, total);
+    if (tid < nf) s_fl[tid] = lofs;
+    if (tid == 0) s_fl[nf] = total;
+    const bool staged = total <= CAP;
+    if (total > 65535) {  // local indices are packed in 16 bits
+        if (tid == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_OVERFLOW);
+        return;
+    }
+    if (!staged && tid == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_FALLBACK);
+    __syncthreads();
+
+    // stage box fractions of the footprint, zero the accumulators
+    if (staged) {
+        for (int f = wave; f < nf; f += kNW) {
+            const int gs = s_fg[f], ls = s_fl[f], c = s_fl[f + 1] - ls;
+            for (int q = lane; q < c; q += 64) {
+                s_u[0][ls + q] = a.coord[gs + q];
+                s_u[1][ls + q] = a.coord[n + gs + q];
+                s_u[2][ls + q] = a.coord[2 * n + gs + q];
+                if constexpr (WMODE != 2) {
+                    s_acc[0][ls + q] = 0;
+                    s_acc[1][ls + q] = 0;
+                    s_acc[2][ls + q] = 0;
+                }
+            }
+        }
+    }
+    // task table
+    int nb = 0;
+    if (tid < nt) {
+        const uint32_t ab = a.task_ab[t0 + tid];
+        const int la = (int)(ab & 0xffffu), lb = (int)(ab >> 16);
+        s_taoff[tid] = s_fl[la];
+        s_tna[tid] = s_fl[la + 1] - s_fl[la];
+        s_tboff[tid] = s_fl[lb] | (la == lb ? (int)0x80000000 : 0);
+        nb = s_fl[lb + 1] - s_fl[lb];
+    }
+    int nslot;
+    const int so = block_scan_excl<kWG>(nb, s_w, nslot);
+    if (tid < nt) s_tslot[tid] = so;
+    if (tid == 0) s_tslot[nt] = nslot;
+    __syncthreads();
+
+    // global slot of a local index (fallback path only)
+    auto gidx = [&](int l) -> int64_t {
+        int lo = 0, hi = nf;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_fl[mid] <= l) lo = mid; else hi = mid;
+        }
+        return (int64_t)s_fg[lo] + (l - s_fl[lo]);
+    };
+    auto load_u = [&](int l, uint32_t &x, uint32_t &y, uint32_t &z) {
+        if (staged) {
+            x = s_u[0][l];
+            y = s_u[1][l];
+            z = s_u[2][l];
+        } else {
+            const int64_t gi = gidx(l);
+            x = a.coord[gi];
+            y = a.coord[n + gi];
+            z = a.coord[2 * n + gi];
+        }
+    };
+
+    const PairParams pp = a.pp;
+    long long e_sum = 0, w_sum = 0, p_cnt = 0;
+    uint32_t ovf = 0;
+    uint32_t *q = s_q[wave];
+    int qn = 0;  // wave-uniform queue length
+
+    // Evaluate the pair in queue slot `slot` (one per lane) and scatter it.
+    auto eval = [&](uint32_t ent) {
+        const int il = (int)(ent & 0xffffu), jl = (int)(ent >> 16);
+        uint32_t ix, iy, iz, jx, jy, jz;
+        load_u(il, ix, iy, iz);
+        load_u(jl, jx, jy, jz);
+        long long qx, qy, qz, qe, qw;
+        if (!pair_terms<F64>(ix, iy, iz, jx, jy, jz, pp, qx, qy, qz, qe, qw, ovf)) return;
+        e_sum += qe;
+        w_sum += qw;
+        p_cnt += 1;
+        if (WMODE != 2 && staged) {
+            atomicAdd((unsigned long long *)&s_acc[0][il], (unsigned long long)(-qx));
+            atomicAdd((unsigned long long *)&s_acc[1][il], (unsigned long long)(-qy));
+            atomicAdd((unsigned long long *)&s_acc[2][il], (unsigned long long)(-qz));
+            atomicAdd((unsigned long long *)&s_acc[0][jl], (unsigned long long)qx);
+            atomicAdd((unsigned long long *)&s_acc[1][jl], (unsigned long long)qy);
+            atomicAdd((unsigned long long *)&s_acc[2][jl], (unsigned long long)qz);
+        } else {
+            const int64_t gi = gidx(il), gj = gidx(jl);
+            unsigned long long *F = (unsigned long long *)a.F;
+            atomicAdd(&F[gi], (unsigned long long)(-qx));
+            atomicAdd(&F[n + gi], (unsigned long long)(-qy));
+            atomicAdd(&F[2 * n + gi], (unsigned long long)(-qz));
+            atomicAdd(&F[gj], (unsigned long long)qx);
+            atomicAdd(&F[n + gj], (unsigned long long)qy);
+            atomicAdd(&F[2 * n + gj], (unsigned long long)qz);
+        }
+    };
+
+    for (int base = wave * 64; base < nslot; base += kNW * 64) {
+        const int s = base + lane;
+        const bool valid = s < nslot;
+        int t = 0;
+        {
+            int lo = 0, hi = nt;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_tslot[mid] <= s) lo = mid; else hi = mid;
+            }
+            t = lo;
+        }
+        const int jj = s - s_tslot[t];
+        const int bo = s_tboff[t];
+        const bool intra = bo < 0;
+        const int jl = (bo & 0x7fffffff) + jj;
+        const int aoff = s_taoff[t];
+        int kend = valid ? s_tna[t] : 0;
+        if (intra) kend = min(kend, jj);
+        uint32_t jx = 0, jy = 0, jz = 0;
+        if (valid) load_u(jl, jx, jy, jz);
+        const int kmax = wave_max32(kend);
+        for (int k = 0; k < kmax; ++k) {
+            const bool act = k < kend;
+            const int il = act ? aoff + k : aoff;
+            bool in = false;
+            if (act) {
+                uint32_t ix, iy, iz;
+                load_u(il, ix, iy, iz);
+                in = canon_r2(ix, iy, iz, jx, jy, jz, pp) < pp.rc2;
+            }
+            const unsigned long long m = __ballot(in);
+            if (in) {
+                const int pos = qn + (int)__popcll(m & ((1ull << lane) - 1ull));
+                q[pos] = (uint32_t)il | ((uint32_t)jl << 16);
+            }
+            qn += (int)__popcll(m);
+            if (qn >= 64) {
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                eval(q[lane]);
+                const uint32_t rest = lane + 64 < qn ? q[lane + 64] : 0u;
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                if (lane + 64 < qn) q[lane] = rest;
+                qn -= 64;
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    if (lane < qn) eval(q[lane]);
+
+    // energy, virial, pair count: one atomic per wave
+    e_sum = wave_sum64(e_sum);
+    w_sum = wave_sum64(w_sum);
+    p_cnt = wave_sum64(p_cnt);
+    if (lane == 0) {
+        atomicAdd((unsigned long long *)&a.ew[0], (unsigned long long)e_sum);
+        atomicAdd((unsigned long long *)&a.ew[1], (unsigned long long)w_sum);
+        atomicAdd((unsigned long long *)&a.ew[2], (unsigned long long)p_cnt);
+    }
+    if (__ballot(ovf != 0u) && lane == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_OVERFLOW);
+
+    if constexpr (WMODE != 2) {
+        if (!staged) return;
+        __syncthreads();
+        unsigned long long *F = (unsigned long long *)a.F;
+        for (int f = wave; f < nf; f += kNW) {
+            const int gs = s_fg[f], ls = s_fl[f], c = s_fl[f + 1] - ls;
+            for (int qq = lane; qq < c; qq += 64) {
+                for (int d = 0; d < 3; ++d) {
+                    const unsigned long long v = (unsigned long long)s_acc[d][ls + qq];
+                    if (WMODE == 0)
+                        F[d * n + gs + qq] += v;
+                    else
+                        atomicAdd(&F[d * n + gs + qq], v);
+                }
+            }
+        }
+    }
+}
+
+template <int CAP, int WMODE, bool F64>
+static int launch_sweep_t(const SweepArgs &a, int ngroups, hipStream_t st) {
+    hipLaunchKernelGGL((k_sweep<CAP, WMODE, F64>), dim3(ngroups), dim3(kWG), 0, st, a);
+    LAUNCHCHK("k_sweep");
+    return LC_OK;
+}
+
+template <int WMODE, bool F64>
+static int launch_sweep_c(int cap, const SweepArgs &a, int ngroups, hipStream_t st) {
+    if (cap <= 1024) return launch_sweep_t<1024, WMODE, F64>(a, ngroups, st);
+    if (cap <= 2048) return launch_sweep_t<2048, WMODE, F64>(a, ngroups, st);
+    return launch_sweep_t<3072, WMODE, F64>(a, ngroups, st);
+}
+
+static int launch_sweep(int cap, int wmode, bool f64, const SweepArgs &a, int ngroups,
+                        hipStream_t st) {
+    if (f64) {
+        if (wmode == 0) return launch_sweep_c<0, true>(cap, a, ngroups, st);
+        if (wmode == 1) return launch_sweep_c<1, true>(cap, a, ngroups, st);
+        return launch_sweep_c<2, true>(cap, a, ngroups, st);
+    }
+    if (wmode == 0) return launch_sweep_c<0, false>(cap, a, ngroups, st);
+    if (wmode == 1) return launch_sweep_c<1, false>(cap, a, ngroups, st);
+    return launch_sweep_c<2, false>(cap, a, ngroups, st);
+}
+
+static PairParams pair_params(const lc_grid *g) {
+    PairParams p;
+    for (int d = 0; d < 3; ++d) {
+        p.s[d] = g->scale[d];
+        p.sd[d] = g->box[d] / 4294967296.0;
+    }
+    p.rc2 = g->rc2;
+    p.ecut = g->ecut;
+    p.rc2d = g->rc * g->rc;
+    const double ic = 1.0 / p.rc2d;
+    const double s6 = ic * ic * ic;
+    p.ecutd = 4.0 * s6 * (s6 - 1.0);
+    return p;
+}
+
+static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *cell_start,
+                       const uint32_t *coord, int64_t n, int64_t *F, int64_t *ew, int precision,
+                       lc_workspace *ws, hipStream_t st, hipEvent_t *ev = nullptr) {
+    int rc = fill64((long long *)F, 3 * n, st);
+    if (rc) return rc;
+    rc = fill64((long long *)ew, 3, st);
+    if (rc) return rc;
+    SweepArgs a;
+    a.grp_task = s->grp_task;
+    a.grp_foot = s->grp_foot;
+    a.foot_cells = s->foot_cells;
+    a.task_ab = s->task_ab;
+    a.cell_start = cell_start;
+    a.coord = coord;
+    a.n = n;
+    a.F = (long long *)F;
+    a.ew = (long long *)ew;
+    a.flags = ws->flags;
+    a.pp = pair_params(g);
+    // LDS tile: expected particles of the largest footprint with headroom
+    const double mean = g->ncell > 0 ? (double)n / (double)g->ncell : 0.0;
+    const double need = mean * s->h.max_cells * 1.35 + 64.0;
+    const int cap = need <= 1024 ? 1024 : (need <= 2048 ? 2048 : 3072);
+    const int nphase = (int)s->h.phase_grp.size() - 1;
+    for (int p = 0; p < nphase; ++p) {
+        const int ng = s->h.phase_grp[p + 1] - s->h.phase_grp[p];
+        if (ng <= 0) continue;
+        a.grp_base = s->h.phase_grp[p];
+        if (ev) HIPCHK(hipEventRecord(ev[2 * p], st));
+        rc = launch_sweep(cap, s->h.write_mode, precision == LC_PREC_FP64, a, ng, st);
+        if (rc) return rc;
+        if (ev) HIPCHK(hipEventRecord(ev[2 * p + 1], st));
+    }
+    return LC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// a7: Verlet
+// ---------------------------------------------------------------------------
+
+__global__ void k_kick_drift(double *__restrict__ pos, double *__restrict__ vel,
+                             const long long *__restrict__ F, int64_t n, double hdt, double dt,
+                             const double *__restrict__ xref, double lim2, GridArgs ga,
+                             uint32_t *__restrict__ coord, uint32_t *__restrict__ flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double r2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const int64_t k = d * n + i;
+        const double acc = (double)F[k] * (1.0 / 4294967296.0);
+        double v = vel[k];
+        v = v + hdt * acc;
+        double x = pos[k];
+        x = x + dt * v;
+        vel[k] = v;
+        pos[k] = x;
+        coord[k] = canon(x, ga.inv[d]);
+        const double dd = x - xref[k];
+        r2 += dd * dd;
+    }
+    if (r2 > lim2) atomicOr(flags, (uint32_t)LC_FLAG_DISP);
+}
+
+__global__ __launch_bounds__(256) void k_kick_ke(double *__restrict__ vel,
+                                                 const long long *__restrict__ F, int64_t n,
+                                                 double hdt, int kick,
+                                                 unsigned long long *__restrict__ ke) {
+    __shared__ long long s_w[4];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    long long q = 0;
+    if (i < n) {
+        double v[3];
+        for (int d = 0; d < 3; ++d) {
+            const int64_t k = d * n + i;
+            double x = vel[k];
+            if (kick) {
+                const double acc = (double)F[k] * (1.0 / 4294967296.0);
+                x = x + hdt * acc;
+                vel[k] = x;
+            }
+            v[d] = x;
+        }
+        double s = v[0] * v[0] + v[1] * v[1];
+        s = s + v[2] * v[2];
+        q = (long long)rint((s * 0.5) * 4294967296.0);
+    }
+    q = wave_sum64(q);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) s_w[w] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        atomicAdd(ke, (unsigned long long)t);
+    }
+}
+
+__global__ void k_copy64(const long long *__restrict__ src, long long *__restrict__ dst, int cnt) {
+    if ((int)threadIdx.x < cnt) dst[threadIdx.x] = src[threadIdx.x];
+}
+
+__global__ void k_gather(const int *__restrict__ perm, int64_t n, const double *__restrict__ in,
+                         double *__restrict__ out, const int *__restrict__ in_ids,
+                         int *__restrict__ out_ids) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t s = perm[k];
+    out[k] = in[s];
+    out[n + k] = in[n + s];
+    out[2 * n + k] = in[2 * n + s];
+    if (in_ids) out_ids[k] = in_ids[s];
+}
+
+static int gather_impl(const int32_t *perm, int64_t n, const double *in3, double *out3,
+                       const int32_t *in_ids, int32_t *out_ids, hipStream_t st) {
+    if (n <= 0) return LC_OK;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm, n, in3,
+                       out3, in_ids, out_ids);
+    LAUNCHCHK("k_gather");
+    return LC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+
+extern "C" int lc_make_grid(const double box[3], double rc, double skin, int flags,
+                            lc_grid *out) {
+    if (!box || !out) return fail(LC_EINVAL, "lc_make_grid: null argument");
+    if (!(rc > 0.0) || !(skin >= 0.0)) return fail(LC_EINVAL, "lc_make_grid: rc/skin");
+    lc_grid g;
+    memset(&g, 0, sizeof g);
+    int64_t ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (!(box[d] > 0.0)) return fail(LC_EINVAL, "lc_make_grid: box length");
+        g.box[d] = box[d];
+        g.inv_box[d] = 1.0 / box[d];
+        const double side = rc * (1.0 + 1.0 / 4096.0) + skin;
+        const double q = box[d] / side;
+        if (!(q < 2147483647.0)) return fail(LC_EINVAL, "lc_make_grid: too many cells");
+        int64_t k = (int64_t)q;
+        if ((flags & LC_GRID_EVEN) && (k & 1)) k -= 1;
+        if (k < 3)
+            return fail(LC_EINVAL, "lc_make_grid: axis %d gets %lld cells (< 3)", d, (long long)k);
+        g.nc[d] = (int32_t)k;
+        ncell *= k;
+        g.scale[d] = (float)(box[d] / 4294967296.0);
+    }
+    if (ncell >= 2147483647LL) return fail(LC_EINVAL, "lc_make_grid: too many cells");
+    g.ncell = (int32_t)ncell;
+    g.rc = rc;
+    g.skin = skin;
+    g.rc2 = (float)(rc * rc);
+    {
+        float inv = 1.0f / g.rc2;
+        float s6 = inv * inv;
+        s6 = s6 * inv;
+        float e = 4.0f * s6;
+        g.ecut = e * (s6 - 1.0f);
+    }
+    *out = g;
+    return LC_OK;
+}
+
+template <typename T>
+static int dalloc(T **p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)count);
+    if (e != hipSuccess) return fail(LC_ENOMEM, "hipMalloc(%lld bytes): %s",
+                                     (long long)(sizeof(T) * count), hipGetErrorString(e));
+    return LC_OK;
+}
+
+extern "C" void lc_workspace_destroy(lc_workspace *ws) {
+    if (!ws) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(ws->device);
+    (void)hipFree(ws->cid);
+    (void)hipFree(ws->rank);
+    (void)hipFree(ws->counts);
+    (void)hipFree(ws->partial);
+    (void)hipFree(ws->flags);
+    (void)hipFree(ws->ew);
+    (void)hipFree(ws->ke);
+    (void)hipFree(ws->xref);
+    (void)hipFree(ws->tmp3);
+    (void)hipFree(ws->tmpi);
+    (void)hipSetDevice(cur);
+    delete ws;
+}
+
+extern "C" int lc_workspace_create(int64_t max_n, int64_t max_cells, lc_workspace **out) {
+    if (!out || max_n < 0 || max_cells < 1 || max_cells >= 2147483647LL || max_n >= 2147483647LL)
+        return fail(LC_EINVAL, "lc_workspace_create: bad sizes");
+    lc_workspace *ws = new lc_workspace();
+    HIPCHK(hipGetDevice(&ws->device));
+    ws->max_n = max_n;
+    ws->max_cells = max_cells;
+    int rc = 0;
+    const int64_t nb = (max_cells + kScanTile - 1) / kScanTile;
+    if ((rc = dalloc(&ws->cid, max_n)) || (rc = dalloc(&ws->rank, max_n)) ||
+        (rc = dalloc(&ws->counts, max_cells)) || (rc = dalloc(&ws->partial, nb + 1)) ||
+        (rc = dalloc(&ws->flags, 1)) || (rc = dalloc(&ws->ew, 3)) || (rc = dalloc(&ws->ke, 1)) ||
+        (rc = dalloc(&ws->xref, 3 * max_n)) || (rc = dalloc(&ws->tmp3, 3 * max_n)) ||
+        (rc = dalloc(&ws->tmpi, max_n))) {
+        lc_workspace_destroy(ws);
+        return rc;
+    }
+    if (hipMemset(ws->flags, 0, sizeof(uint32_t)) != hipSuccess) {
+        lc_workspace_destroy(ws);
+        return fail(LC_EHIP, "hipMemset flags");
+    }
+    *out = ws;
+    return LC_OK;
+}
+
+extern "C" int lc_workspace_clear_status(lc_workspace *ws, void *stream) {
+    if (!ws) return fail(LC_EINVAL, "null workspace");
+    return fill32((int *)ws->flags, 1, (hipStream_t)stream);
+}
+
+extern "C" int lc_workspace_status(lc_workspace *ws, void *stream, uint32_t *flags) {
+    if (!ws || !flags) return fail(LC_EINVAL, "null argument");
+    uint32_t v = 0;
+    HIPCHK(hipMemcpyAsync(&v, ws->flags, sizeof v, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    *flags = v;
+    return LC_OK;
+}
+
+static int check_ws(const lc_workspace *ws, int64_t n, int64_t ncell) {
+    if (!ws) return fail(LC_EINVAL, "null workspace");
+    if (n > ws->max_n || ncell > ws->max_cells)
+        return fail(LC_ECAPACITY, "workspace too small: n %lld > %lld or cells %lld > %lld",
+                    (long long)n, (long long)ws->max_n, (long long)ncell,
+                    (long long)ws->max_cells);
+    return LC_OK;
+}
+
+extern "C" int lc_build_cells(const lc_grid *g, const double *pos, int64_t n, int32_t *cell_start,
+                              int32_t *perm, uint32_t *coord, lc_workspace *ws, void *stream) {
+    if (!g || (n > 0 && (!pos || !perm || !coord)) || !cell_start)
+        return fail(LC_EINVAL, "lc_build_cells: null argument");
+    if (n < 0 || n >= 2147483647LL) return fail(LC_EINVAL, "lc_build_cells: bad n");
+    int rc = check_ws(ws, n, g->ncell);
+    if (rc) return rc;
+    return build_cells_impl(g, pos, n, cell_start, perm, coord, ws, (hipStream_t)stream);
+}
+
+extern "C" int lc_gather(const int32_t *perm, int64_t n, const double *in3, double *out3,
+                         const int32_t *in_ids, int32_t *out_ids, void *stream) {
+    if (n > 0 && (!perm || !in3 || !out3 || in3 == out3))
+        return fail(LC_EINVAL, "lc_gather: bad arguments");
+    if ((in_ids == nullptr) != (out_ids == nullptr)) return fail(LC_EINVAL, "lc_gather: ids");
+    return gather_impl(perm, n, in3, out3, in_ids, out_ids, (hipStream_t)stream);
+}
+
+extern "C" int lc_make_schedule(const lc_grid *g, int kind, const int8_t *offsets, int n,
+                                lc_schedule **out) {
+    if (!g || !out) return fail(LC_EINVAL, "lc_make_schedule: null argument");
+    if (kind < 0 || kind >= LC_SCHED_COUNT) return fail(LC_EINVAL, "unknown schedule kind %d", kind);
+    lc_schedule *s = new lc_schedule();
+    for (int d = 0; d < 3; ++d) s->nc[d] = g->nc[d];
+    std::string err;
+    int rc = lcs::build_schedule(g->nc, kind, offsets, n, s->h, err);
+    if (rc) {
+        delete s;
+        return fail(rc, "lc_make_schedule: %s", err.c_str());
+    }
+    if (!lcs::validate(s->h, g->ncell, err)) {
+        delete s;
+        return fail(LC_ESCHED, "lc_make_schedule: %s", err.c_str());
+    }
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(LC_EHIP, "hipGetDevice");
+    }
+    auto up = [&](auto **dst, const auto &vec) -> int {
+        int r = dalloc(dst, (int64_t)vec.size());
+        if (r) return r;
+        if (!vec.empty() && hipMemcpy(*dst, vec.data(), sizeof(vec[0]) * vec.size(),
+                                      hipMemcpyHostToDevice) != hipSuccess)
+            return fail(LC_EHIP, "schedule upload");
+        return LC_OK;
+    };
+    if ((rc = up(&s->grp_task, s->h.grp_task)) || (rc = up(&s->grp_foot, s->h.grp_foot)) ||
+        (rc = up(&s->foot_cells, s->h.foot_cells)) || (rc = up(&s->task_ab, s->h.task_ab))) {
+        lc_schedule_free(s);
+        return rc;
+    }
+    *out = s;
+    return LC_OK;
+}
+
+extern "C" void lc_schedule_free(lc_schedule *s) {
+    if (!s) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(s->device);
+    (void)hipFree(s->grp_task);
+    (void)hipFree(s->grp_foot);
+    (void)hipFree(s->foot_cells);
+    (void)hipFree(s->task_ab);
+    (void)hipSetDevice(cur);
+    delete s;
+}
+
+extern "C" int lc_schedule_info_get(const lc_schedule *s, lc_schedule_info *out) {
+    if (!s || !out) return fail(LC_EINVAL, "null argument");
+    memset(out, 0, sizeof *out);
+    out->kind = s->h.kind;
+    out->nphase = (int32_t)s->h.phase_grp.size() - 1;
+    out->ntask = s->h.ntask;
+    out->ngroup = (int64_t)s->h.grp_task.size() - 1;
+    out->max_group_tasks = s->h.max_tasks;
+    out->max_group_cells = s->h.max_cells;
+    out->write_mode = s->h.write_mode;
+    return LC_OK;
+}
+
+extern "C" int lc_schedule_plan(const lc_grid *g, int kind, const int8_t *offsets, int n,
+                                lc_schedule_info *out) {
+    if (!g || !out) return fail(LC_EINVAL, "lc_schedule_plan: null argument");
+    if (kind < 0 || kind >= LC_SCHED_COUNT) return fail(LC_EINVAL, "unknown schedule kind %d", kind);
+    lcs::HostSchedule h;
+    std::string err;
+    int rc = lcs::build_schedule(g->nc, kind, offsets, n, h, err);
+    if (rc) return fail(rc, "lc_schedule_plan: %s", err.c_str());
+    if (!lcs::validate(h, g->ncell, err)) return fail(LC_ESCHED, "lc_schedule_plan: %s", err.c_str());
+    memset(out, 0, sizeof *out);
+    out->kind = h.kind;
+    out->nphase = (int32_t)h.phase_grp.size() - 1;
+    out->ntask = h.ntask;
+    out->ngroup = (int64_t)h.grp_task.size() - 1;
+    out->max_group_tasks = h.max_tasks;
+    out->max_group_cells = h.max_cells;
+    out->write_mode = h.write_mode;
+    return LC_OK;
+}
+
+extern "C" int lc_validate_phases(int64_t ncell, int32_t nphase, const int32_t *phase_grp,
+                                  const int32_t *grp_foot, const int32_t *foot_cells) {
+    if (ncell < 1 || nphase < 0 || !phase_grp || !grp_foot || (nphase > 0 && !foot_cells))
+        return fail(LC_EINVAL, "lc_validate_phases: bad arguments");
+    lcs::HostSchedule h;
+    h.write_mode = 0;
+    h.phase_grp.assign(phase_grp, phase_grp + nphase + 1);
+    const int32_t ng = phase_grp[nphase];
+    if (phase_grp[0] != 0 || ng < 0) return fail(LC_EINVAL, "lc_validate_phases: phase_grp");
+    for (int p = 0; p < nphase; ++p)
+        if (phase_grp[p + 1] < phase_grp[p]) return fail(LC_EINVAL, "lc_validate_phases: order");
+    h.grp_foot.assign(grp_foot, grp_foot + ng + 1);
+    for (int k = 0; k < ng; ++k)
+        if (grp_foot[k + 1] < grp_foot[k]) return fail(LC_EINVAL, "lc_validate_phases: grp_foot");
+    h.foot_cells.assign(foot_cells, foot_cells + grp_foot[ng]);
+    std::string err;
+    if (!lcs::validate(h, ncell, err)) return fail(LC_ESCHED, "%s", err.c_str());
+    return LC_OK;
+}
+
+extern "C" int lc_serialization_degree(const int32_t dims[3], int kind, const int8_t *offsets,
+                                       int n, int64_t *level_hist, int64_t hist_len,
+                                       lc_sd_result *out) {
+    if (!dims || !out) return fail(LC_EINVAL, "null argument");
+    for (int d = 0; d < 3; ++d)
+        if (dims[d] < 1) return fail(LC_EINVAL, "dims must be >= 1");
+    const bool two_d = dims[2] == 1;
+    std::vector<lcs::Offset> order;
+    std::string err;
+    if (kind != LC_SCHED_LEX && kind != LC_SCHED_OPT && kind != LC_SCHED_BEST &&
+        kind != LC_SCHED_BAD && kind != LC_SCHED_LOOPEX && kind != LC_SCHED_CUSTOM)
+        return fail(LC_EINVAL, "kind %d has no creation order", kind);
+    if (!lcs::stencil_order(kind, two_d, offsets, n, order, err))
+        return fail(LC_EINVAL, "serialization_degree: %s", err.c_str());
+    std::vector<int32_t> A, B, level;
+    if (kind == LC_SCHED_LOOPEX) {
+        if (!lcs::loopex_tasks(dims, order, A, B))
+            return fail(LC_EINVAL, "loop exchange needs even dims");
+    } else {
+        lcs::basic_tasks(dims, order, A, B);
+    }
+    const int64_t ncell = (int64_t)dims[0] * dims[1] * dims[2];
+    const int64_t cp = lcs::task_levels(ncell, A, B, level);
+    memset(out, 0, sizeof *out);
+    out->tasks = (int64_t)A.size();
+    out->cp = cp;
+    out->speedup = cp ? (double)out->tasks / (double)cp : 0.0;
+    out->degree = out->tasks ? (double)cp / (double)out->tasks : 0.0;
+    out->n = (int32_t)order.size();
+    if (kind != LC_SCHED_LOOPEX) {
+        const int delta = lcs::delta_rule(order);
+        out->delta = delta;
+        const double k = (double)ncell, nn = (double)order.size();
+        out->s_eq2 = nn * k / (nn + delta * (k - 1.0));
+        out->s_max = nn / delta;
+    }
+    if (level_hist) {
+        for (int64_t l = 0; l < hist_len; ++l) level_hist[l] = 0;
+        for (int32_t l : level)
+            if (l - 1 < hist_len) level_hist[l - 1]++;
+    }
+    return LC_OK;
+}
+
+extern "C" int lc_compute_forces(const lc_grid *g, const lc_schedule *s, const int32_t *cell_start,
+                                 const uint32_t *coord, int64_t n, int64_t *F, int64_t *ew,
+                                 int precision, lc_workspace *ws, void *stream) {
+    if (!g || !s || !cell_start || !F || !ew || (n > 0 && !coord))
+        return fail(LC_EINVAL, "lc_compute_forces: null argument");
+    if (precision != LC_PREC_FP32 && precision != LC_PREC_FP64)
+        return fail(LC_EINVAL, "lc_compute_forces: precision");
+    if (s->nc[0] != g->nc[0] || s->nc[1] != g->nc[1] || s->nc[2] != g->nc[2])
+        return fail(LC_EINVAL, "lc_compute_forces: schedule built for another grid");
+    if (n < 0 || n >= 2147483647LL) return fail(LC_EINVAL, "lc_compute_forces: bad n");
+    int rc = check_ws(ws, 0, 0);
+    if (rc) return rc;
+    return forces_impl(g, s, cell_start, coord, n, F, ew, precision, ws, (hipStream_t)stream);
+}
+
+extern "C" int lc_compute_forces_profiled(const lc_grid *g, const lc_schedule *s,
+                                          const int32_t *cell_start, const uint32_t *coord,
+                                          int64_t n, int64_t *F, int64_t *ew, int precision,
+                                          lc_workspace *ws, void *stream, double *sweep_ms,
+                                          double *phase_ms) {
+    if (!sweep_ms) return fail(LC_EINVAL, "lc_compute_forces_profiled: sweep_ms");
+    if (!g || !s || !cell_start || !F || !ew || (n > 0 && !coord))
+        return fail(LC_EINVAL, "lc_compute_forces_profiled: null argument");
+    if (precision != LC_PREC_FP32 && precision != LC_PREC_FP64)
+        return fail(LC_EINVAL, "lc_compute_forces_profiled: precision");
+    if (s->nc[0] != g->nc[0] || s->nc[1] != g->nc[1] || s->nc[2] != g->nc[2])
+        return fail(LC_EINVAL, "lc_compute_forces_profiled: schedule built for another grid");
+    int rc = check_ws(ws, 0, 0);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int nphase = (int)s->h.phase_grp.size() - 1;
+    std::vector<hipEvent_t> ev((size_t)2 * nphase, nullptr);
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &x : ev)
+                if (x) (void)hipEventDestroy(x);
+            return fail(LC_EHIP, "hipEventCreate");
+        }
+    rc = forces_impl(g, s, cell_start, coord, n, F, ew, precision, ws, st, ev.data());
+    double total = 0.0;
+    if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(LC_EHIP, "hipStreamSynchronize");
+    for (int p = 0; p < nphase && !rc; ++p) {
+        float ms = 0.0f;
+        if (s->h.phase_grp[p + 1] > s->h.phase_grp[p]) {
+            if (hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]) != hipSuccess) {
+                rc = fail(LC_EHIP, "hipEventElapsedTime");
+                break;
+            }
+        }
+        total += ms;
+        if (phase_ms) phase_ms[p] = ms;
+    }
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    if (!rc) *sweep_ms = total;
+    return rc;
+}
+
+extern "C" int lc_kinetic_energy(const double *vel, int64_t n, int64_t *ke, void *stream) {
+    if (!ke || (n > 0 && !vel)) return fail(LC_EINVAL, "lc_kinetic_energy: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = fill64((long long *)ke, 1, st);
+    if (rc) return rc;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_kick_ke, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                           (double *)vel, (const long long *)nullptr, n, 0.0, 0,
+                           (unsigned long long *)ke);
+        LAUNCHCHK("k_kick_ke");
+    }
+    return LC_OK;
+}
+
+static int rebuild(const lc_grid *g, double *pos, double *vel, int32_t *ids, int64_t n,
+                   int32_t *cell_start, int32_t *perm, uint32_t *coord, lc_workspace *ws,
+                   hipStream_t st) {
+    int rc = build_cells_impl(g, pos, n, cell_start, perm, coord, ws, st);
+    if (rc) return rc;
+    const size_t b3 = sizeof(double) * 3 * (size_t)n;
+    if ((rc = gather_impl(perm, n, pos, ws->tmp3, ids, ws->tmpi, st))) return rc;
+    HIPCHK(hipMemcpyAsync(pos, ws->tmp3, b3, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws->xref, ws->tmp3, b3, hipMemcpyDeviceToDevice, st));
+    if (ids) HIPCHK(hipMemcpyAsync(ids, ws->tmpi, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+    if ((rc = gather_impl(perm, n, vel, ws->tmp3, nullptr, nullptr, st))) return rc;
+    HIPCHK(hipMemcpyAsync(vel, ws->tmp3, b3, hipMemcpyDeviceToDevice, st));
+    return LC_OK;
+}
+
+extern "C" int lc_verlet_step(const lc_grid *g, const lc_schedule *s, double *pos, double *vel,
+                              int32_t *ids, int64_t n, int64_t *F, int32_t *cell_start,
+                              int32_t *perm, uint32_t *coord, double dt, int nsteps,
+                              int rebuild_every, int64_t *trace, lc_workspace *ws, void *stream) {
+    if (!g || !s || !trace || !F || !cell_start || (n > 0 && (!pos || !vel || !perm || !coord)))
+        return fail(LC_EINVAL, "lc_verlet_step: null argument");
+    if (nsteps < 0 || rebuild_every < 1) return fail(LC_EINVAL, "lc_verlet_step: steps");
+    int rc = check_ws(ws, n, g->ncell);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    GridArgs ga;
+    for (int d = 0; d < 3; ++d) {
+        ga.inv[d] = g->inv_box[d];
+        ga.nc[d] = g->nc[d];
+    }
+    const double hdt = 0.5 * dt;
+    const double lim = 0.5 * g->skin;
+    const double lim2 = lim * lim;
+    const unsigned nbk = (unsigned)((n + 255) / 256);
+    // step 0: sort into cells at the current positions, forces, energies
+    if ((rc = rebuild(g, pos, vel, ids, n, cell_start, perm, coord, ws, st))) return rc;
+    if ((rc = forces_impl(g, s, cell_start, coord, n, F, ws->ew, LC_PREC_FP32, ws, st))) return rc;
+    for (int step = 0; step <= nsteps; ++step) {
+        if (step > 0) {
+            if (n > 0) {
+                hipLaunchKernelGGL(k_kick_drift, dim3(nbk), dim3(256), 0, st, pos, vel,
+                                   (const long long *)F, n, hdt, dt, ws->xref, lim2, ga, coord,
+                                   ws->flags);
+                LAUNCHCHK("k_kick_drift");
+            }
+            if (step % rebuild_every == 0)
+                if ((rc = rebuild(g, pos, vel, ids, n, cell_start, perm, coord, ws, st))) return rc;
+            if ((rc = forces_impl(g, s, cell_start, coord, n, F, ws->ew, LC_PREC_FP32, ws, st)))
+                return rc;
+        }
+        long long *row = (long long *)trace + 2 * step;
+        if ((rc = fill64(row, 1, st))) return rc;
+        if (n > 0) {
+            hipLaunchKernelGGL(k_kick_ke, dim3(nbk), dim3(256), 0, st, vel, (const long long *)F, n,
+                               hdt, step > 0 ? 1 : 0, (unsigned long long *)row);
+            LAUNCHCHK("k_kick_ke");
+        }
+        hipLaunchKernelGGL(k_copy64, dim3(1), dim3(64), 0, st, (const long long *)ws->ew, row + 1, 1);
+        LAUNCHCHK("k_copy64");
+    }
+    return LC_OK;
+}

@@ -1,0 +1,397 @@
+// Host-side cell-task scheduler (see sched.h).
+#include "lc_sched.h"
+
+#include <algorithm>
+#include <cstring>
+#include <unordered_map>
+
+#include "lc.h"
+
+namespace lcs {
+
+namespace {
+
+Offset mk(int x, int y, int z) {
+    Offset o;
+    o.d[0] = (int8_t)x;
+    o.d[1] = (int8_t)y;
+    o.d[2] = (int8_t)z;
+    return o;
+}
+
+bool same(const Offset &a, const Offset &b) {
+    return a.d[0] == b.d[0] && a.d[1] == b.d[1] && a.d[2] == b.d[2];
+}
+
+bool is_zero(const Offset &a) { return !a.d[0] && !a.d[1] && !a.d[2]; }
+
+int64_t wrap(int64_t a, int64_t m) {
+    a %= m;
+    return a < 0 ? a + m : a;
+}
+
+// (dz, dy, dx) ascending: the linear-index order of the offsets.
+bool lin_less(const Offset &a, const Offset &b) {
+    if (a.d[2] != b.d[2]) return a.d[2] < b.d[2];
+    if (a.d[1] != b.d[1]) return a.d[1] < b.d[1];
+    return a.d[0] < b.d[0];
+}
+
+}  // namespace
+
+std::vector<Offset> half_stencil(bool two_d) {
+    std::vector<Offset> h;
+    if (two_d) {
+        h = {mk(0, -1, 0), mk(1, -1, 0), mk(1, 0, 0), mk(1, 1, 0)};
+        return h;
+    }
+    for (int b = -1; b <= 1; ++b)
+        for (int a = -1; a <= 1; ++a) h.push_back(mk(1, a, b));
+    for (int a = -1; a <= 1; ++a) h.push_back(mk(0, a, 1));
+    h.push_back(mk(0, -1, 0));
+    return h;
+}
+
+bool stencil_order(int kind, bool two_d, const int8_t *offsets, int n,
+                   std::vector<Offset> &order, std::string &err) {
+    order.clear();
+    const Offset intra = mk(0, 0, 0), ex = mk(1, 0, 0);
+    if (kind == LC_SCHED_CUSTOM) {
+        if (!offsets || n <= 0) {
+            err = "custom order needs offsets";
+            return false;
+        }
+        for (int k = 0; k < n; ++k)
+            order.push_back(mk(offsets[3 * k], offsets[3 * k + 1], offsets[3 * k + 2]));
+        // validate: intra once, and one of d / -d for every neighbour
+        int nz = 0, want = two_d ? 9 : 27;
+        std::vector<int> seen(27, 0);
+        for (auto &o : order) {
+            for (int d = 0; d < 3; ++d)
+                if (o.d[d] < -1 || o.d[d] > 1) {
+                    err = "offset component outside [-1, 1]";
+                    return false;
+                }
+            if (two_d && o.d[2]) {
+                err = "2D order with nonzero dz";
+                return false;
+            }
+            int k1 = (o.d[0] + 1) + 3 * (o.d[1] + 1) + 9 * (o.d[2] + 1);
+            int k2 = (-o.d[0] + 1) + 3 * (-o.d[1] + 1) + 9 * (-o.d[2] + 1);
+            if (seen[k1] || (k1 != k2 && seen[k2])) {
+                err = "offset or its mirror repeated";
+                return false;
+            }
+            seen[k1] = 1;
+            nz += is_zero(o) ? 1 : 2;
+        }
+        if (nz != want) {
+            err = "order is not a complete half shell plus intra";
+            return false;
+        }
+        return true;
+    }
+    std::vector<Offset> h = half_stencil(two_d);
+    std::sort(h.begin(), h.end(), lin_less);
+    if (two_d) {
+        const Offset bl = mk(0, -1, 0), lr = mk(1, -1, 0), ur = mk(1, 1, 0);
+        switch (kind) {
+            case LC_SCHED_LEX:  // Fig. 5(a)
+            case LC_SCHED_LOOPEX: order = {intra, bl, lr, ex, ur}; return true;
+            case LC_SCHED_BAD: order = {intra, bl, lr, ur, ex}; return true;   // 5(b)
+            case LC_SCHED_OPT: order = {ex, lr, ur, bl, intra}; return true;   // 5(c)
+            case LC_SCHED_BEST: order = {intra, ex, lr, ur, bl}; return true;
+            default: err = "kind has no 2D order"; return false;
+        }
+    }
+    std::vector<Offset> dx1, dx0;
+    for (auto &o : h) {
+        if (same(o, ex)) continue;
+        (o.d[0] == 1 ? dx1 : dx0).push_back(o);
+    }
+    switch (kind) {
+        case LC_SCHED_LEX:
+        case LC_SCHED_LOOPEX:
+        case LC_SCHED_BLOCK8:
+        case LC_SCHED_ATOMIC_TILE:
+        case LC_SCHED_ATOMIC_PAIR:
+            order.push_back(intra);
+            for (auto &o : h) order.push_back(o);
+            return true;
+        case LC_SCHED_OPT:
+            order.push_back(ex);
+            for (auto &o : dx1) order.push_back(o);
+            for (auto &o : dx0) order.push_back(o);
+            order.push_back(intra);
+            return true;
+        case LC_SCHED_BEST:
+            order.push_back(intra);
+            order.push_back(ex);
+            for (auto &o : dx1) order.push_back(o);
+            for (auto &o : dx0) order.push_back(o);
+            return true;
+        case LC_SCHED_BAD:
+            order.push_back(intra);
+            for (auto &o : h)
+                if (!same(o, ex)) order.push_back(o);
+            order.push_back(ex);
+            return true;
+        default: err = "unknown schedule kind"; return false;
+    }
+}
+
+void basic_tasks(const int32_t dims[3], const std::vector<Offset> &order,
+                 std::vector<int32_t> &A, std::vector<int32_t> &B) {
+    const int64_t nx = dims[0], ny = dims[1], nz = dims[2];
+    A.clear();
+    B.clear();
+    A.reserve((size_t)(nx * ny * nz) * order.size());
+    B.reserve(A.capacity());
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                const int32_t a = (int32_t)(x + nx * (y + ny * z));
+                for (const Offset &o : order) {
+                    A.push_back(a);
+                    B.push_back((int32_t)(wrap(x + o.d[0], nx) +
+                                          nx * (wrap(y + o.d[1], ny) +
+                                                ny * wrap(z + o.d[2], nz))));
+                }
+            }
+}
+
+bool loopex_tasks(const int32_t dims[3], const std::vector<Offset> &order,
+                  std::vector<int32_t> &A, std::vector<int32_t> &B) {
+    const int64_t nx = dims[0], ny = dims[1], nz = dims[2];
+    const bool flat = nz == 1;
+    if ((nx & 1) || (ny & 1) || (!flat && (nz & 1))) return false;
+    A.clear();
+    B.clear();
+    const int zc = flat ? 1 : 2, zs = flat ? 1 : 2;
+    for (const Offset &o : order)
+        for (int c = 0; c < 4 * zc; ++c) {
+            const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+            for (int64_t z = cz; z < nz; z += zs)
+                for (int64_t y = cy; y < ny; y += 2)
+                    for (int64_t x = cx; x < nx; x += 2) {
+                        A.push_back((int32_t)(x + nx * (y + ny * z)));
+                        B.push_back((int32_t)(wrap(x + o.d[0], nx) +
+                                              nx * (wrap(y + o.d[1], ny) +
+                                                    ny * wrap(z + o.d[2], nz))));
+                    }
+        }
+    return true;
+}
+
+int64_t task_levels(int64_t ncell, const std::vector<int32_t> &A,
+                    const std::vector<int32_t> &B,
+                    std::vector<int32_t> &level) {
+    std::vector<int32_t> last((size_t)ncell, 0);
+    level.resize(A.size());
+    int64_t cp = 0;
+    for (size_t t = 0; t < A.size(); ++t) {
+        const int32_t l = 1 + std::max(last[A[t]], last[B[t]]);
+        level[t] = l;
+        last[A[t]] = l;
+        last[B[t]] = l;
+        cp = std::max<int64_t>(cp, l);
+    }
+    return cp;
+}
+
+int delta_rule(const std::vector<Offset> &order) {
+    auto pos = [&](const Offset &o) -> int {
+        for (size_t k = 0; k < order.size(); ++k)
+            if (same(order[k], o)) return (int)k + 1;
+        return 0;
+    };
+    int delta = pos(mk(1, 0, 0));
+    for (const Offset &d : order) {
+        Offset back = mk(d.d[0] - 1, d.d[1], d.d[2]);
+        int pb = pos(back);
+        if (pb) delta = std::max(delta, pos(d) - pb + 1);
+    }
+    return delta;
+}
+
+namespace {
+
+// Assemble one work-group from a task list: footprint = distinct cells in
+// order of first appearance.
+bool add_group(HostSchedule &hs, const std::vector<int32_t> &A,
+               const std::vector<int32_t> &B, std::string &err) {
+    std::vector<int32_t> cells;
+    auto local = [&](int32_t c) -> int {
+        for (size_t k = 0; k < cells.size(); ++k)
+            if (cells[k] == c) return (int)k;
+        cells.push_back(c);
+        return (int)cells.size() - 1;
+    };
+    for (size_t t = 0; t < A.size(); ++t) {
+        const int a = local(A[t]), b = local(B[t]);
+        hs.task_ab.push_back((uint32_t)a | ((uint32_t)b << 16));
+    }
+    if ((int)A.size() > kMaxGroupTasks || (int)cells.size() > kMaxGroupCells) {
+        err = "work-group exceeds task/cell limits";
+        return false;
+    }
+    hs.foot_cells.insert(hs.foot_cells.end(), cells.begin(), cells.end());
+    hs.grp_task.push_back((int32_t)hs.task_ab.size());
+    hs.grp_foot.push_back((int32_t)hs.foot_cells.size());
+    hs.max_tasks = std::max(hs.max_tasks, (int)A.size());
+    hs.max_cells = std::max(hs.max_cells, (int)cells.size());
+    hs.ntask += (int64_t)A.size();
+    return true;
+}
+
+// Partition n cells along an axis into an even number of blocks, each at
+// least `minsize` cells, sizes differing by at most one; a single block when
+// two blocks of minsize do not fit.  With an even count the blocks 2-colour
+// under the periodic wrap; same-coloured blocks are then separated by a
+// whole block, which keeps their write footprints apart when that block is
+// at least as wide as the stencil reaches on that side (minsize: 1 along x,
+// where the half stencil is one-sided, 2 along y and z).  Returns block start
+// offsets with n appended.
+std::vector<int> axis_blocks(int n, int minsize) {
+    if (n < 2 * minsize) return {0, n};
+    int m = n / minsize;
+    if (m & 1) m -= 1;
+    const int base = n / m, extra = n % m;
+    std::vector<int> s(1, 0);
+    int pos = 0;
+    for (int b = 0; b < m; ++b) {
+        pos += base + (b < extra ? 1 : 0);
+        s.push_back(pos);
+    }
+    return s;
+}
+
+}  // namespace
+
+int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
+                   int n, HostSchedule &hs, std::string &err) {
+    hs = HostSchedule();
+    hs.kind = kind;
+    hs.grp_task.push_back(0);
+    hs.grp_foot.push_back(0);
+    hs.phase_grp.push_back(0);
+    const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    std::vector<Offset> order;
+    if (!stencil_order(kind, false, offsets, n, order, err)) return LC_EINVAL;
+
+    if (kind == LC_SCHED_BLOCK8 || kind == LC_SCHED_ATOMIC_TILE) {
+        hs.write_mode = kind == LC_SCHED_BLOCK8 ? 0 : 1;
+        std::vector<int> bs[3];
+        for (int d = 0; d < 3; ++d) bs[d] = axis_blocks(nc[d], d == 0 ? 1 : 2);
+        const int nb[3] = {(int)bs[0].size() - 1, (int)bs[1].size() - 1,
+                           (int)bs[2].size() - 1};
+        const int ncol[3] = {nb[0] > 1 ? 2 : 1, nb[1] > 1 ? 2 : 1, nb[2] > 1 ? 2 : 1};
+        const int nphase_col = ncol[0] * ncol[1] * ncol[2];
+        for (int ph = 0; ph < nphase_col; ++ph) {
+            const int col[3] = {ph % ncol[0], (ph / ncol[0]) % ncol[1],
+                                ph / (ncol[0] * ncol[1])};
+            for (int bz = 0; bz < nb[2]; ++bz)
+                for (int by = 0; by < nb[1]; ++by)
+                    for (int bx = 0; bx < nb[0]; ++bx) {
+                        if ((bx % ncol[0]) != col[0] || (by % ncol[1]) != col[1] ||
+                            (bz % ncol[2]) != col[2])
+                            continue;
+                        std::vector<int32_t> A, B;
+                        for (int z = bs[2][bz]; z < bs[2][bz + 1]; ++z)
+                            for (int y = bs[1][by]; y < bs[1][by + 1]; ++y)
+                                for (int x = bs[0][bx]; x < bs[0][bx + 1]; ++x) {
+                                    const int32_t a = x + nc[0] * (y + nc[1] * z);
+                                    for (const Offset &o : order) {
+                                        A.push_back(a);
+                                        B.push_back((int32_t)(
+                                            wrap(x + o.d[0], nc[0]) +
+                                            nc[0] * (wrap(y + o.d[1], nc[1]) +
+                                                     nc[1] * wrap(z + o.d[2], nc[2]))));
+                                    }
+                                }
+                        if (!add_group(hs, A, B, err)) return LC_ECAPACITY;
+                    }
+            if (kind == LC_SCHED_BLOCK8)
+                hs.phase_grp.push_back((int32_t)(hs.grp_task.size() - 1));
+        }
+        if (kind == LC_SCHED_ATOMIC_TILE)
+            hs.phase_grp.push_back((int32_t)(hs.grp_task.size() - 1));
+        return LC_OK;
+    }
+
+    if (kind == LC_SCHED_ATOMIC_PAIR) {
+        hs.write_mode = 2;
+        std::vector<int32_t> A, B;
+        basic_tasks(nc, order, A, B);
+        const size_t per = order.size();
+        for (size_t c = 0; c < (size_t)ncell; ++c) {
+            std::vector<int32_t> a(A.begin() + c * per, A.begin() + (c + 1) * per);
+            std::vector<int32_t> b(B.begin() + c * per, B.begin() + (c + 1) * per);
+            if (!add_group(hs, a, b, err)) return LC_ECAPACITY;
+        }
+        hs.phase_grp.push_back((int32_t)(hs.grp_task.size() - 1));
+        return LC_OK;
+    }
+
+    // Creation-order kinds: execute the DAG level by level.
+    std::vector<int32_t> A, B;
+    if (kind == LC_SCHED_LOOPEX) {
+        if (!loopex_tasks(nc, order, A, B)) {
+            err = "loop-exchange colouring needs even cell counts";
+            return LC_EINVAL;
+        }
+    } else {
+        basic_tasks(nc, order, A, B);
+    }
+    std::vector<int32_t> level;
+    const int64_t cp = task_levels(ncell, A, B, level);
+    // bucket tasks by level, keeping creation order inside a level
+    std::vector<int64_t> cnt((size_t)cp + 2, 0);
+    for (int32_t l : level) cnt[(size_t)l + 1]++;
+    for (size_t l = 1; l < cnt.size(); ++l) cnt[l] += cnt[l - 1];
+    std::vector<int32_t> byl(A.size());
+    {
+        std::vector<int64_t> fill(cnt.begin(), cnt.end());
+        for (size_t t = 0; t < A.size(); ++t) byl[(size_t)fill[(size_t)level[t]]++] = (int32_t)t;
+    }
+    hs.write_mode = 0;
+    for (int64_t l = 1; l <= cp; ++l) {
+        for (int64_t k = cnt[(size_t)l]; k < cnt[(size_t)l + 1]; k += kLevelGroupTasks) {
+            const int64_t e = std::min<int64_t>(k + kLevelGroupTasks, cnt[(size_t)l + 1]);
+            std::vector<int32_t> a, b;
+            for (int64_t q = k; q < e; ++q) {
+                a.push_back(A[(size_t)byl[(size_t)q]]);
+                b.push_back(B[(size_t)byl[(size_t)q]]);
+            }
+            if (!add_group(hs, a, b, err)) return LC_ECAPACITY;
+        }
+        hs.phase_grp.push_back((int32_t)(hs.grp_task.size() - 1));
+    }
+    return LC_OK;
+}
+
+bool validate(const HostSchedule &hs, int64_t ncell, std::string &err) {
+    if (hs.write_mode != 0) return true;  // atomic write-back needs no colouring
+    std::vector<int32_t> owner((size_t)ncell, -1);
+    std::vector<int32_t> stamp((size_t)ncell, -1);
+    const int nphase = (int)hs.phase_grp.size() - 1;
+    for (int p = 0; p < nphase; ++p)
+        for (int g = hs.phase_grp[p]; g < hs.phase_grp[p + 1]; ++g)
+            for (int f = hs.grp_foot[g]; f < hs.grp_foot[g + 1]; ++f) {
+                const int32_t c = hs.foot_cells[f];
+                if (c < 0 || c >= ncell) {
+                    err = "footprint cell out of range";
+                    return false;
+                }
+                if (stamp[c] == p && owner[c] != g) {
+                    err = "phase " + std::to_string(p) + ": cell " + std::to_string(c) +
+                          " written by two work-groups";
+                    return false;
+                }
+                stamp[c] = p;
+                owner[c] = g;
+            }
+    return true;
+}
+
+}  // namespace lcs

@@ -1,0 +1,79 @@
+// Host-side cell-task scheduler: creation orders, task DAG levels, phase and
+// work-group construction, validation, and the serialisation-degree model.
+// Pure C++ (no HIP); the device upload lives in lc.hip.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace lcs {
+
+struct Offset {
+    int8_t d[3];
+};
+
+// Fig. 3 half stencils.  3D: the whole +x layer (9), the three +z cells of
+// the centre layer, the cell below the centre (axes read from the drawing as
+// depth = z, right = x, up = y).  2D: below, and the three cells of the +x
+// column.
+std::vector<Offset> half_stencil(bool two_d);
+
+// Stencil evaluation order (intra = (0,0,0) included) of a preset kind
+// (LC_SCHED_LEX/OPT/BEST/BAD/LOOPEX), or the caller's order for CUSTOM.
+// Returns false with `err` set when the order is not a valid half shell.
+bool stencil_order(int kind, bool two_d, const int8_t *offsets, int n,
+                   std::vector<Offset> &order, std::string &err);
+
+// Tasks (cellA, cellB) in creation order.
+//   basic:  for z, for y, for x: for each entry of `order`
+//   loopex: for each entry of `order`: for each colour in {0,1}^D (x
+//           fastest): for each cell of that colour (x fastest)
+void basic_tasks(const int32_t dims[3], const std::vector<Offset> &order,
+                 std::vector<int32_t> &A, std::vector<int32_t> &B);
+bool loopex_tasks(const int32_t dims[3], const std::vector<Offset> &order,
+                  std::vector<int32_t> &A, std::vector<int32_t> &B);
+
+// DAG level of every task under the inout rule, by the last-writer
+// recurrence: level[t] = 1 + max(last[A_t], last[B_t]), then both cells'
+// last = level[t].  Returns the critical path (max level).
+int64_t task_levels(int64_t ncell, const std::vector<int32_t> &A,
+                    const std::vector<int32_t> &B,
+                    std::vector<int32_t> &level);
+
+// Stencil displacement Delta of an evaluation order over a periodic row.
+// Stencils at x and x + e_x are both full chains through their centre cell;
+// stencil x+1 touches cell x+d (d in stencil, d - e_x in stencil) with its
+// task at position pos(d - e_x), after stencil x touched it at pos(d); and
+// its first task touches its own centre, which stencil x wrote at pos(e_x).
+// Hence Delta = max(pos(e_x), max_d [pos(d) - pos(d - e_x) + 1]).
+int delta_rule(const std::vector<Offset> &order);
+
+// Device-ready schedule in host memory.
+struct HostSchedule {
+    int kind = 0;
+    int write_mode = 0;               // 0 plain, 1 atomic tile, 2 atomic pair
+    std::vector<int32_t> phase_grp;   // nphase + 1
+    std::vector<int32_t> grp_task;    // ngroup + 1 (index into task_ab)
+    std::vector<int32_t> grp_foot;    // ngroup + 1 (index into foot_cells)
+    std::vector<int32_t> foot_cells;  // global cell id per footprint slot
+    std::vector<uint32_t> task_ab;    // local a | (local b << 16)
+    int64_t ntask = 0;
+    int max_tasks = 0;
+    int max_cells = 0;
+};
+
+constexpr int kMaxGroupTasks = 512;
+constexpr int kMaxGroupCells = 128;
+constexpr int kLevelGroupTasks = 16;
+
+// Build the schedule of `kind` on grid `nc` (LC_SCHED_*).  Returns 0 or a
+// negative LC_E* code with `err` set.
+int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
+                   int n, HostSchedule &hs, std::string &err);
+
+// Every phase's work-groups write pairwise disjoint cells (required for
+// plain read-modify-write).  Returns true when valid.
+bool validate(const HostSchedule &hs, int64_t ncell, std::string &err);
+
+}  // namespace lcs

@@ -1,0 +1,368 @@
+"""Python binding of ``liblc.so`` (include/lc.h): argument marshalling only.
+
+Every step of the force sweep runs in the HIP library; this module turns
+torch tensors (device memory) and the current torch stream into the raw
+pointers the C-ABI takes, and raises :class:`LCError` on a negative status.
+If the library has not been built the import fails loudly -- there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblc.so")
+
+# schedule kinds (LC_SCHED_*)
+LEX, OPT, BEST, BAD, LOOPEX, BLOCK8, ATOMIC_TILE, ATOMIC_PAIR, CUSTOM = range(9)
+KINDS = {"lex": LEX, "opt": OPT, "best": BEST, "bad": BAD, "loopex": LOOPEX,
+         "block8": BLOCK8, "atomic_tile": ATOMIC_TILE, "atomic_pair": ATOMIC_PAIR,
+         "custom": CUSTOM}
+PREC = {"fp32": 0, "fp64": 1}
+FLAG_OVERFLOW, FLAG_DISP, FLAG_FALLBACK = 1, 2, 4
+SCALE = 2.0 ** 32
+
+
+class LCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lc error {code}: {msg}")
+        self.code = code
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_double * 3), ("inv_box", ctypes.c_double * 3),
+                ("rc", ctypes.c_double), ("skin", ctypes.c_double),
+                ("nc", ctypes.c_int32 * 3), ("ncell", ctypes.c_int32),
+                ("scale", ctypes.c_float * 3), ("rc2", ctypes.c_float),
+                ("ecut", ctypes.c_float), ("pad", ctypes.c_int32)]
+
+
+class _SchedInfo(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nphase", ctypes.c_int32),
+                ("ntask", ctypes.c_int64), ("ngroup", ctypes.c_int64),
+                ("max_group_tasks", ctypes.c_int32),
+                ("max_group_cells", ctypes.c_int32),
+                ("write_mode", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class _SD(ctypes.Structure):
+    _fields_ = [("tasks", ctypes.c_int64), ("cp", ctypes.c_int64),
+                ("speedup", ctypes.c_double), ("degree", ctypes.c_double),
+                ("n", ctypes.c_int32), ("delta", ctypes.c_int32),
+                ("s_eq2", ctypes.c_double), ("s_max", ctypes.c_double)]
+
+
+_lib = None
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+INT = ctypes.c_int
+
+SYMBOLS = {
+    "lc_last_error": ([], ctypes.c_char_p),
+    "lc_make_grid": ([P, ctypes.c_double, ctypes.c_double, INT, P], INT),
+    "lc_workspace_create": ([I64, I64, P], INT),
+    "lc_workspace_destroy": ([P], None),
+    "lc_workspace_clear_status": ([P, P], INT),
+    "lc_workspace_status": ([P, P, P], INT),
+    "lc_build_cells": ([P, P, I64, P, P, P, P, P], INT),
+    "lc_gather": ([P, I64, P, P, P, P, P], INT),
+    "lc_make_schedule": ([P, INT, P, INT, P], INT),
+    "lc_schedule_info_get": ([P, P], INT),
+    "lc_schedule_free": ([P], None),
+    "lc_schedule_plan": ([P, INT, P, INT, P], INT),
+    "lc_validate_phases": ([I64, ctypes.c_int32, P, P, P], INT),
+    "lc_serialization_degree": ([P, INT, P, INT, P, I64, P], INT),
+    "lc_compute_forces": ([P, P, P, P, I64, P, P, INT, P, P], INT),
+    "lc_compute_forces_profiled": ([P, P, P, P, I64, P, P, INT, P, P, P, P], INT),
+    "lc_verlet_step": ([P, P, P, P, P, I64, P, P, P, P, ctypes.c_double, INT,
+                        INT, P, P, P], INT),
+    "lc_kinetic_energy": ([P, I64, P, P], INT),
+}
+
+
+def lib():
+    """Load the in-tree liblc.so; raise if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_1401_4441_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SYMBOLS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _chk(rc: int):
+    if rc < 0:
+        raise LCError(rc, lib().lc_last_error().decode())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _p(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+
+class Grid:
+    def __init__(self, box, rc: float, skin: float = 0.0, even: bool = False):
+        self._g = _Grid()
+        b = (ctypes.c_double * 3)(*[float(x) for x in box])
+        _chk(lib().lc_make_grid(ctypes.cast(b, P), float(rc), float(skin),
+                                1 if even else 0, ctypes.byref(self._g)))
+
+    @property
+    def ptr(self):
+        return ctypes.byref(self._g)
+
+    @property
+    def nc(self):
+        return tuple(self._g.nc)
+
+    @property
+    def ncell(self) -> int:
+        return int(self._g.ncell)
+
+    @property
+    def box(self):
+        return tuple(self._g.box)
+
+    @property
+    def rc(self) -> float:
+        return float(self._g.rc)
+
+    @property
+    def skin(self) -> float:
+        return float(self._g.skin)
+
+
+class Workspace:
+    def __init__(self, max_n: int, max_cells: int):
+        self._h = ctypes.c_void_p()
+        _chk(lib().lc_workspace_create(int(max_n), int(max_cells),
+                                       ctypes.byref(self._h)))
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def clear_status(self, stream=None):
+        _chk(lib().lc_workspace_clear_status(self._h, _stream(stream)))
+
+    def status(self, stream=None) -> int:
+        v = ctypes.c_uint32(0)
+        _chk(lib().lc_workspace_status(self._h, _stream(stream), ctypes.byref(v)))
+        return int(v.value)
+
+    def close(self):
+        if self._h:
+            lib().lc_workspace_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Schedule:
+    def __init__(self, grid: Grid, kind, offsets=None):
+        if isinstance(kind, str):
+            kind = KINDS[kind]
+        self._h = ctypes.c_void_p()
+        self.grid = grid
+        if offsets is not None:
+            import numpy as np
+            arr = np.ascontiguousarray(np.asarray(offsets, dtype=np.int8).reshape(-1, 3))
+            self._offs = arr
+            op, n = ctypes.c_void_p(arr.ctypes.data), arr.shape[0]
+        else:
+            op, n = None, 0
+        _chk(lib().lc_make_schedule(grid.ptr, int(kind), op, int(n),
+                                    ctypes.byref(self._h)))
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def info(self) -> dict:
+        i = _SchedInfo()
+        _chk(lib().lc_schedule_info_get(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in _SchedInfo._fields_ if k != "pad"}
+
+    def close(self):
+        if self._h:
+            lib().lc_schedule_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def schedule_plan(grid: Grid, kind, offsets=None) -> dict:
+    """Host-only: build and validate a schedule, return its shape."""
+    import numpy as np
+    if isinstance(kind, str):
+        kind = KINDS[kind]
+    if offsets is not None:
+        arr = np.ascontiguousarray(np.asarray(offsets, dtype=np.int8).reshape(-1, 3))
+        op, n = ctypes.c_void_p(arr.ctypes.data), arr.shape[0]
+    else:
+        op, n = None, 0
+    i = _SchedInfo()
+    _chk(lib().lc_schedule_plan(grid.ptr, int(kind), op, int(n), ctypes.byref(i)))
+    return {k: getattr(i, k) for k, _ in _SchedInfo._fields_ if k != "pad"}
+
+
+def validate_phases(ncell: int, phase_grp, grp_foot, foot_cells) -> None:
+    """Host-only schedule validator on explicit arrays; raises LCError
+    (code LC_ESCHED = -4) when a phase has two groups writing one cell."""
+    import numpy as np
+    pg = np.ascontiguousarray(np.asarray(phase_grp, dtype=np.int32))
+    gf = np.ascontiguousarray(np.asarray(grp_foot, dtype=np.int32))
+    fc = np.ascontiguousarray(np.asarray(foot_cells, dtype=np.int32))
+    _chk(lib().lc_validate_phases(int(ncell), len(pg) - 1, ctypes.c_void_p(pg.ctypes.data),
+                                  ctypes.c_void_p(gf.ctypes.data),
+                                  ctypes.c_void_p(fc.ctypes.data)))
+
+
+def build_cells(grid: Grid, pos: torch.Tensor, ws: Workspace, cell_start=None,
+                perm=None, coord=None, stream=None):
+    """Counting sort into cells.  pos: (3, N) float64 cuda.  Returns
+    (cell_start int32 [ncell+1], perm int32 [N], coord uint32-as-int32 (3, N))."""
+    n = pos.shape[1]
+    dev = pos.device
+    if cell_start is None:
+        cell_start = torch.empty(grid.ncell + 1, dtype=torch.int32, device=dev)
+    if perm is None:
+        perm = torch.empty(n, dtype=torch.int32, device=dev)
+    if coord is None:
+        coord = torch.empty((3, n), dtype=torch.int32, device=dev)
+    _chk(lib().lc_build_cells(grid.ptr, _p(pos), n, _p(cell_start), _p(perm),
+                              _p(coord), ws.ptr, _stream(stream)))
+    return cell_start, perm, coord
+
+
+def gather(perm: torch.Tensor, src3: torch.Tensor, ids: torch.Tensor | None = None,
+           stream=None):
+    n = perm.shape[0]
+    out = torch.empty_like(src3)
+    out_ids = torch.empty_like(ids) if ids is not None else None
+    _chk(lib().lc_gather(_p(perm), n, _p(src3), _p(out), _p(ids), _p(out_ids),
+                         _stream(stream)))
+    return out, out_ids
+
+
+def compute_forces(grid: Grid, sched: Schedule, cell_start, coord, ws: Workspace,
+                   precision: str = "fp32", F=None, ew=None, stream=None):
+    """One force evaluation.  Returns (F int64 (3, N) cell-sorted, ew int64
+    [energy, virial, pairs])."""
+    n = coord.shape[1]
+    dev = coord.device
+    if F is None:
+        F = torch.empty((3, n), dtype=torch.int64, device=dev)
+    if ew is None:
+        ew = torch.empty(3, dtype=torch.int64, device=dev)
+    _chk(lib().lc_compute_forces(grid.ptr, sched.ptr, _p(cell_start), _p(coord), n,
+                                 _p(F), _p(ew), PREC[precision], ws.ptr,
+                                 _stream(stream)))
+    return F, ew
+
+
+def compute_forces_profiled(grid: Grid, sched: Schedule, cell_start, coord,
+                            ws: Workspace, precision: str = "fp32", F=None, ew=None,
+                            stream=None):
+    """compute_forces with HIP events around every sweep phase (synchronises).
+    Returns (F, ew, sweep_ms, per-phase ms list)."""
+    import numpy as np
+    n = coord.shape[1]
+    dev = coord.device
+    if F is None:
+        F = torch.empty((3, n), dtype=torch.int64, device=dev)
+    if ew is None:
+        ew = torch.empty(3, dtype=torch.int64, device=dev)
+    nphase = sched.info()["nphase"]
+    ph = np.zeros(max(nphase, 1), dtype=np.float64)
+    tot = ctypes.c_double(0.0)
+    _chk(lib().lc_compute_forces_profiled(grid.ptr, sched.ptr, _p(cell_start), _p(coord), n,
+                                          _p(F), _p(ew), PREC[precision], ws.ptr,
+                                          _stream(stream), ctypes.byref(tot),
+                                          ctypes.c_void_p(ph.ctypes.data)))
+    return F, ew, float(tot.value), ph[:nphase].tolist()
+
+
+def verlet_step(grid: Grid, sched: Schedule, pos, vel, ids, ws: Workspace,
+                dt: float, nsteps: int, rebuild_every: int, F=None,
+                cell_start=None, perm=None, coord=None, trace=None, stream=None):
+    """nsteps of velocity Verlet; pos/vel/ids are reordered in place into cell
+    order.  Returns (trace int64 (nsteps+1, 2) [KE, PE], F)."""
+    n = pos.shape[1]
+    dev = pos.device
+    if F is None:
+        F = torch.empty((3, n), dtype=torch.int64, device=dev)
+    if cell_start is None:
+        cell_start = torch.empty(grid.ncell + 1, dtype=torch.int32, device=dev)
+    if perm is None:
+        perm = torch.empty(n, dtype=torch.int32, device=dev)
+    if coord is None:
+        coord = torch.empty((3, n), dtype=torch.int32, device=dev)
+    if trace is None:
+        trace = torch.empty((nsteps + 1, 2), dtype=torch.int64, device=dev)
+    _chk(lib().lc_verlet_step(grid.ptr, sched.ptr, _p(pos), _p(vel), _p(ids), n,
+                              _p(F), _p(cell_start), _p(perm), _p(coord),
+                              float(dt), int(nsteps), int(rebuild_every),
+                              _p(trace), ws.ptr, _stream(stream)))
+    return trace, F
+
+
+def kinetic_energy(vel: torch.Tensor, out=None, stream=None):
+    n = vel.shape[1]
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=vel.device)
+    _chk(lib().lc_kinetic_energy(_p(vel), n, _p(out), _stream(stream)))
+    return out
+
+
+def serialization_degree(dims, kind, offsets=None, hist_len: int = 0) -> dict:
+    """Host-only: critical path of a creation order's task DAG (Eq. 1-4)."""
+    import numpy as np
+    if isinstance(kind, str):
+        kind = KINDS[kind]
+    d = (ctypes.c_int32 * 3)(*[int(x) for x in dims])
+    if offsets is not None:
+        arr = np.ascontiguousarray(np.asarray(offsets, dtype=np.int8).reshape(-1, 3))
+        op, n = ctypes.c_void_p(arr.ctypes.data), arr.shape[0]
+    else:
+        op, n = None, 0
+    hist = np.zeros(max(hist_len, 0), dtype=np.int64)
+    hp = ctypes.c_void_p(hist.ctypes.data) if hist_len > 0 else None
+    r = _SD()
+    _chk(lib().lc_serialization_degree(ctypes.cast(d, P), int(kind), op, int(n), hp,
+                                       int(hist_len), ctypes.byref(r)))
+    out = {k: getattr(r, k) for k, _ in _SD._fields_}
+    if hist_len > 0:
+        out["level_hist"] = hist
+    return out

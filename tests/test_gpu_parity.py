@@ -1,0 +1,223 @@
+"""GPU parity: the HIP path (through the C-ABI binding) against the oracle.
+
+Bar: forces, energies, virials and pair counts are int64 and must be
+bit-exact against the oracle's fixed-point link-cell sweep for every
+schedule; cell_start must match exactly and cell membership as sets; the
+FP64-arithmetic variant must sit within 2e-7 normwise of the FP64 oracle
+(their only difference is the box-fraction quantisation of the positions,
+a step of L * 2^-32 = 4e-9 at L = 17.1; the LJ force changes by a factor
+of about 14 / r ~ 15 per unit relative displacement near contact, giving
+~6e-8, with a margin of 3); the FP32 path within 1e-5 normwise and per particle within
+1e-5 * sum_j |f_ij| of FP64; Verlet trajectories bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1401_4441_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+lc = pytest.importorskip("paper_1401_4441_amd.lc")
+
+DEV = torch.device("cuda:0")
+KINDS = ["block8", "atomic_tile", "atomic_pair", "loopex", "opt", "lex"]
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+class Setup:
+    def __init__(self, box, skin=0.0, even=False):
+        self.box = box
+        self.g = lc.Grid(box.L, box.rc, skin, even)
+        self.ws = lc.Workspace(box.n, self.g.ncell)
+        self.pos = torch.from_numpy(box.pos).to(DEV)
+        self.cs, self.perm, self.coord = lc.build_cells(self.g, self.pos, self.ws)
+        self.perm_h = self.perm.cpu().numpy()
+        self.u = O.canonical(box.pos, box.L)
+
+    def unsort(self, F):
+        Fh = F.cpu().numpy()
+        out = np.empty_like(Fh)
+        out[:, self.perm_h] = Fh
+        return out
+
+    def forces(self, kind, precision="fp32"):
+        s = lc.Schedule(self.g, kind)
+        self.ws.clear_status()
+        F, ew = lc.compute_forces(self.g, s, self.cs, self.coord, self.ws, precision)
+        torch.cuda.synchronize()
+        return self.unsort(F), [int(x) for x in ew.cpu().numpy()], self.ws.status()
+
+
+_c1 = None
+
+
+def c1():
+    global _c1
+    if _c1 is None:
+        _c1 = Setup(synth.fcc(4000, 0.8, rc=2.5, seed=1001))
+    return _c1
+
+
+def test_build_cells_c1():
+    S = c1()
+    _say("build_cells fcc4k nc", S.g.nc)
+    cs = S.cs.cpu().numpy()
+    assert (cs == O.cell_start(S.u, S.g.nc)).all()
+    perm = S.perm_h
+    assert np.array_equal(np.sort(perm), np.arange(S.box.n))
+    # slot k lies in the cell whose range contains k (membership as sets)
+    cid = O.cell_ids(S.u, S.g.nc)
+    slot_cell = np.repeat(np.arange(S.g.ncell), np.diff(cs))
+    assert (cid[perm] == slot_cell).all()
+    coord = S.coord.cpu().numpy().view(np.uint32)
+    assert (coord == S.u[:, perm]).all()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_forces_bit_exact_c1(kind):
+    S = c1()
+    _say("forces fcc4k", kind)
+    F, ew, st = S.forces(kind)
+    Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, S.box.L, S.box.rc, S.g.nc)
+    assert st & lc.FLAG_OVERFLOW == 0
+    assert (F == Fo).all()
+    assert ew == [Eo, Wo, npo]
+
+
+def test_fp64_variant_and_fp32_error_c1():
+    S = c1()
+    _say("fp64 variant fcc4k")
+    F64g, ew64, _ = S.forces("block8", "fp64")
+    F32g, ew32, _ = S.forces("block8", "fp32")
+    F, mag, U, W, npairs = O.forces_brute_f64(S.box.pos, S.box.L, S.box.rc, u=S.u)
+    assert ew64[2] == ew32[2] == npairs
+    err64 = np.linalg.norm(F64g / lc.SCALE - F) / np.linalg.norm(F)
+    assert err64 <= 2e-7
+    Fx = F32g / lc.SCALE
+    err32 = np.linalg.norm(Fx - F) / np.linalg.norm(F)
+    assert err32 <= 1e-5
+    assert (np.abs(Fx - F).max(axis=0) <= 1e-5 * mag).all()
+    assert ew32[0] / lc.SCALE == pytest.approx(U, rel=1e-5)
+
+
+def test_momentum_exact_c1():
+    S = c1()
+    F, _, _ = S.forces("block8")
+    assert (F.sum(axis=1) == 0).all()
+
+
+def test_c2_full_size_all_schedules():
+    """256k particles, 26^3 cells: every schedule bit-exact vs the oracle."""
+    box = synth.fcc(256000, 0.8, rc=2.5, seed=1002)
+    S = Setup(box, even=True)
+    _say("fcc256k nc", S.g.nc)
+    Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
+    for kind in ["block8", "atomic_tile", "atomic_pair", "loopex", "lex"]:
+        _say("  fcc256k", kind)
+        F, ew, st = S.forces(kind)
+        assert (F == Fo).all(), kind
+        assert ew == [Eo, Wo, npo], kind
+        assert st == 0, (kind, st)
+
+
+def test_ragged_and_vacancies():
+    """N not a multiple of the lattice or of 64; odd cell counts."""
+    for n, rho, seed in ((1234, 0.8, 3), (777, 0.6, 4), (5003, 0.85, 5)):
+        box = synth.fcc(n, rho, rc=2.5, seed=seed)
+        S = Setup(box)
+        _say("ragged", n, rho, S.g.nc)
+        Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
+        for kind in ("block8", "atomic_pair", "opt"):
+            F, ew, _ = S.forces(kind)
+            assert (F == Fo).all() and ew == [Eo, Wo, npo], (n, kind)
+
+
+def test_minimum_grid_and_empty_cells():
+    """3 cells per axis (the smallest grid) and a dilute box with many empty
+    cells."""
+    cases = [synth.fcc(108, 0.15, rc=2.5, seed=7),   # L = 8.96: 3^3 cells
+             synth.fcc(200, 0.05, rc=2.5, seed=8)]   # dilute: many empty cells
+    for box in cases:
+        S = Setup(box)
+        _say("small", box.n, S.g.nc)
+        Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
+        for kind in ("block8", "atomic_tile", "atomic_pair", "lex"):
+            F, ew, _ = S.forces(kind)
+            assert (F == Fo).all() and ew == [Eo, Wo, npo], kind
+
+
+def test_lds_overflow_falls_back_exactly():
+    """A cutoff so large that a work-group footprint exceeds the LDS tile:
+    the global-memory path takes over and stays bit-exact."""
+    box = synth.fcc(4000, 0.8, rc=5.6, seed=9)  # 3^3 cells of 5.7
+    S = Setup(box)
+    _say("fallback nc", S.g.nc)
+    Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
+    for kind in ("block8", "atomic_tile"):
+        F, ew, st = S.forces(kind)
+        assert st & lc.FLAG_FALLBACK
+        assert (F == Fo).all() and ew == [Eo, Wo, npo], kind
+
+
+def test_overflow_flag():
+    """Two particles 0.05 apart: the force exceeds the fixed-point range;
+    the oracle refuses too."""
+    box = synth.fcc(500, 0.8, rc=2.5, seed=10)
+    box.pos[:, 1] = box.pos[:, 0] + np.array([0.05, 0.0, 0.0])
+    S = Setup(box)
+    _, _, st = S.forces("block8")
+    assert st & lc.FLAG_OVERFLOW
+    with pytest.raises(O.OracleError):
+        O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
+
+
+def _verlet_gpu(box, vel, dt, steps, rebuild, skin, chunks=(None,)):
+    g = lc.Grid(box.L, box.rc, skin)
+    ws = lc.Workspace(box.n, g.ncell)
+    s = lc.Schedule(g, "block8")
+    pos = torch.from_numpy(box.pos).to(DEV)
+    v = torch.from_numpy(vel).to(DEV)
+    ids = torch.arange(box.n, dtype=torch.int32, device=DEV)
+    traces = []
+    for c in chunks:
+        tr, F = lc.verlet_step(g, s, pos, v, ids, ws, dt, c or steps, rebuild)
+        traces.append(tr.cpu().numpy())
+    torch.cuda.synchronize()
+    idh = ids.cpu().numpy()
+    P = np.empty((3, box.n))
+    V = np.empty((3, box.n))
+    P[:, idh] = pos.cpu().numpy()
+    V[:, idh] = v.cpu().numpy()
+    return P, V, traces, ws.status()
+
+
+def test_verlet_bit_exact_vs_oracle():
+    box = synth.fcc(4000, 0.8, rc=2.5, seed=1001)
+    vel = synth.maxwell_boltzmann(box.n, 1.0, seed=2001)
+    _say("verlet fcc4k 20 steps")
+    P, V, (tr,), st = _verlet_gpu(box, vel, 0.005, 20, 10, 0.6)
+    Po, Vo, Fo, tro = O.verlet_fx(box.pos, vel, box.L, box.rc, 0.005, 20)
+    assert st & lc.FLAG_DISP == 0
+    assert (P == Po).all() and (V == Vo).all()
+    assert (tr == tro).all()
+
+
+def test_verlet_resume_is_bit_exact():
+    box = synth.fcc(2048, 0.8, rc=2.5, seed=12)
+    vel = synth.maxwell_boltzmann(box.n, 1.0, seed=13)
+    P1, V1, _, _ = _verlet_gpu(box, vel, 0.005, 20, 10, 0.6)
+    P2, V2, trs, _ = _verlet_gpu(box, vel, 0.005, 20, 10, 0.6, chunks=(10, 10))
+    assert (P1 == P2).all() and (V1 == V2).all()
+
+
+def test_displacement_flag():
+    """Cells kept far longer than the skin allows must raise the flag."""
+    box = synth.fcc(2048, 0.8, rc=2.5, seed=14)
+    vel = synth.maxwell_boltzmann(box.n, 1.0, seed=15)
+    _, _, _, st = _verlet_gpu(box, vel, 0.005, 120, 1000, 0.1)
+    assert st & lc.FLAG_DISP
