@@ -274,9 +274,10 @@ int lc_verlet_step(const lc_grid *g, const lc_schedule *s, double *pos,
                    double dt, int nsteps, int rebuild_every, int64_t *trace,
                    lc_workspace *ws, void *stream);
 
-/* Kinetic energy {sum of rint(0.5 v^2 2^32)} into ke[0] (device int64). */
+/* Kinetic energy {sum of rint(0.5 v^2 2^32)} into ke[0] (device int64);
+ * ws provides the partial-sum slots. */
 int lc_kinetic_energy(const double *vel, int64_t n, int64_t *ke,
-                      void *stream);
+                      lc_workspace *ws, void *stream);
 
 #ifdef __cplusplus
 }

@@ -74,6 +74,7 @@ struct lc_workspace {
     int32_t *partial = nullptr;  // scan block totals
     uint32_t *flags = nullptr;   // device status flags
     int64_t *ew = nullptr;       // 3: energy, virial, pairs
+    int64_t *part = nullptr;     // kPartSlots x 3 spread partial sums
     int64_t *ke = nullptr;       // 1
     double *xref = nullptr;      // 3N positions at the last rebuild
     double *tmp3 = nullptr;      // 3N staging for reorders
@@ -82,6 +83,7 @@ struct lc_workspace {
 
 struct lc_schedule {
     int device = 0;
+    int ncu = 256;
     int32_t nc[3] = {0, 0, 0};
     lcs::HostSchedule h;
     int32_t *grp_task = nullptr, *grp_foot = nullptr, *foot_cells = nullptr;
@@ -92,6 +94,7 @@ struct lc_schedule {
 // device helpers
 // ---------------------------------------------------------------------------
 
+constexpr int kPartSlots = 1024;    // spread slots for global int64 sums
 constexpr int kWG = 512;            // threads per sweep work-group
 constexpr int kNW = kWG / 64;       // waves per sweep work-group
 constexpr int kQ = 128;             // per-wave pair queue (>= 64 + 63)
@@ -402,134 +405,133 @@ struct SweepArgs {
     const uint32_t *coord;
     int64_t n;
     long long *F;
-    long long *ew;
+    long long *part;  // kPartSlots x 3 partial {energy, virial, pairs}
     uint32_t *flags;
+    int ksplit;       // i-range per work unit (0: whole range), see sweep_pairs
     PairParams pp;
 };
 
-// WMODE: 0 = accumulate in LDS, plain read-modify-write of the footprint
-//        (the phase must be conflict-free); 1 = accumulate in LDS, global
-//        atomic write-back; 2 = every pair adds into global memory with
-//        atomics.
-template <int CAP, int WMODE, bool F64>
-__global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
-    __shared__ uint32_t s_u[3][CAP];
-    __shared__ long long s_acc[WMODE == 2 ? 1 : 3][WMODE == 2 ? 1 : CAP];
-    __shared__ int s_fg[kMaxF];          // global first slot of footprint cell
-    __shared__ int s_fl[kMaxF + 1];      // local first slot (prefix)
-    __shared__ int s_taoff[kMaxT];       // local first slot of cell A
-    __shared__ int s_tna[kMaxT];         // particles in A
-    __shared__ int s_tboff[kMaxT];       // local first slot of cell B (bit 31: intra)
-    __shared__ int s_tslot[kMaxT + 1];   // prefix of |B| over tasks
-    __shared__ uint32_t s_q[kNW][kQ];
-    __shared__ int s_w[kNW + 1];
+// Exact round-to-nearest-even of v * 2^32 to int64 for |v * 2^32| < 2^51:
+// adding 1.5 * 2^52 in FP64 rounds the (exactly scaled) value to an integer
+// that then sits in the low mantissa bits.  Lanes outside that range (or
+// NaN) set `slow` and are redone with q32f, which also flags overflow.
+__device__ __forceinline__ long long q32_fast(float v, bool &slow) {
+    const double d = (double)v * 4294967296.0;
+    const double magic = 6755399441055744.0;  // 1.5 * 2^52
+    slow |= !(fabs(d) < 2251799813685248.0);  // 2^51
+    return (long long)__double_as_longlong(d + magic) - 0x4338000000000000LL;
+}
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int g = a.grp_base + blockIdx.x;
-    const int t0 = a.grp_task[g], nt = a.grp_task[g + 1] - t0;
-    const int f0 = a.grp_foot[g], nf = a.grp_foot[g + 1] - f0;
+// FP32 pair terms with the fast quantisation; same values as pair_terms<false>.
+__device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, const PairParams &p,
+                                                long long &qx, long long &qy, long long &qz,
+                                                long long &qe, long long &qw, uint32_t &ovf) {
+    float dx = canon_d(uj.x, ui.x, p.s[0]);
+    float dy = canon_d(uj.y, ui.y, p.s[1]);
+    float dz = canon_d(uj.z, ui.z, p.s[2]);
+    float r2 = dx * dx + dy * dy;
+    r2 = r2 + dz * dz;
+    if (!(r2 < p.rc2)) return false;
+    float inv = 1.0f / r2;
+    float s6 = inv * inv;
+    s6 = s6 * inv;
+    float t = 24.0f * inv;
+    t = t * s6;
+    float g = 2.0f * s6;
+    g = g - 1.0f;
+    const float fs = t * g;
+    float e = 4.0f * s6;
+    e = e * (s6 - 1.0f);
+    e = e - p.ecut;
+    const float fx = fs * dx, fy = fs * dy, fz = fs * dz, w = fs * r2;
+    bool slow = false;
+    qx = q32_fast(fx, slow);
+    qy = q32_fast(fy, slow);
+    qz = q32_fast(fz, slow);
+    qe = q32_fast(e, slow);
+    qw = q32_fast(w, slow);
+    if (slow) {
+        qx = q32f(fx, ovf);
+        qy = q32f(fy, ovf);
+        qz = q32f(fz, ovf);
+        qe = q32f(e, ovf);
+        qw = q32f(w, ovf);
+    }
+    return true;
+}
+
+// Shared memory of one sweep work-group.
+template <int CAP, int WMODE>
+struct SweepLDS {
+    uint4 u[CAP];                                           // box fractions
+    long long acc[WMODE == 2 ? 1 : 3][WMODE == 2 ? 1 : CAP];  // int64 forces
+    int fg[kMaxF];          // global first slot of each footprint cell
+    int fl[kMaxF + 1];      // local first slot (prefix over the footprint)
+    int ta[kMaxT];          // task: local first slot of A | (count of A << 16)
+    int tb[kMaxT];          // task: local first slot of B, bit 31 = intra
+    int tslot[kMaxT + 1];   // prefix of |B| over the tasks
+    uint32_t q[kNW][kQ];    // per-wave queue of in-cutoff pairs (i | j << 16)
+    long long red[kNW][3];
+    int w[kNW + 1];
+    int maxna;              // largest cell A over the group's tasks
+};
+
+// Global slot of a local footprint index (fallback path).
+template <class L>
+__device__ __forceinline__ int64_t foot_gidx(const L &sh, int nf, int l) {
+    int lo = 0, hi = nf;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sh.fl[mid] <= l) lo = mid; else hi = mid;
+    }
+    return (int64_t)sh.fg[lo] + (l - sh.fl[lo]);
+}
+
+// The candidate loop and pair evaluation of one work-group.  STAGED: the
+// footprint's box fractions and accumulators live in LDS; otherwise box
+// fractions come from global memory and every pair adds into F with global
+// atomics.
+template <int CAP, int WMODE, bool F64, bool STAGED>
+__device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE> &sh, const SweepArgs &a, int nf,
+                                            int nt, int nslot, long long &e_sum, long long &w_sum,
+                                            long long &p_cnt, uint32_t &ovf) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t n = a.n;
-
-    // footprint table and local layout
-    int cnt = 0;
-    if (tid < nf) {
-        const int c = a.foot_cells[f0 + tid];
-        const int gs = a.cell_start[c];
-        cnt = a.cell_start[c + 1] - gs;
-        s_fg[tid] = gs;
-    }
-    int total;
-    const int lofs = block_scan_excl<kWG>(cnt, s_w, total);
-    if (tid < nf) s_fl[tid] = lofs;
-    if (tid == 0) s_fl[nf] = total;
-    const bool staged = total <= CAP;
-    if (total > 65535) {  // local indices are packed in 16 bits
-        if (tid == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_OVERFLOW);
-        return;
-    }
-    if (!staged && tid == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_FALLBACK);
-    __syncthreads();
-
-    // stage box fractions of the footprint, zero the accumulators
-    if (staged) {
-        for (int f = wave; f < nf; f += kNW) {
-            const int gs = s_fg[f], ls = s_fl[f], c = s_fl[f + 1] - ls;
-            for (int q = lane; q < c; q += 64) {
-                s_u[0][ls + q] = a.coord[gs + q];
-                s_u[1][ls + q] = a.coord[n + gs + q];
-                s_u[2][ls + q] = a.coord[2 * n + gs + q];
-                if constexpr (WMODE != 2) {
-                    s_acc[0][ls + q] = 0;
-                    s_acc[1][ls + q] = 0;
-                    s_acc[2][ls + q] = 0;
-                }
-            }
-        }
-    }
-    // task table
-    int nb = 0;
-    if (tid < nt) {
-        const uint32_t ab = a.task_ab[t0 + tid];
-        const int la = (int)(ab & 0xffffu), lb = (int)(ab >> 16);
-        s_taoff[tid] = s_fl[la];
-        s_tna[tid] = s_fl[la + 1] - s_fl[la];
-        s_tboff[tid] = s_fl[lb] | (la == lb ? (int)0x80000000 : 0);
-        nb = s_fl[lb + 1] - s_fl[lb];
-    }
-    int nslot;
-    const int so = block_scan_excl<kWG>(nb, s_w, nslot);
-    if (tid < nt) s_tslot[tid] = so;
-    if (tid == 0) s_tslot[nt] = nslot;
-    __syncthreads();
-
-    // global slot of a local index (fallback path only)
-    auto gidx = [&](int l) -> int64_t {
-        int lo = 0, hi = nf;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_fl[mid] <= l) lo = mid; else hi = mid;
-        }
-        return (int64_t)s_fg[lo] + (l - s_fl[lo]);
-    };
-    auto load_u = [&](int l, uint32_t &x, uint32_t &y, uint32_t &z) {
-        if (staged) {
-            x = s_u[0][l];
-            y = s_u[1][l];
-            z = s_u[2][l];
-        } else {
-            const int64_t gi = gidx(l);
-            x = a.coord[gi];
-            y = a.coord[n + gi];
-            z = a.coord[2 * n + gi];
-        }
-    };
-
     const PairParams pp = a.pp;
-    long long e_sum = 0, w_sum = 0, p_cnt = 0;
-    uint32_t ovf = 0;
-    uint32_t *q = s_q[wave];
+    uint32_t *q = sh.q[wave];
     int qn = 0;  // wave-uniform queue length
 
-    // Evaluate the pair in queue slot `slot` (one per lane) and scatter it.
+    auto load_u = [&](int l) -> uint4 {
+        if constexpr (STAGED) {
+            return sh.u[l];
+        } else {
+            const int64_t gi = foot_gidx(sh, nf, l);
+            return make_uint4(a.coord[gi], a.coord[n + gi], a.coord[2 * n + gi], 0u);
+        }
+    };
+
     auto eval = [&](uint32_t ent) {
         const int il = (int)(ent & 0xffffu), jl = (int)(ent >> 16);
-        uint32_t ix, iy, iz, jx, jy, jz;
-        load_u(il, ix, iy, iz);
-        load_u(jl, jx, jy, jz);
+        const uint4 ui = load_u(il), uj = load_u(jl);
         long long qx, qy, qz, qe, qw;
-        if (!pair_terms<F64>(ix, iy, iz, jx, jy, jz, pp, qx, qy, qz, qe, qw, ovf)) return;
+        bool in;
+        if constexpr (F64)
+            in = pair_terms<true>(ui.x, ui.y, ui.z, uj.x, uj.y, uj.z, pp, qx, qy, qz, qe, qw, ovf);
+        else
+            in = pair_terms_fast(ui, uj, pp, qx, qy, qz, qe, qw, ovf);
+        if (!in) return;
         e_sum += qe;
         w_sum += qw;
         p_cnt += 1;
-        if (WMODE != 2 && staged) {
-            atomicAdd((unsigned long long *)&s_acc[0][il], (unsigned long long)(-qx));
-            atomicAdd((unsigned long long *)&s_acc[1][il], (unsigned long long)(-qy));
-            atomicAdd((unsigned long long *)&s_acc[2][il], (unsigned long long)(-qz));
-            atomicAdd((unsigned long long *)&s_acc[0][jl], (unsigned long long)qx);
-            atomicAdd((unsigned long long *)&s_acc[1][jl], (unsigned long long)qy);
-            atomicAdd((unsigned long long *)&s_acc[2][jl], (unsigned long long)qz);
+        if constexpr (STAGED && WMODE != 2) {
+            atomicAdd((unsigned long long *)&sh.acc[0][il], (unsigned long long)(-qx));
+            atomicAdd((unsigned long long *)&sh.acc[1][il], (unsigned long long)(-qy));
+            atomicAdd((unsigned long long *)&sh.acc[2][il], (unsigned long long)(-qz));
+            atomicAdd((unsigned long long *)&sh.acc[0][jl], (unsigned long long)qx);
+            atomicAdd((unsigned long long *)&sh.acc[1][jl], (unsigned long long)qy);
+            atomicAdd((unsigned long long *)&sh.acc[2][jl], (unsigned long long)qz);
         } else {
-            const int64_t gi = gidx(il), gj = gidx(jl);
+            const int64_t gi = foot_gidx(sh, nf, il), gj = foot_gidx(sh, nf, jl);
             unsigned long long *F = (unsigned long long *)a.F;
             atomicAdd(&F[gi], (unsigned long long)(-qx));
             atomicAdd(&F[n + gi], (unsigned long long)(-qy));
@@ -540,41 +542,63 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
         }
     };
 
-    for (int base = wave * 64; base < nslot; base += kNW * 64) {
+    // Work units: a chunk of 64 consecutive j slots, and (when ksplit > 0)
+    // a sub-range of ksplit steps of its i loop, so that a group with few
+    // chunks still spreads over all of its waves.
+    const int nchunk = (nslot + 63) >> 6;
+    const int nsub = a.ksplit > 0 ? max(1, (sh.maxna + a.ksplit - 1) / a.ksplit) : 1;
+    const int nunit = nchunk * nsub;
+    for (int unit = wave; unit < nunit; unit += kNW) {
+        const int chunk = unit / nsub, sub = unit - chunk * nsub;
+        const int base = chunk * 64;
         const int s = base + lane;
         const bool valid = s < nslot;
-        int t = 0;
-        {
-            int lo = 0, hi = nt;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (s_tslot[mid] <= s) lo = mid; else hi = mid;
-            }
-            t = lo;
+        int lo = 0, hi = nt;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (sh.tslot[mid] <= s) lo = mid; else hi = mid;
         }
-        const int jj = s - s_tslot[t];
-        const int bo = s_tboff[t];
+        const int t = lo;
+        const int jj = s - sh.tslot[t];
+        const int bo = sh.tb[t];
         const bool intra = bo < 0;
         const int jl = (bo & 0x7fffffff) + jj;
-        const int aoff = s_taoff[t];
-        int kend = valid ? s_tna[t] : 0;
-        if (intra) kend = min(kend, jj);
-        uint32_t jx = 0, jy = 0, jz = 0;
-        if (valid) load_u(jl, jx, jy, jz);
-        const int kmax = wave_max32(kend);
-        for (int k = 0; k < kmax; ++k) {
-            const bool act = k < kend;
-            const int il = act ? aoff + k : aoff;
-            bool in = false;
-            if (act) {
-                uint32_t ix, iy, iz;
-                load_u(il, ix, iy, iz);
-                in = canon_r2(ix, iy, iz, jx, jy, jz, pp) < pp.rc2;
+        const int ta = sh.ta[t];
+        const int aoff = ta & 0xffff;
+        const int na = valid ? (ta >> 16) : 0;
+        uint4 uj = make_uint4(0u, 0u, 0u, 0u);
+        if (valid) uj = load_u(jl);
+        // diagonal order: lane jj visits i = (k + jj) mod na, so the lanes of
+        // one task touch different i at each step (spreads the i-side LDS
+        // atomics); intra tasks keep each unordered pair once via i < j
+        const int kmax0 = wave_max32(na);
+        const int kbeg = nsub > 1 ? sub * a.ksplit : 0;
+        const int kmax = nsub > 1 ? min(kmax0, kbeg + a.ksplit) : kmax0;
+        int ik = na > 0 ? (jj + kbeg) % na : 0;
+        // software pipeline: the box fraction of the next i is loaded while
+        // the current one is tested (the load index is clamped so it is
+        // always inside the staged footprint)
+        auto i_of = [&](int kk) { return aoff + kk; };
+        uint4 ui_next = make_uint4(0u, 0u, 0u, 0u);
+        if constexpr (STAGED) ui_next = sh.u[min(i_of(ik), CAP - 1)];
+        for (int k = kbeg; k < kmax; ++k) {
+            const bool act = k < na && (!intra || ik < jj);
+            const int il = i_of(ik);
+            const int ik_next = ik + 1 == na ? 0 : ik + 1;
+            uint4 ui;
+            if constexpr (STAGED) {
+                ui = ui_next;
+                ui_next = sh.u[min(i_of(ik_next), CAP - 1)];
+            } else {
+                ui = act ? load_u(il) : make_uint4(0u, 0u, 0u, 0u);
             }
+            const bool in = act && canon_r2(ui.x, ui.y, ui.z, uj.x, uj.y, uj.z, pp) < pp.rc2;
+            ik = ik_next;
             const unsigned long long m = __ballot(in);
             if (in) {
-                const int pos = qn + (int)__popcll(m & ((1ull << lane) - 1ull));
-                q[pos] = (uint32_t)il | ((uint32_t)jl << 16);
+                const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                q[qn + below] = (uint32_t)il | ((uint32_t)jl << 16);
             }
             qn += (int)__popcll(m);
             if (qn >= 64) {
@@ -594,34 +618,138 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     if (lane < qn) eval(q[lane]);
+}
 
-    // energy, virial, pair count: one atomic per wave
+// One phase of cell-cell tasks; one work-group per task group.
+// WMODE: 0 = accumulate in LDS, plain read-modify-write of the footprint
+//        (the phase must be conflict-free); 1 = accumulate in LDS, global
+//        atomic write-back; 2 = every pair adds into global memory with
+//        atomics.
+template <int CAP, int WMODE, bool F64>
+__global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
+    __shared__ SweepLDS<CAP, WMODE> sh;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = a.grp_base + blockIdx.x;
+    const int t0 = a.grp_task[g], nt = a.grp_task[g + 1] - t0;
+    const int f0 = a.grp_foot[g], nf = a.grp_foot[g + 1] - f0;
+    const int64_t n = a.n;
+
+    // footprint table and local layout (the task entry is fetched now so
+    // that its load overlaps the footprint's)
+    const uint32_t my_ab = tid < nt ? a.task_ab[t0 + tid] : 0u;
+    int cnt = 0;
+    if (tid < nf) {
+        const int c = a.foot_cells[f0 + tid];
+        const int gs = a.cell_start[c];
+        cnt = a.cell_start[c + 1] - gs;
+        sh.fg[tid] = gs;
+    }
+    int total;
+    const int lofs = block_scan_excl<kWG>(cnt, sh.w, total);
+    if (tid < nf) sh.fl[tid] = lofs;
+    if (tid == 0) sh.fl[nf] = total;
+    if (total > 65535) {  // local indices are packed in 16 bits
+        if (tid == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_OVERFLOW);
+        return;
+    }
+    const bool staged = total <= CAP;
+    if (!staged && tid == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_FALLBACK);
+    __syncthreads();
+
+    // Stage the footprint: one particle per thread, all global loads in
+    // flight together.  With plain write-back (WMODE 0) the accumulators
+    // start from the current forces, which no other work-group of this phase
+    // touches, so the write-back below is a plain store.
+    if (staged) {
+        for (int k = tid; k < total; k += kWG) {
+            const int64_t gi = foot_gidx(sh, nf, k);
+            const uint32_t ux = a.coord[gi], uy = a.coord[n + gi], uz = a.coord[2 * n + gi];
+            if constexpr (WMODE == 0) {
+                const long long fx = a.F[gi], fy = a.F[n + gi], fz = a.F[2 * n + gi];
+                sh.acc[0][k] = fx;
+                sh.acc[1][k] = fy;
+                sh.acc[2][k] = fz;
+            } else if constexpr (WMODE == 1) {
+                sh.acc[0][k] = 0;
+                sh.acc[1][k] = 0;
+                sh.acc[2][k] = 0;
+            }
+            sh.u[k] = make_uint4(ux, uy, uz, 0u);
+        }
+    }
+    // task table
+    if (tid == 0) sh.maxna = 0;
+    __syncthreads();
+    int nb = 0;
+    if (tid < nt) {
+        const uint32_t ab = my_ab;
+        const int la = (int)(ab & 0xffffu), lb = (int)(ab >> 16);
+        sh.ta[tid] = sh.fl[la] | ((sh.fl[la + 1] - sh.fl[la]) << 16);
+        sh.tb[tid] = sh.fl[lb] | (la == lb ? (int)0x80000000 : 0);
+        nb = sh.fl[lb + 1] - sh.fl[lb];
+        atomicMax(&sh.maxna, sh.fl[la + 1] - sh.fl[la]);
+    }
+    int nslot;
+    const int so = block_scan_excl<kWG>(nb, sh.w, nslot);
+    if (tid < nt) sh.tslot[tid] = so;
+    if (tid == 0) sh.tslot[nt] = nslot;
+    __syncthreads();
+
+    long long e_sum = 0, w_sum = 0, p_cnt = 0;
+    uint32_t ovf = 0;
+    if (staged)
+        sweep_pairs<CAP, WMODE, F64, true>(sh, a, nf, nt, nslot, e_sum, w_sum, p_cnt, ovf);
+    else
+        sweep_pairs<CAP, WMODE, F64, false>(sh, a, nf, nt, nslot, e_sum, w_sum, p_cnt, ovf);
+
+    // energy, virial, pair count: reduce over the work-group, then one
+    // atomic per sum into a slot spread by group index (same-address global
+    // atomics from every work-group would serialise)
     e_sum = wave_sum64(e_sum);
     w_sum = wave_sum64(w_sum);
     p_cnt = wave_sum64(p_cnt);
     if (lane == 0) {
-        atomicAdd((unsigned long long *)&a.ew[0], (unsigned long long)e_sum);
-        atomicAdd((unsigned long long *)&a.ew[1], (unsigned long long)w_sum);
-        atomicAdd((unsigned long long *)&a.ew[2], (unsigned long long)p_cnt);
+        sh.red[wave][0] = e_sum;
+        sh.red[wave][1] = w_sum;
+        sh.red[wave][2] = p_cnt;
     }
     if (__ballot(ovf != 0u) && lane == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_OVERFLOW);
+    __syncthreads();
+    if (tid < 3) {
+        long long v = 0;
+        for (int k = 0; k < kNW; ++k) v += sh.red[k][tid];
+        atomicAdd((unsigned long long *)&a.part[(g % kPartSlots) * 3 + tid], (unsigned long long)v);
+    }
 
     if constexpr (WMODE != 2) {
         if (!staged) return;
-        __syncthreads();
         unsigned long long *F = (unsigned long long *)a.F;
-        for (int f = wave; f < nf; f += kNW) {
-            const int gs = s_fg[f], ls = s_fl[f], c = s_fl[f + 1] - ls;
-            for (int qq = lane; qq < c; qq += 64) {
-                for (int d = 0; d < 3; ++d) {
-                    const unsigned long long v = (unsigned long long)s_acc[d][ls + qq];
-                    if (WMODE == 0)
-                        F[d * n + gs + qq] += v;
-                    else
-                        atomicAdd(&F[d * n + gs + qq], v);
-                }
+        for (int k = tid; k < total; k += kWG) {
+            const int64_t gi = foot_gidx(sh, nf, k);
+            for (int d = 0; d < 3; ++d) {
+                const unsigned long long v = (unsigned long long)sh.acc[d][k];
+                if constexpr (WMODE == 0)
+                    F[d * n + gi] = v;
+                else
+                    atomicAdd(&F[d * n + gi], v);
             }
         }
+    }
+}
+
+// Sum the spread partial slots into out[0..ncomp): one work-group,
+// fixed order.
+__global__ __launch_bounds__(256) void k_reduce_parts(const long long *__restrict__ part,
+                                                      int ncomp, long long *__restrict__ out) {
+    __shared__ long long s_w[4];
+    for (int c = 0; c < ncomp; ++c) {
+        long long v = 0;
+        for (int k = threadIdx.x; k < kPartSlots; k += 256) v += part[k * ncomp + c];
+        v = wave_sum64(v);
+        if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) out[c] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        __syncthreads();
     }
 }
 
@@ -671,7 +799,7 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
                        lc_workspace *ws, hipStream_t st, hipEvent_t *ev = nullptr) {
     int rc = fill64((long long *)F, 3 * n, st);
     if (rc) return rc;
-    rc = fill64((long long *)ew, 3, st);
+    rc = fill64((long long *)ws->part, 3 * kPartSlots, st);
     if (rc) return rc;
     SweepArgs a;
     a.grp_task = s->grp_task;
@@ -682,23 +810,29 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     a.coord = coord;
     a.n = n;
     a.F = (long long *)F;
-    a.ew = (long long *)ew;
+    a.part = (long long *)ws->part;
     a.flags = ws->flags;
     a.pp = pair_params(g);
     // LDS tile: expected particles of the largest footprint with headroom
     const double mean = g->ncell > 0 ? (double)n / (double)g->ncell : 0.0;
-    const double need = mean * s->h.max_cells * 1.35 + 64.0;
+    const double need = mean * s->h.max_cells * 1.25;
     const int cap = need <= 1024 ? 1024 : (need <= 2048 ? 2048 : 3072);
     const int nphase = (int)s->h.phase_grp.size() - 1;
     for (int p = 0; p < nphase; ++p) {
         const int ng = s->h.phase_grp[p + 1] - s->h.phase_grp[p];
         if (ng <= 0) continue;
         a.grp_base = s->h.phase_grp[p];
+        // a phase that cannot give every CU a few work-groups splits the
+        // i loops so that each group spreads over all of its waves
+        a.ksplit = 0;
         if (ev) HIPCHK(hipEventRecord(ev[2 * p], st));
         rc = launch_sweep(cap, s->h.write_mode, precision == LC_PREC_FP64, a, ng, st);
         if (rc) return rc;
         if (ev) HIPCHK(hipEventRecord(ev[2 * p + 1], st));
     }
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (const long long *)ws->part, 3,
+                       (long long *)ew);
+    LAUNCHCHK("k_reduce_parts");
     return LC_OK;
 }
 
@@ -732,7 +866,7 @@ __global__ void k_kick_drift(double *__restrict__ pos, double *__restrict__ vel,
 __global__ __launch_bounds__(256) void k_kick_ke(double *__restrict__ vel,
                                                  const long long *__restrict__ F, int64_t n,
                                                  double hdt, int kick,
-                                                 unsigned long long *__restrict__ ke) {
+                                                 unsigned long long *__restrict__ part) {
     __shared__ long long s_w[4];
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     long long q = 0;
@@ -758,7 +892,7 @@ __global__ __launch_bounds__(256) void k_kick_ke(double *__restrict__ vel,
     __syncthreads();
     if (threadIdx.x == 0) {
         const long long t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
-        atomicAdd(ke, (unsigned long long)t);
+        atomicAdd(&part[blockIdx.x % kPartSlots], (unsigned long long)t);
     }
 }
 
@@ -850,6 +984,7 @@ extern "C" void lc_workspace_destroy(lc_workspace *ws) {
     (void)hipFree(ws->partial);
     (void)hipFree(ws->flags);
     (void)hipFree(ws->ew);
+    (void)hipFree(ws->part);
     (void)hipFree(ws->ke);
     (void)hipFree(ws->xref);
     (void)hipFree(ws->tmp3);
@@ -869,7 +1004,8 @@ extern "C" int lc_workspace_create(int64_t max_n, int64_t max_cells, lc_workspac
     const int64_t nb = (max_cells + kScanTile - 1) / kScanTile;
     if ((rc = dalloc(&ws->cid, max_n)) || (rc = dalloc(&ws->rank, max_n)) ||
         (rc = dalloc(&ws->counts, max_cells)) || (rc = dalloc(&ws->partial, nb + 1)) ||
-        (rc = dalloc(&ws->flags, 1)) || (rc = dalloc(&ws->ew, 3)) || (rc = dalloc(&ws->ke, 1)) ||
+        (rc = dalloc(&ws->flags, 1)) || (rc = dalloc(&ws->ew, 3)) ||
+        (rc = dalloc(&ws->part, 3 * kPartSlots)) || (rc = dalloc(&ws->ke, 1)) ||
         (rc = dalloc(&ws->xref, 3 * max_n)) || (rc = dalloc(&ws->tmp3, 3 * max_n)) ||
         (rc = dalloc(&ws->tmpi, max_n))) {
         lc_workspace_destroy(ws);
@@ -943,6 +1079,13 @@ extern "C" int lc_make_schedule(const lc_grid *g, int kind, const int8_t *offset
     if (hipGetDevice(&s->device) != hipSuccess) {
         delete s;
         return fail(LC_EHIP, "hipGetDevice");
+    }
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device) ==
+                hipSuccess &&
+            ncu > 0)
+            s->ncu = ncu;
     }
     auto up = [&](auto **dst, const auto &vec) -> int {
         int r = dalloc(dst, (int64_t)vec.size());
@@ -1128,17 +1271,22 @@ extern "C" int lc_compute_forces_profiled(const lc_grid *g, const lc_schedule *s
     return rc;
 }
 
-extern "C" int lc_kinetic_energy(const double *vel, int64_t n, int64_t *ke, void *stream) {
+extern "C" int lc_kinetic_energy(const double *vel, int64_t n, int64_t *ke, lc_workspace *ws,
+                                 void *stream) {
     if (!ke || (n > 0 && !vel)) return fail(LC_EINVAL, "lc_kinetic_energy: null argument");
     hipStream_t st = (hipStream_t)stream;
-    int rc = fill64((long long *)ke, 1, st);
+    if (!ws) return fail(LC_EINVAL, "lc_kinetic_energy: null workspace");
+    int rc = fill64((long long *)ws->part, kPartSlots, st);
     if (rc) return rc;
     if (n > 0) {
         hipLaunchKernelGGL(k_kick_ke, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                            (double *)vel, (const long long *)nullptr, n, 0.0, 0,
-                           (unsigned long long *)ke);
+                           (unsigned long long *)ws->part);
         LAUNCHCHK("k_kick_ke");
     }
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (const long long *)ws->part, 1,
+                       (long long *)ke);
+    LAUNCHCHK("k_reduce_parts");
     return LC_OK;
 }
 
@@ -1193,12 +1341,15 @@ extern "C" int lc_verlet_step(const lc_grid *g, const lc_schedule *s, double *po
                 return rc;
         }
         long long *row = (long long *)trace + 2 * step;
-        if ((rc = fill64(row, 1, st))) return rc;
+        if ((rc = fill64((long long *)ws->part, kPartSlots, st))) return rc;
         if (n > 0) {
             hipLaunchKernelGGL(k_kick_ke, dim3(nbk), dim3(256), 0, st, vel, (const long long *)F, n,
-                               hdt, step > 0 ? 1 : 0, (unsigned long long *)row);
+                               hdt, step > 0 ? 1 : 0, (unsigned long long *)ws->part);
             LAUNCHCHK("k_kick_ke");
         }
+        hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (const long long *)ws->part,
+                           1, row);
+        LAUNCHCHK("k_reduce_parts");
         hipLaunchKernelGGL(k_copy64, dim3(1), dim3(64), 0, st, (const long long *)ws->ew, row + 1, 1);
         LAUNCHCHK("k_copy64");
     }

@@ -290,6 +290,10 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
         for (int ph = 0; ph < nphase_col; ++ph) {
             const int col[3] = {ph % ncol[0], (ph / ncol[0]) % ncol[1],
                                 ph / (ncol[0] * ncol[1])};
+            // groups of this phase, launched largest first (longest-
+            // processing-time order: the big blocks start early and the
+            // phase tail is short)
+            std::vector<std::pair<std::vector<int32_t>, std::vector<int32_t>>> groups;
             for (int bz = 0; bz < nb[2]; ++bz)
                 for (int by = 0; by < nb[1]; ++by)
                     for (int bx = 0; bx < nb[0]; ++bx) {
@@ -309,8 +313,13 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
                                                      nc[1] * wrap(z + o.d[2], nc[2]))));
                                     }
                                 }
-                        if (!add_group(hs, A, B, err)) return LC_ECAPACITY;
+                        groups.emplace_back(std::move(A), std::move(B));
                     }
+            std::stable_sort(groups.begin(), groups.end(), [](const auto &x, const auto &y) {
+                return x.first.size() > y.first.size();
+            });
+            for (auto &gr : groups)
+                if (!add_group(hs, gr.first, gr.second, err)) return LC_ECAPACITY;
             if (kind == LC_SCHED_BLOCK8)
                 hs.phase_grp.push_back((int32_t)(hs.grp_task.size() - 1));
         }

@@ -79,7 +79,7 @@ SYMBOLS = {
     "lc_compute_forces_profiled": ([P, P, P, P, I64, P, P, INT, P, P, P, P], INT),
     "lc_verlet_step": ([P, P, P, P, P, I64, P, P, P, P, ctypes.c_double, INT,
                         INT, P, P, P], INT),
-    "lc_kinetic_energy": ([P, I64, P, P], INT),
+    "lc_kinetic_energy": ([P, I64, P, P, P], INT),
 }
 
 
@@ -338,11 +338,11 @@ def verlet_step(grid: Grid, sched: Schedule, pos, vel, ids, ws: Workspace,
     return trace, F
 
 
-def kinetic_energy(vel: torch.Tensor, out=None, stream=None):
+def kinetic_energy(vel: torch.Tensor, ws: Workspace, out=None, stream=None):
     n = vel.shape[1]
     if out is None:
         out = torch.empty(1, dtype=torch.int64, device=vel.device)
-    _chk(lib().lc_kinetic_energy(_p(vel), n, _p(out), _stream(stream)))
+    _chk(lib().lc_kinetic_energy(_p(vel), n, _p(out), ws.ptr, _stream(stream)))
     return out
 
 
