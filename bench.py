@@ -2,8 +2,9 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload fcc256k]
 
-A step is one whole force evaluation (lc_compute_forces: zero-fill of the
-int64 forces, then every phase of the conflict-free BLOCK8 schedule) over a
+A step is one whole force evaluation (lc_compute_forces under the faster of
+the two conflict-free schedules, BLOCK8 colouring or BUFFER buffer+reduce,
+picked by a short trial and named in the output) over a
 256,000-particle Lennard-Jones FCC crystal at density 0.8 with rc = 2.5 in a
 periodic cube (26^3 cells), cells prebuilt and all inputs resident in HBM.
 Prints ONE JSON line: pair interactions per second (pairs inside the cutoff
@@ -109,9 +110,18 @@ def main():
         ms = e0.elapsed_time(e1) / steps
         return s, ms, wall
 
-    # ---- the timed region: K evaluations under the conflict-free schedule
+    # ---- pick the conflict-free schedule: BLOCK8 (two-strided colouring,
+    # 8 phases) or BUFFER (buffer + reduce, one phase); short trial of each
+    trial = {}
+    for kind in ("block8", "buffer"):
+        s_, kms, _ = time_sched(kind, 5, 2)
+        trial[kind] = kms
+        s_.close()
+    best = min(trial, key=trial.get)
+
+    # ---- the timed region: K evaluations under that schedule
     ws.clear_status()
-    sched, ms, wall = time_sched("block8", args.steps, args.warmup)
+    sched, ms, wall = time_sched(best, args.steps, args.warmup)
     pairs = int(ew[2].item())
     status = ws.status()
     value = pairs / (ms * 1e-3)
@@ -144,7 +154,7 @@ def main():
         "dtype": "f32 pair math, int64 fixed-point accumulation",
         "data": "synthetic (seeded FCC lattice + uniform jitter)",
         "config": {"workload": w["desc"], "n": box.n, "cells": list(g.nc),
-                   "schedule": "block8", "pairs_in_cutoff": pairs,
+                   "schedule": best, "schedule_trial_ms": trial, "pairs_in_cutoff": pairs,
                    "candidate_pairs": ncand, "status_flags": status},
         "roofline": {
             "bound": "alu",
@@ -166,12 +176,13 @@ def main():
     # ---- baselines: same evaluation under the other schedules
     if not args.no_extra:
         extra = {}
-        for kind, st, wu in (("atomic_tile", 20, 3), ("atomic_pair", 20, 3),
-                             ("loopex", 10, 2), ("opt", 2, 1), ("lex", 1, 1)):
+        for kind, st, wu in (("block8", 20, 3), ("buffer", 20, 3), ("atomic_tile", 20, 3),
+                             ("atomic_pair", 20, 3), ("loopex", 10, 2), ("opt", 2, 1),
+                             ("lex", 1, 1)):
             s, kms, _ = time_sched(kind, st, wu)
             extra[kind] = {"ms_per_step": kms, "pairs_per_s": pairs / (kms * 1e-3),
                            "phases": s.info()["nphase"],
-                           "block8_speedup": kms / ms}
+                           "time_vs_headline": kms / ms}
             s.close()
         out["schedules"] = extra
         # the paper's serialisation degree on this grid (host computation)

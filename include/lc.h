@@ -159,7 +159,15 @@ int lc_gather(const int32_t *perm, int64_t n, const double *in3, double *out3,
                                    int64 atomics (the plain atomics baseline)*/
 #define LC_SCHED_CUSTOM 8       /* basic order with a caller-given stencil
                                    order (offsets argument)                 */
-#define LC_SCHED_COUNT 9
+#define LC_SCHED_BUFFER 9       /* Sec. VI strategy 3, buffer + reduce:
+                                   BLOCK8's groups in ONE phase; each group
+                                   stores its footprint sums (plain stores)
+                                   into its own replica slot of a partial
+                                   buffer, then a gather kernel sums the
+                                   replicas of every particle.  No colours,
+                                   no atomics; R_max x 24 B per particle of
+                                   workspace memory (grown on first use)    */
+#define LC_SCHED_COUNT 10
 
 typedef struct lc_schedule lc_schedule;
 
@@ -170,8 +178,9 @@ typedef struct lc_schedule_info {
     int64_t ngroup;   /* work-groups over all phases                        */
     int32_t max_group_tasks;
     int32_t max_group_cells;
-    int32_t write_mode; /* 0 plain RMW, 1 atomic tile, 2 atomic per pair    */
-    int32_t pad;
+    int32_t write_mode; /* 0 plain RMW, 1 atomic tile, 2 atomic per pair,
+                           3 replica buffer + gather                        */
+    int32_t max_replicas; /* LC_SCHED_BUFFER: replica slots per particle   */
 } lc_schedule_info;
 
 /* [host] Build the task list of `kind` for grid g, split it into phases
@@ -235,7 +244,9 @@ int lc_serialization_degree(const int32_t dims[3], int kind,
  *   F   [device] int64 3 x N, cell-sorted order, OVERWRITTEN with the force
  *   ew  [device] int64 [3]: OVERWRITTEN with {energy, virial, pairs in
  *       cutoff} (energy/virial in units of 2^-32)
- * Status flags (overflow, fallback) accumulate in ws. */
+ * Status flags (overflow, fallback) accumulate in ws.  LC_SCHED_BUFFER
+ * keeps its partial buffer in ws; the first call (or a larger N) allocates
+ * it with hipMalloc, later calls do not allocate. */
 int lc_compute_forces(const lc_grid *g, const lc_schedule *s,
                       const int32_t *cell_start, const uint32_t *coord,
                       int64_t n, int64_t *F, int64_t *ew, int precision,

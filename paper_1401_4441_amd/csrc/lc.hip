@@ -79,6 +79,8 @@ struct lc_workspace {
     double *xref = nullptr;      // 3N positions at the last rebuild
     double *tmp3 = nullptr;      // 3N staging for reorders
     int32_t *tmpi = nullptr;     // N staging for ids
+    long long *pbuf = nullptr;   // replica partial sums (buffer + reduce)
+    int64_t pbuf_elems = 0;
 };
 
 struct lc_schedule {
@@ -88,6 +90,7 @@ struct lc_schedule {
     lcs::HostSchedule h;
     int32_t *grp_task = nullptr, *grp_foot = nullptr, *foot_cells = nullptr;
     uint32_t *task_ab = nullptr;
+    int32_t *foot_rep = nullptr, *cell_rep = nullptr;  // buffer + reduce
 };
 
 // ---------------------------------------------------------------------------
@@ -106,6 +109,7 @@ static_assert(kMaxT <= kWG && kMaxF <= kWG, "tables scanned one item per thread"
 struct PairParams {
     float s[3];    // (float)(L * 2^-32)
     float rc2;     // (float)(rc * rc)
+    float rc2f;    // enlarged cutoff of the float candidate filter
     float ecut;    // canonical pair energy at rc2
     double sd[3];  // L * 2^-32 (exact) for the FP64 variant
     double rc2d;   // rc * rc
@@ -280,6 +284,16 @@ static int fill32(int *p, int64_t n, hipStream_t st) {
     return LC_OK;
 }
 
+template <typename T>
+static int dalloc(T **p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)count);
+    if (e != hipSuccess) return fail(LC_ENOMEM, "hipMalloc(%lld bytes): %s",
+                                     (long long)(sizeof(T) * count), hipGetErrorString(e));
+    return LC_OK;
+}
+
 // ---------------------------------------------------------------------------
 // a1: cell build
 // ---------------------------------------------------------------------------
@@ -405,9 +419,10 @@ struct SweepArgs {
     const uint32_t *coord;
     int64_t n;
     long long *F;
+    const int *foot_rep;  // replica slot per footprint entry (WMODE 3)
+    long long *pbuf;      // replica partial sums (WMODE 3), 3 x n per slot
     long long *part;  // kPartSlots x 3 partial {energy, virial, pairs}
     uint32_t *flags;
-    int ksplit;       // i-range per work unit (0: whole range), see sweep_pairs
     PairParams pp;
 };
 
@@ -460,10 +475,12 @@ __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, 
     return true;
 }
 
-// Shared memory of one sweep work-group.
-template <int CAP, int WMODE>
+// Shared memory of one sweep work-group.  FF: the tile also holds float
+// coordinates relative to the group origin for the candidate filter.
+template <int CAP, int WMODE, bool FF>
 struct SweepLDS {
     uint4 u[CAP];                                           // box fractions
+    float4 f[FF ? CAP : 1];                                 // filter coordinates
     long long acc[WMODE == 2 ? 1 : 3][WMODE == 2 ? 1 : CAP];  // int64 forces
     int fg[kMaxF];          // global first slot of each footprint cell
     int fl[kMaxF + 1];      // local first slot (prefix over the footprint)
@@ -473,10 +490,9 @@ struct SweepLDS {
     uint32_t q[kNW][kQ];    // per-wave queue of in-cutoff pairs (i | j << 16)
     long long red[kNW][3];
     int w[kNW + 1];
-    int maxna;              // largest cell A over the group's tasks
 };
 
-// Global slot of a local footprint index (fallback path).
+// Global slot of a local footprint index.
 template <class L>
 __device__ __forceinline__ int64_t foot_gidx(const L &sh, int nf, int l) {
     int lo = 0, hi = nf;
@@ -487,14 +503,32 @@ __device__ __forceinline__ int64_t foot_gidx(const L &sh, int nf, int l) {
     return (int64_t)sh.fg[lo] + (l - sh.fl[lo]);
 }
 
-// The candidate loop and pair evaluation of one work-group.  STAGED: the
-// footprint's box fractions and accumulators live in LDS; otherwise box
-// fractions come from global memory and every pair adds into F with global
-// atomics.
-template <int CAP, int WMODE, bool F64, bool STAGED>
-__device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE> &sh, const SweepArgs &a, int nf,
-                                            int nt, int nslot, long long &e_sum, long long &w_sum,
-                                            long long &p_cnt, uint32_t &ovf) {
+// Footprint cell (local index) holding a local particle index.
+template <class L>
+__device__ __forceinline__ int foot_cell(const L &sh, int nf, int l) {
+    int lo = 0, hi = nf;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sh.fl[mid] <= l) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// The candidate loop and pair evaluation of one work-group.
+//   STAGED: the footprint's box fractions and accumulators live in LDS;
+//           otherwise box fractions come from global memory and every pair
+//           adds into F with global atomics.
+//   FF:     the candidate test uses the float tile (group-relative
+//           coordinates) against a slightly enlarged cutoff; the exact
+//           canonical test is repeated when the pair is evaluated.
+// Lanes own j slots (64 consecutive slots of the concatenated B cells of the
+// group's tasks) and loop over the i particles of their task's cell A;
+// pairs inside the cutoff are compacted into a per-wave queue and evaluated
+// 64 at a time, so the Lennard-Jones arithmetic runs on full waves.
+template <int CAP, int WMODE, bool F64, bool STAGED, bool FF>
+__device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const SweepArgs &a,
+                                            int nf, int nt, int nslot, long long &e_sum,
+                                            long long &w_sum, long long &p_cnt, uint32_t &ovf) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t n = a.n;
     const PairParams pp = a.pp;
@@ -531,26 +565,50 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE> &sh, const Swee
             atomicAdd((unsigned long long *)&sh.acc[1][jl], (unsigned long long)qy);
             atomicAdd((unsigned long long *)&sh.acc[2][jl], (unsigned long long)qz);
         } else {
-            const int64_t gi = foot_gidx(sh, nf, il), gj = foot_gidx(sh, nf, jl);
-            unsigned long long *F = (unsigned long long *)a.F;
-            atomicAdd(&F[gi], (unsigned long long)(-qx));
-            atomicAdd(&F[n + gi], (unsigned long long)(-qy));
-            atomicAdd(&F[2 * n + gi], (unsigned long long)(-qz));
-            atomicAdd(&F[gj], (unsigned long long)qx);
-            atomicAdd(&F[n + gj], (unsigned long long)qy);
-            atomicAdd(&F[2 * n + gj], (unsigned long long)qz);
+            // global path: into F, or (buffer + reduce) into this group's
+            // replica slots, which no other group writes
+            int64_t gi = foot_gidx(sh, nf, il), gj = foot_gidx(sh, nf, jl);
+            unsigned long long *Fi = (unsigned long long *)a.F, *Fj = Fi;
+            if constexpr (WMODE == 3) {
+                const int f0 = a.grp_foot[a.grp_base + blockIdx.x];
+                const int ri = a.foot_rep[f0 + foot_cell(sh, nf, il)];
+                const int rj = a.foot_rep[f0 + foot_cell(sh, nf, jl)];
+                Fi = (unsigned long long *)a.pbuf + (int64_t)ri * 3 * n;
+                Fj = (unsigned long long *)a.pbuf + (int64_t)rj * 3 * n;
+            }
+            atomicAdd(&Fi[gi], (unsigned long long)(-qx));
+            atomicAdd(&Fi[n + gi], (unsigned long long)(-qy));
+            atomicAdd(&Fi[2 * n + gi], (unsigned long long)(-qz));
+            atomicAdd(&Fj[gj], (unsigned long long)qx);
+            atomicAdd(&Fj[n + gj], (unsigned long long)qy);
+            atomicAdd(&Fj[2 * n + gj], (unsigned long long)qz);
         }
     };
 
-    // Work units: a chunk of 64 consecutive j slots, and (when ksplit > 0)
-    // a sub-range of ksplit steps of its i loop, so that a group with few
-    // chunks still spreads over all of its waves.
-    const int nchunk = (nslot + 63) >> 6;
-    const int nsub = a.ksplit > 0 ? max(1, (sh.maxna + a.ksplit - 1) / a.ksplit) : 1;
-    const int nunit = nchunk * nsub;
-    for (int unit = wave; unit < nunit; unit += kNW) {
-        const int chunk = unit / nsub, sub = unit - chunk * nsub;
-        const int base = chunk * 64;
+    // queue an in-cutoff pair; evaluate 64 at a time
+    auto push = [&](bool in, int il, uint32_t jbits) {
+        const unsigned long long m = __ballot(in);
+        if (in) {
+            const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            q[qn + below] = (uint32_t)il | jbits;
+        }
+        qn = __builtin_amdgcn_readfirstlane(qn + (int)__popcll(m));
+        if (qn >= 64) {
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            eval(q[lane]);
+            const uint32_t rest = lane + 64 < qn ? q[lane + 64] : 0u;
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            if (lane + 64 < qn) q[lane] = rest;
+            qn -= 64;
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        }
+    };
+
+    for (int base = wave * 64; base < nslot; base += kNW * 64) {
         const int s = base + lane;
         const bool valid = s < nslot;
         int lo = 0, hi = nt;
@@ -563,55 +621,41 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE> &sh, const Swee
         const int bo = sh.tb[t];
         const bool intra = bo < 0;
         const int jl = (bo & 0x7fffffff) + jj;
+        const uint32_t jbits = (uint32_t)jl << 16;
         const int ta = sh.ta[t];
         const int aoff = ta & 0xffff;
-        const int na = valid ? (ta >> 16) : 0;
-        uint4 uj = make_uint4(0u, 0u, 0u, 0u);
-        if (valid) uj = load_u(jl);
-        // diagonal order: lane jj visits i = (k + jj) mod na, so the lanes of
-        // one task touch different i at each step (spreads the i-side LDS
-        // atomics); intra tasks keep each unordered pair once via i < j
-        const int kmax0 = wave_max32(na);
-        const int kbeg = nsub > 1 ? sub * a.ksplit : 0;
-        const int kmax = nsub > 1 ? min(kmax0, kbeg + a.ksplit) : kmax0;
-        int ik = na > 0 ? (jj + kbeg) % na : 0;
-        // software pipeline: the box fraction of the next i is loaded while
-        // the current one is tested (the load index is clamped so it is
-        // always inside the staged footprint)
-        auto i_of = [&](int kk) { return aoff + kk; };
-        uint4 ui_next = make_uint4(0u, 0u, 0u, 0u);
-        if constexpr (STAGED) ui_next = sh.u[min(i_of(ik), CAP - 1)];
-        for (int k = kbeg; k < kmax; ++k) {
-            const bool act = k < na && (!intra || ik < jj);
-            const int il = i_of(ik);
-            const int ik_next = ik + 1 == na ? 0 : ik + 1;
-            uint4 ui;
-            if constexpr (STAGED) {
-                ui = ui_next;
-                ui_next = sh.u[min(i_of(ik_next), CAP - 1)];
-            } else {
-                ui = act ? load_u(il) : make_uint4(0u, 0u, 0u, 0u);
+        // i runs over cell A; an intra task keeps each unordered pair once
+        // (i before j inside the cell)
+        if constexpr (STAGED && FF) {
+            const int kend = valid ? (intra ? jj : (ta >> 16)) : 0;
+            const int kmax = wave_max32(kend);
+            const float4 fj = valid ? sh.f[jl] : make_float4(0.f, 0.f, 0.f, 0.f);
+            float4 fn = sh.f[min(aoff, CAP - 1)];
+            for (int k = 0; k < kmax; ++k) {
+                const float4 fi = fn;
+                fn = sh.f[min(aoff + k + 1, CAP - 1)];
+                const float dx = fj.x - fi.x, dy = fj.y - fi.y, dz = fj.z - fi.z;
+                float r2 = dx * dx + dy * dy;
+                r2 = r2 + dz * dz;
+                push(k < kend && r2 < pp.rc2f, aoff + k, jbits);
             }
-            const bool in = act && canon_r2(ui.x, ui.y, ui.z, uj.x, uj.y, uj.z, pp) < pp.rc2;
-            ik = ik_next;
-            const unsigned long long m = __ballot(in);
-            if (in) {
-                const int below = (int)__builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                q[qn + below] = (uint32_t)il | ((uint32_t)jl << 16);
-            }
-            qn += (int)__popcll(m);
-            if (qn >= 64) {
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                eval(q[lane]);
-                const uint32_t rest = lane + 64 < qn ? q[lane + 64] : 0u;
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                if (lane + 64 < qn) q[lane] = rest;
-                qn -= 64;
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        } else {
+            // diagonal order: lane jj visits i = (k + jj) mod na, so lanes of
+            // one task touch different i at each step (spreads the i-side
+            // atomics); an intra task keeps a pair when i < j
+            const uint4 uj = valid ? load_u(jl) : make_uint4(0u, 0u, 0u, 0u);
+            const int na = valid ? (ta >> 16) : 0;
+            const int kdiag = wave_max32(na);
+            int ik = na > 0 ? jj % na : 0;
+            for (int k = 0; k < kdiag; ++k) {
+                const bool act = k < na && (!intra || ik < jj);
+                bool in = false;
+                if (act) {
+                    const uint4 ui = load_u(aoff + ik);
+                    in = canon_r2(ui.x, ui.y, ui.z, uj.x, uj.y, uj.z, pp) < pp.rc2;
+                }
+                push(in, aoff + ik, jbits);
+                ik = ik + 1 == na ? 0 : ik + 1;
             }
         }
     }
@@ -625,9 +669,9 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE> &sh, const Swee
 //        (the phase must be conflict-free); 1 = accumulate in LDS, global
 //        atomic write-back; 2 = every pair adds into global memory with
 //        atomics.
-template <int CAP, int WMODE, bool F64>
+template <int CAP, int WMODE, bool F64, bool FF>
 __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
-    __shared__ SweepLDS<CAP, WMODE> sh;
+    __shared__ SweepLDS<CAP, WMODE, FF> sh;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = a.grp_base + blockIdx.x;
     const int t0 = a.grp_task[g], nt = a.grp_task[g + 1] - t0;
@@ -661,6 +705,13 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
     // start from the current forces, which no other work-group of this phase
     // touches, so the write-back below is a plain store.
     if (staged) {
+        uint32_t ox = 0, oy = 0, oz = 0;
+        if constexpr (FF) {  // group origin: the first particle of the footprint
+            const int64_t g0 = sh.fg[0];
+            ox = a.coord[g0];
+            oy = a.coord[n + g0];
+            oz = a.coord[2 * n + g0];
+        }
         for (int k = tid; k < total; k += kWG) {
             const int64_t gi = foot_gidx(sh, nf, k);
             const uint32_t ux = a.coord[gi], uy = a.coord[n + gi], uz = a.coord[2 * n + gi];
@@ -669,25 +720,37 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
                 sh.acc[0][k] = fx;
                 sh.acc[1][k] = fy;
                 sh.acc[2][k] = fz;
-            } else if constexpr (WMODE == 1) {
+            } else if constexpr (WMODE == 1 || WMODE == 3) {
                 sh.acc[0][k] = 0;
                 sh.acc[1][k] = 0;
                 sh.acc[2][k] = 0;
             }
             sh.u[k] = make_uint4(ux, uy, uz, 0u);
+            if constexpr (FF)
+                sh.f[k] = make_float4(canon_d(ux, ox, a.pp.s[0]), canon_d(uy, oy, a.pp.s[1]),
+                                      canon_d(uz, oz, a.pp.s[2]), 0.f);
+        }
+    }
+    if constexpr (WMODE == 3) {
+        if (!staged) {  // the global path accumulates into the replica slots
+            for (int k = tid; k < total; k += kWG) {
+                const int f = foot_cell(sh, nf, k);
+                const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
+                long long *P = a.pbuf + (int64_t)a.foot_rep[f0 + f] * 3 * n;
+                P[gi] = 0;
+                P[n + gi] = 0;
+                P[2 * n + gi] = 0;
+            }
+            __syncthreads();
         }
     }
     // task table
-    if (tid == 0) sh.maxna = 0;
-    __syncthreads();
     int nb = 0;
     if (tid < nt) {
-        const uint32_t ab = my_ab;
-        const int la = (int)(ab & 0xffffu), lb = (int)(ab >> 16);
+        const int la = (int)(my_ab & 0xffffu), lb = (int)(my_ab >> 16);
         sh.ta[tid] = sh.fl[la] | ((sh.fl[la + 1] - sh.fl[la]) << 16);
         sh.tb[tid] = sh.fl[lb] | (la == lb ? (int)0x80000000 : 0);
         nb = sh.fl[lb + 1] - sh.fl[lb];
-        atomicMax(&sh.maxna, sh.fl[la + 1] - sh.fl[la]);
     }
     int nslot;
     const int so = block_scan_excl<kWG>(nb, sh.w, nslot);
@@ -698,9 +761,9 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
     long long e_sum = 0, w_sum = 0, p_cnt = 0;
     uint32_t ovf = 0;
     if (staged)
-        sweep_pairs<CAP, WMODE, F64, true>(sh, a, nf, nt, nslot, e_sum, w_sum, p_cnt, ovf);
+        sweep_pairs<CAP, WMODE, F64, true, FF>(sh, a, nf, nt, nslot, e_sum, w_sum, p_cnt, ovf);
     else
-        sweep_pairs<CAP, WMODE, F64, false>(sh, a, nf, nt, nslot, e_sum, w_sum, p_cnt, ovf);
+        sweep_pairs<CAP, WMODE, F64, false, FF>(sh, a, nf, nt, nslot, e_sum, w_sum, p_cnt, ovf);
 
     // energy, virial, pair count: reduce over the work-group, then one
     // atomic per sum into a slot spread by group index (same-address global
@@ -721,7 +784,17 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
         atomicAdd((unsigned long long *)&a.part[(g % kPartSlots) * 3 + tid], (unsigned long long)v);
     }
 
-    if constexpr (WMODE != 2) {
+    if constexpr (WMODE == 3) {
+        if (!staged) return;
+        for (int k = tid; k < total; k += kWG) {
+            const int f = foot_cell(sh, nf, k);
+            const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
+            long long *P = a.pbuf + (int64_t)a.foot_rep[f0 + f] * 3 * n;
+            P[gi] = sh.acc[0][k];
+            P[n + gi] = sh.acc[1][k];
+            P[2 * n + gi] = sh.acc[2][k];
+        }
+    } else if constexpr (WMODE != 2) {
         if (!staged) return;
         unsigned long long *F = (unsigned long long *)a.F;
         for (int k = tid; k < total; k += kWG) {
@@ -735,6 +808,31 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
             }
         }
     }
+}
+
+// Buffer + reduce: F of every particle = sum of its cell's replica slots.
+__global__ void k_gather_partials(const long long *__restrict__ pbuf,
+                                  const int *__restrict__ cell_rep,
+                                  const int *__restrict__ cell_start, int ncell, int64_t n,
+                                  long long *__restrict__ F) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int lo = 0, hi = ncell;  // cell_start[lo] <= p < cell_start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cell_start[mid] <= p) lo = mid; else hi = mid;
+    }
+    const int R = cell_rep[lo];
+    long long fx = 0, fy = 0, fz = 0;
+    for (int r = 0; r < R; ++r) {
+        const long long *P = pbuf + (int64_t)r * 3 * n;
+        fx += P[p];
+        fy += P[n + p];
+        fz += P[2 * n + p];
+    }
+    F[p] = fx;
+    F[n + p] = fy;
+    F[2 * n + p] = fz;
 }
 
 // Sum the spread partial slots into out[0..ncomp): one work-group,
@@ -753,30 +851,44 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const long long *__restric
     }
 }
 
-template <int CAP, int WMODE, bool F64>
+template <int CAP, int WMODE, bool F64, bool FF>
 static int launch_sweep_t(const SweepArgs &a, int ngroups, hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep<CAP, WMODE, F64>), dim3(ngroups), dim3(kWG), 0, st, a);
+    hipLaunchKernelGGL((k_sweep<CAP, WMODE, F64, FF>), dim3(ngroups), dim3(kWG), 0, st, a);
     LAUNCHCHK("k_sweep");
     return LC_OK;
 }
 
-template <int WMODE, bool F64>
+// LDS tile capacities (particles): with the float filter tile {768, 1024,
+// 2048}, without {1024, 2048, 3072}.
+template <int WMODE, bool F64, bool FF>
 static int launch_sweep_c(int cap, const SweepArgs &a, int ngroups, hipStream_t st) {
-    if (cap <= 1024) return launch_sweep_t<1024, WMODE, F64>(a, ngroups, st);
-    if (cap <= 2048) return launch_sweep_t<2048, WMODE, F64>(a, ngroups, st);
-    return launch_sweep_t<3072, WMODE, F64>(a, ngroups, st);
+    if constexpr (FF) {
+        if (cap <= 768) return launch_sweep_t<768, WMODE, F64, true>(a, ngroups, st);
+        if (cap <= 1024) return launch_sweep_t<1024, WMODE, F64, true>(a, ngroups, st);
+        return launch_sweep_t<2048, WMODE, F64, true>(a, ngroups, st);
+    } else {
+        if (cap <= 1024) return launch_sweep_t<1024, WMODE, F64, false>(a, ngroups, st);
+        if (cap <= 2048) return launch_sweep_t<2048, WMODE, F64, false>(a, ngroups, st);
+        return launch_sweep_t<3072, WMODE, F64, false>(a, ngroups, st);
+    }
 }
 
-static int launch_sweep(int cap, int wmode, bool f64, const SweepArgs &a, int ngroups,
+static int launch_sweep(int cap, int wmode, bool f64, bool ff, const SweepArgs &a, int ngroups,
                         hipStream_t st) {
     if (f64) {
-        if (wmode == 0) return launch_sweep_c<0, true>(cap, a, ngroups, st);
-        if (wmode == 1) return launch_sweep_c<1, true>(cap, a, ngroups, st);
-        return launch_sweep_c<2, true>(cap, a, ngroups, st);
+        if (wmode == 0) return launch_sweep_c<0, true, false>(cap, a, ngroups, st);
+        if (wmode == 1) return launch_sweep_c<1, true, false>(cap, a, ngroups, st);
+        if (wmode == 3) return launch_sweep_c<3, true, false>(cap, a, ngroups, st);
+        return launch_sweep_c<2, true, false>(cap, a, ngroups, st);
     }
-    if (wmode == 0) return launch_sweep_c<0, false>(cap, a, ngroups, st);
-    if (wmode == 1) return launch_sweep_c<1, false>(cap, a, ngroups, st);
-    return launch_sweep_c<2, false>(cap, a, ngroups, st);
+    if (ff) {
+        if (wmode == 0) return launch_sweep_c<0, false, true>(cap, a, ngroups, st);
+        if (wmode == 3) return launch_sweep_c<3, false, true>(cap, a, ngroups, st);
+    }
+    if (wmode == 0) return launch_sweep_c<0, false, false>(cap, a, ngroups, st);
+    if (wmode == 1) return launch_sweep_c<1, false, false>(cap, a, ngroups, st);
+    if (wmode == 3) return launch_sweep_c<3, false, false>(cap, a, ngroups, st);
+    return launch_sweep_c<2, false, false>(cap, a, ngroups, st);
 }
 
 static PairParams pair_params(const lc_grid *g) {
@@ -786,6 +898,11 @@ static PairParams pair_params(const lc_grid *g) {
         p.sd[d] = g->box[d] / 4294967296.0;
     }
     p.rc2 = g->rc2;
+    // The float filter's r^2 differs from the canonical one by a few 1e-6
+    // of rc^2 (group-relative coordinates up to ~10 cells carry ~1e-6
+    // absolute rounding); 1e-4 relative headroom keeps every pair the
+    // canonical test accepts.
+    p.rc2f = (float)((double)g->rc2 * (1.0 + 1e-4));
     p.ecut = g->ecut;
     p.rc2d = g->rc * g->rc;
     const double ic = 1.0 / p.rc2d;
@@ -797,8 +914,19 @@ static PairParams pair_params(const lc_grid *g) {
 static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *cell_start,
                        const uint32_t *coord, int64_t n, int64_t *F, int64_t *ew, int precision,
                        lc_workspace *ws, hipStream_t st, hipEvent_t *ev = nullptr) {
-    int rc = fill64((long long *)F, 3 * n, st);
+    const bool buffered = s->h.write_mode == 3;
+    int rc = buffered ? LC_OK : fill64((long long *)F, 3 * n, st);
     if (rc) return rc;
+    if (buffered) {
+        const int64_t need = (int64_t)s->h.rmax * 3 * n;
+        if (need > ws->pbuf_elems) {  // grown once, reused afterwards
+            (void)hipFree(ws->pbuf);
+            ws->pbuf = nullptr;
+            ws->pbuf_elems = 0;
+            if ((rc = dalloc(&ws->pbuf, need))) return rc;
+            ws->pbuf_elems = need;
+        }
+    }
     rc = fill64((long long *)ws->part, 3 * kPartSlots, st);
     if (rc) return rc;
     SweepArgs a;
@@ -810,25 +938,37 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     a.coord = coord;
     a.n = n;
     a.F = (long long *)F;
+    a.foot_rep = s->foot_rep;
+    a.pbuf = ws->pbuf;
     a.part = (long long *)ws->part;
     a.flags = ws->flags;
     a.pp = pair_params(g);
     // LDS tile: expected particles of the largest footprint with headroom
     const double mean = g->ncell > 0 ? (double)n / (double)g->ncell : 0.0;
-    const double need = mean * s->h.max_cells * 1.25;
-    const int cap = need <= 1024 ? 1024 : (need <= 2048 ? 2048 : 3072);
+    const bool ff = s->h.compact && precision == LC_PREC_FP32 &&
+                    (s->h.write_mode == 0 || s->h.write_mode == 3);
+    const double need = mean * s->h.max_cells * 1.35;
+    int cap;
+    if (ff)
+        cap = need <= 768 ? 768 : (need <= 1024 ? 1024 : 2048);
+    else
+        cap = need <= 1024 ? 1024 : (need <= 2048 ? 2048 : 3072);
     const int nphase = (int)s->h.phase_grp.size() - 1;
     for (int p = 0; p < nphase; ++p) {
         const int ng = s->h.phase_grp[p + 1] - s->h.phase_grp[p];
         if (ng <= 0) continue;
         a.grp_base = s->h.phase_grp[p];
-        // a phase that cannot give every CU a few work-groups splits the
-        // i loops so that each group spreads over all of its waves
-        a.ksplit = 0;
         if (ev) HIPCHK(hipEventRecord(ev[2 * p], st));
-        rc = launch_sweep(cap, s->h.write_mode, precision == LC_PREC_FP64, a, ng, st);
+        rc = launch_sweep(cap, s->h.write_mode, precision == LC_PREC_FP64, ff && need <= 2048, a,
+                          ng, st);
         if (rc) return rc;
         if (ev) HIPCHK(hipEventRecord(ev[2 * p + 1], st));
+    }
+    if (buffered && n > 0) {
+        hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                           (const long long *)ws->pbuf, (const int *)s->cell_rep, cell_start,
+                           g->ncell, n, (long long *)F);
+        LAUNCHCHK("k_gather_partials");
     }
     hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (const long long *)ws->part, 3,
                        (long long *)ew);
@@ -963,15 +1103,6 @@ extern "C" int lc_make_grid(const double box[3], double rc, double skin, int fla
     return LC_OK;
 }
 
-template <typename T>
-static int dalloc(T **p, int64_t count) {
-    *p = nullptr;
-    if (count <= 0) count = 1;
-    hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)count);
-    if (e != hipSuccess) return fail(LC_ENOMEM, "hipMalloc(%lld bytes): %s",
-                                     (long long)(sizeof(T) * count), hipGetErrorString(e));
-    return LC_OK;
-}
 
 extern "C" void lc_workspace_destroy(lc_workspace *ws) {
     if (!ws) return;
@@ -989,6 +1120,7 @@ extern "C" void lc_workspace_destroy(lc_workspace *ws) {
     (void)hipFree(ws->xref);
     (void)hipFree(ws->tmp3);
     (void)hipFree(ws->tmpi);
+    (void)hipFree(ws->pbuf);
     (void)hipSetDevice(cur);
     delete ws;
 }
@@ -1096,7 +1228,8 @@ extern "C" int lc_make_schedule(const lc_grid *g, int kind, const int8_t *offset
         return LC_OK;
     };
     if ((rc = up(&s->grp_task, s->h.grp_task)) || (rc = up(&s->grp_foot, s->h.grp_foot)) ||
-        (rc = up(&s->foot_cells, s->h.foot_cells)) || (rc = up(&s->task_ab, s->h.task_ab))) {
+        (rc = up(&s->foot_cells, s->h.foot_cells)) || (rc = up(&s->task_ab, s->h.task_ab)) ||
+        (rc = up(&s->foot_rep, s->h.foot_rep)) || (rc = up(&s->cell_rep, s->h.cell_rep))) {
         lc_schedule_free(s);
         return rc;
     }
@@ -1113,6 +1246,8 @@ extern "C" void lc_schedule_free(lc_schedule *s) {
     (void)hipFree(s->grp_foot);
     (void)hipFree(s->foot_cells);
     (void)hipFree(s->task_ab);
+    (void)hipFree(s->foot_rep);
+    (void)hipFree(s->cell_rep);
     (void)hipSetDevice(cur);
     delete s;
 }
@@ -1127,6 +1262,7 @@ extern "C" int lc_schedule_info_get(const lc_schedule *s, lc_schedule_info *out)
     out->max_group_tasks = s->h.max_tasks;
     out->max_group_cells = s->h.max_cells;
     out->write_mode = s->h.write_mode;
+    out->max_replicas = s->h.rmax;
     return LC_OK;
 }
 
@@ -1147,6 +1283,7 @@ extern "C" int lc_schedule_plan(const lc_grid *g, int kind, const int8_t *offset
     out->max_group_tasks = h.max_tasks;
     out->max_group_cells = h.max_cells;
     out->write_mode = h.write_mode;
+    out->max_replicas = h.rmax;
     return LC_OK;
 }
 

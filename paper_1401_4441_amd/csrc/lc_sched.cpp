@@ -115,6 +115,7 @@ bool stencil_order(int kind, bool two_d, const int8_t *offsets, int n,
         case LC_SCHED_BLOCK8:
         case LC_SCHED_ATOMIC_TILE:
         case LC_SCHED_ATOMIC_PAIR:
+        case LC_SCHED_BUFFER:
             order.push_back(intra);
             for (auto &o : h) order.push_back(o);
             return true;
@@ -279,13 +280,24 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
     std::vector<Offset> order;
     if (!stencil_order(kind, false, offsets, n, order, err)) return LC_EINVAL;
 
-    if (kind == LC_SCHED_BLOCK8 || kind == LC_SCHED_ATOMIC_TILE) {
-        hs.write_mode = kind == LC_SCHED_BLOCK8 ? 0 : 1;
+    if (kind == LC_SCHED_BLOCK8 || kind == LC_SCHED_ATOMIC_TILE || kind == LC_SCHED_BUFFER) {
+        hs.write_mode = kind == LC_SCHED_BLOCK8 ? 0 : (kind == LC_SCHED_ATOMIC_TILE ? 1 : 3);
         std::vector<int> bs[3];
         for (int d = 0; d < 3; ++d) bs[d] = axis_blocks(nc[d], d == 0 ? 1 : 2);
         const int nb[3] = {(int)bs[0].size() - 1, (int)bs[1].size() - 1,
                            (int)bs[2].size() - 1};
         const int ncol[3] = {nb[0] > 1 ? 2 : 1, nb[1] > 1 ? 2 : 1, nb[2] > 1 ? 2 : 1};
+        {
+            // footprint extent per axis: the largest block plus the stencil
+            // reach (1 cell along +x, 1 on each side along y and z)
+            hs.compact = true;
+            for (int d = 0; d < 3; ++d) {
+                int big = 0;
+                for (int b = 0; b < nb[d]; ++b) big = std::max(big, bs[d][b + 1] - bs[d][b]);
+                const int extent = big + (d == 0 ? 1 : 2);
+                if (2 * extent >= nc[d]) hs.compact = false;
+            }
+        }
         const int nphase_col = ncol[0] * ncol[1] * ncol[2];
         for (int ph = 0; ph < nphase_col; ++ph) {
             const int col[3] = {ph % ncol[0], (ph / ncol[0]) % ncol[1],
@@ -323,13 +335,25 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
             if (kind == LC_SCHED_BLOCK8)
                 hs.phase_grp.push_back((int32_t)(hs.grp_task.size() - 1));
         }
-        if (kind == LC_SCHED_ATOMIC_TILE)
+        if (kind != LC_SCHED_BLOCK8)
             hs.phase_grp.push_back((int32_t)(hs.grp_task.size() - 1));
+        if (kind == LC_SCHED_BUFFER) {
+            // replica slot r of (group, cell): the r-th group whose footprint
+            // holds the cell writes slot r of its particles
+            hs.cell_rep.assign((size_t)ncell, 0);
+            hs.foot_rep.resize(hs.foot_cells.size());
+            for (size_t k = 0; k < hs.foot_cells.size(); ++k) {
+                hs.foot_rep[k] = hs.cell_rep[(size_t)hs.foot_cells[k]]++;
+                hs.rmax = std::max(hs.rmax, hs.cell_rep[(size_t)hs.foot_cells[k]]);
+            }
+        }
         return LC_OK;
     }
 
     if (kind == LC_SCHED_ATOMIC_PAIR) {
         hs.write_mode = 2;
+        // footprint of a home cell: 2 cells along x, 3 along y and z
+        hs.compact = 2 * 2 < nc[0] && 2 * 3 < nc[1] && 2 * 3 < nc[2];
         std::vector<int32_t> A, B;
         basic_tasks(nc, order, A, B);
         const size_t per = order.size();

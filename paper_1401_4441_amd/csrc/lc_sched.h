@@ -61,6 +61,14 @@ struct HostSchedule {
     int64_t ntask = 0;
     int max_tasks = 0;
     int max_cells = 0;
+    // every group's footprint spans less than half the box along each axis
+    // (group-relative float coordinates then reproduce minimum images)
+    bool compact = false;
+    // buffer + reduce: replica slot of every footprint entry (parallel to
+    // foot_cells), replica count per cell, and its maximum
+    std::vector<int32_t> foot_rep;
+    std::vector<int32_t> cell_rep;
+    int rmax = 0;
 };
 
 constexpr int kMaxGroupTasks = 512;

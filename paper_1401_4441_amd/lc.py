@@ -17,10 +17,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblc.so")
 
 # schedule kinds (LC_SCHED_*)
-LEX, OPT, BEST, BAD, LOOPEX, BLOCK8, ATOMIC_TILE, ATOMIC_PAIR, CUSTOM = range(9)
+LEX, OPT, BEST, BAD, LOOPEX, BLOCK8, ATOMIC_TILE, ATOMIC_PAIR, CUSTOM, BUFFER = range(10)
 KINDS = {"lex": LEX, "opt": OPT, "best": BEST, "bad": BAD, "loopex": LOOPEX,
          "block8": BLOCK8, "atomic_tile": ATOMIC_TILE, "atomic_pair": ATOMIC_PAIR,
-         "custom": CUSTOM}
+         "custom": CUSTOM, "buffer": BUFFER}
 PREC = {"fp32": 0, "fp64": 1}
 FLAG_OVERFLOW, FLAG_DISP, FLAG_FALLBACK = 1, 2, 4
 SCALE = 2.0 ** 32
@@ -45,7 +45,7 @@ class _SchedInfo(ctypes.Structure):
                 ("ntask", ctypes.c_int64), ("ngroup", ctypes.c_int64),
                 ("max_group_tasks", ctypes.c_int32),
                 ("max_group_cells", ctypes.c_int32),
-                ("write_mode", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("write_mode", ctypes.c_int32), ("max_replicas", ctypes.c_int32)]
 
 
 class _SD(ctypes.Structure):

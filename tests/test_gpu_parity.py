@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 lc = pytest.importorskip("paper_1401_4441_amd.lc")
 
 DEV = torch.device("cuda:0")
-KINDS = ["block8", "atomic_tile", "atomic_pair", "loopex", "opt", "lex"]
+KINDS = ["block8", "buffer", "atomic_tile", "atomic_pair", "loopex", "opt", "lex"]
 
 
 def _say(*a):
@@ -117,7 +117,7 @@ def test_c2_full_size_all_schedules():
     S = Setup(box, even=True)
     _say("fcc256k nc", S.g.nc)
     Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
-    for kind in ["block8", "atomic_tile", "atomic_pair", "loopex", "lex"]:
+    for kind in ["block8", "buffer", "atomic_tile", "atomic_pair", "loopex", "lex"]:
         _say("  fcc256k", kind)
         F, ew, st = S.forces(kind)
         assert (F == Fo).all(), kind
@@ -132,7 +132,7 @@ def test_ragged_and_vacancies():
         S = Setup(box)
         _say("ragged", n, rho, S.g.nc)
         Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
-        for kind in ("block8", "atomic_pair", "opt"):
+        for kind in ("block8", "buffer", "atomic_pair", "opt"):
             F, ew, _ = S.forces(kind)
             assert (F == Fo).all() and ew == [Eo, Wo, npo], (n, kind)
 
@@ -146,7 +146,7 @@ def test_minimum_grid_and_empty_cells():
         S = Setup(box)
         _say("small", box.n, S.g.nc)
         Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
-        for kind in ("block8", "atomic_tile", "atomic_pair", "lex"):
+        for kind in ("block8", "buffer", "atomic_tile", "atomic_pair", "lex"):
             F, ew, _ = S.forces(kind)
             assert (F == Fo).all() and ew == [Eo, Wo, npo], kind
 
@@ -158,7 +158,7 @@ def test_lds_overflow_falls_back_exactly():
     S = Setup(box)
     _say("fallback nc", S.g.nc)
     Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
-    for kind in ("block8", "atomic_tile"):
+    for kind in ("block8", "buffer", "atomic_tile"):
         F, ew, st = S.forces(kind)
         assert st & lc.FLAG_FALLBACK
         assert (F == Fo).all() and ew == [Eo, Wo, npo], kind

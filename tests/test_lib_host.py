@@ -102,7 +102,7 @@ def test_custom_order_rejects_non_half_shell():
                                 offsets=[O.INTRA, (1, 0, 0), (-1, 0, 0), (1, 1, 0), (0, 1, 0)])
 
 
-@pytest.mark.parametrize("kind,nphase", [("loopex", 27), ("block8", 8),
+@pytest.mark.parametrize("kind,nphase", [("loopex", 27), ("block8", 8), ("buffer", 1),
                                          ("atomic_tile", 1), ("atomic_pair", 1)])
 def test_schedule_plan_shapes(kind, nphase):
     g = lc.Grid((68.399,) * 3, 2.5, even=True)
