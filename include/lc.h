@@ -290,6 +290,73 @@ int lc_verlet_step(const lc_grid *g, const lc_schedule *s, double *pos,
 int lc_kinetic_energy(const double *vel, int64_t n, int64_t *ke,
                       lc_workspace *ws, void *stream);
 
+/* ---- a8: batched independent boxes -------------------------------------- */
+
+/* One periodic box of a batch: its grid (lc_make_grid) and particle count.
+ * In the batch's packed arrays box b owns the particles [pstart_b, pstart_b
+ * + n_b) and the cells [cstart_b, cstart_b + ncell_b), in box order. */
+typedef struct lc_box_desc {
+    lc_grid grid;
+    int64_t n;
+} lc_box_desc;
+
+/* How a box is split into work-groups. */
+#define LC_BATCH_AUTO 0   /* whole box in one work-group when it has <= 36
+                             cells and fits the LDS tile, else blocks      */
+#define LC_BATCH_WHOLE 1  /* one work-group owns the whole box            */
+#define LC_BATCH_BLOCKS 2 /* buffer + reduce blocks (as LC_SCHED_BUFFER)  */
+
+typedef struct lc_batch lc_batch;
+
+typedef struct lc_batch_info {
+    int32_t nbox;
+    int32_t nwhole;       /* boxes run as one work-group                   */
+    int64_t ntot;         /* particles over all boxes                      */
+    int64_t ncell;        /* cells over all boxes                          */
+    int64_t ngroup;       /* work-groups of one force evaluation           */
+    int64_t ntask;        /* cell-cell tasks over all boxes                */
+    int32_t max_replicas; /* replica slots per particle (buffer + reduce)  */
+    int32_t lds_tile;     /* particles per work-group tile                 */
+} lc_batch_info;
+
+/* [host] Build the combined schedule of nbox boxes (Sec. VI strategy 3 for
+ * split boxes; whole-box groups need no reduction partner) and upload it to
+ * the current device.  modes: per-box LC_BATCH_* (NULL = all AUTO). */
+int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t *modes,
+                    lc_batch **out);
+int lc_batch_info_get(const lc_batch *b, lc_batch_info *out);
+/* [host] pstart, cstart: host int64 arrays of nbox + 1 entries. */
+int lc_batch_offsets(const lc_batch *b, int64_t *pstart, int64_t *cstart);
+void lc_batch_free(lc_batch *b);
+
+/* Counting sort of all boxes at once.  pos [device] double 3 x ntot (box b's
+ * particles at pstart_b..), cell_start [device] int32 ncell+1 (global slots),
+ * perm [device] int32 ntot (sorted slot -> input index, stays inside the
+ * box), coord [device] uint32 3 x ntot.  ws: max_n >= ntot, max_cells >=
+ * ncell. */
+int lc_batch_build_cells(const lc_batch *b, const double *pos,
+                         int32_t *cell_start, int32_t *perm, uint32_t *coord,
+                         lc_workspace *ws, void *stream);
+
+/* One force evaluation of every box: all work-groups of all boxes in ONE
+ * sweep launch (persistent != 0: a grid sized to the device draws groups from
+ * a ticket counter, largest first) plus one gather launch.  F [device] int64
+ * 3 x ntot; ew [device] int64 nbox x 3 {energy, virial, pairs} per box. */
+int lc_batch_forces(const lc_batch *b, const int32_t *cell_start,
+                    const uint32_t *coord, int64_t *F, int64_t *ew,
+                    int persistent, lc_workspace *ws, void *stream);
+
+/* HIP graph of lc_batch_forces with fixed buffers, captured on `stream`
+ * (which must not be the legacy null stream); replays are bit-identical
+ * evaluations.  lc_graph_launch enqueues one replay on `stream`. */
+typedef struct lc_graph lc_graph;
+int lc_batch_graph_create(const lc_batch *b, const int32_t *cell_start,
+                          const uint32_t *coord, int64_t *F, int64_t *ew,
+                          int persistent, lc_workspace *ws, void *stream,
+                          lc_graph **out);
+int lc_graph_launch(lc_graph *gr, void *stream);
+void lc_graph_free(lc_graph *gr);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,7 @@
 //   k_gather                reorder SoA rows by a permutation
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -424,6 +425,13 @@ struct SweepArgs {
     long long *part;  // kPartSlots x 3 partial {energy, virial, pairs}
     uint32_t *flags;
     PairParams pp;
+    // batched boxes (all NULL for a single box)
+    const int *grp_box;        // box of each group
+    const PairParams *ppar;    // pair parameters per box
+    long long *ew_box;         // per-box {energy, virial, pairs}, summed atomically
+    // persistent launch: work-groups draw groups from this ticket counter
+    int *ticket;
+    int ngroups;
 };
 
 // Exact round-to-nearest-even of v * 2^32 to int64 for |v * 2^32| < 2^51:
@@ -527,11 +535,11 @@ __device__ __forceinline__ int foot_cell(const L &sh, int nf, int l) {
 // 64 at a time, so the Lennard-Jones arithmetic runs on full waves.
 template <int CAP, int WMODE, bool F64, bool STAGED, bool FF>
 __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const SweepArgs &a,
-                                            int nf, int nt, int nslot, long long &e_sum,
-                                            long long &w_sum, long long &p_cnt, uint32_t &ovf) {
+                                            const PairParams &pp, int f0, int nf, int nt,
+                                            int nslot, long long &e_sum, long long &w_sum,
+                                            long long &p_cnt, uint32_t &ovf) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t n = a.n;
-    const PairParams pp = a.pp;
     uint32_t *q = sh.q[wave];
     int qn = 0;  // wave-uniform queue length
 
@@ -570,7 +578,6 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             int64_t gi = foot_gidx(sh, nf, il), gj = foot_gidx(sh, nf, jl);
             unsigned long long *Fi = (unsigned long long *)a.F, *Fj = Fi;
             if constexpr (WMODE == 3) {
-                const int f0 = a.grp_foot[a.grp_base + blockIdx.x];
                 const int ri = a.foot_rep[f0 + foot_cell(sh, nf, il)];
                 const int rj = a.foot_rep[f0 + foot_cell(sh, nf, jl)];
                 Fi = (unsigned long long *)a.pbuf + (int64_t)ri * 3 * n;
@@ -664,16 +671,12 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
     if (lane < qn) eval(q[lane]);
 }
 
-// One phase of cell-cell tasks; one work-group per task group.
-// WMODE: 0 = accumulate in LDS, plain read-modify-write of the footprint
-//        (the phase must be conflict-free); 1 = accumulate in LDS, global
-//        atomic write-back; 2 = every pair adds into global memory with
-//        atomics.
+// All work of one task group (see k_sweep).
 template <int CAP, int WMODE, bool F64, bool FF>
-__global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
-    __shared__ SweepLDS<CAP, WMODE, FF> sh;
+__device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const SweepArgs &a,
+                                            const int g) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int g = a.grp_base + blockIdx.x;
+    const PairParams pp = a.ppar ? a.ppar[a.grp_box[g]] : a.pp;
     const int t0 = a.grp_task[g], nt = a.grp_task[g + 1] - t0;
     const int f0 = a.grp_foot[g], nf = a.grp_foot[g + 1] - f0;
     const int64_t n = a.n;
@@ -727,8 +730,8 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
             }
             sh.u[k] = make_uint4(ux, uy, uz, 0u);
             if constexpr (FF)
-                sh.f[k] = make_float4(canon_d(ux, ox, a.pp.s[0]), canon_d(uy, oy, a.pp.s[1]),
-                                      canon_d(uz, oz, a.pp.s[2]), 0.f);
+                sh.f[k] = make_float4(canon_d(ux, ox, pp.s[0]), canon_d(uy, oy, pp.s[1]),
+                                      canon_d(uz, oz, pp.s[2]), 0.f);
         }
     }
     if constexpr (WMODE == 3) {
@@ -761,9 +764,11 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
     long long e_sum = 0, w_sum = 0, p_cnt = 0;
     uint32_t ovf = 0;
     if (staged)
-        sweep_pairs<CAP, WMODE, F64, true, FF>(sh, a, nf, nt, nslot, e_sum, w_sum, p_cnt, ovf);
+        sweep_pairs<CAP, WMODE, F64, true, FF>(sh, a, pp, f0, nf, nt, nslot, e_sum, w_sum, p_cnt,
+                                               ovf);
     else
-        sweep_pairs<CAP, WMODE, F64, false, FF>(sh, a, nf, nt, nslot, e_sum, w_sum, p_cnt, ovf);
+        sweep_pairs<CAP, WMODE, F64, false, FF>(sh, a, pp, f0, nf, nt, nslot, e_sum, w_sum, p_cnt,
+                                                ovf);
 
     // energy, virial, pair count: reduce over the work-group, then one
     // atomic per sum into a slot spread by group index (same-address global
@@ -781,7 +786,9 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
     if (tid < 3) {
         long long v = 0;
         for (int k = 0; k < kNW; ++k) v += sh.red[k][tid];
-        atomicAdd((unsigned long long *)&a.part[(g % kPartSlots) * 3 + tid], (unsigned long long)v);
+        long long *dst = a.ew_box ? &a.ew_box[a.grp_box[g] * 3 + tid]
+                                  : &a.part[(g % kPartSlots) * 3 + tid];
+        atomicAdd((unsigned long long *)dst, (unsigned long long)v);
     }
 
     if constexpr (WMODE == 3) {
@@ -807,6 +814,33 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
                     atomicAdd(&F[d * n + gi], v);
             }
         }
+    }
+}
+
+// One phase of cell-cell tasks.  Without a ticket counter every work-group
+// runs group grp_base + blockIdx.x; with one (persistent launch) each
+// work-group keeps drawing the next group until all ngroups are taken.
+// WMODE: 0 = accumulate in LDS, plain read-modify-write of the footprint
+//        (the phase must be conflict-free); 1 = accumulate in LDS, global
+//        atomic write-back; 2 = every pair adds into global memory with
+//        atomics; 3 = accumulate in LDS, plain stores into the group's
+//        replica slots (buffer + reduce).
+template <int CAP, int WMODE, bool F64, bool FF>
+__global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
+    __shared__ SweepLDS<CAP, WMODE, FF> sh;
+    if (!a.ticket) {
+        sweep_group<CAP, WMODE, F64, FF>(sh, a, a.grp_base + blockIdx.x);
+        return;
+    }
+    __shared__ int s_next;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = atomicAdd(a.ticket, 1);
+        __syncthreads();
+        const int k = s_next;
+        __syncthreads();
+        if (k >= a.ngroups) break;
+        sweep_group<CAP, WMODE, F64, FF>(sh, a, a.grp_base + k);
+        __syncthreads();
     }
 }
 
@@ -911,22 +945,24 @@ static PairParams pair_params(const lc_grid *g) {
     return p;
 }
 
+static int ensure_pbuf(lc_workspace *ws, int64_t need) {
+    if (need <= ws->pbuf_elems) return LC_OK;
+    (void)hipFree(ws->pbuf);
+    ws->pbuf = nullptr;
+    ws->pbuf_elems = 0;
+    int rc = dalloc(&ws->pbuf, need);
+    if (rc) return rc;
+    ws->pbuf_elems = need;
+    return LC_OK;
+}
+
 static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *cell_start,
                        const uint32_t *coord, int64_t n, int64_t *F, int64_t *ew, int precision,
                        lc_workspace *ws, hipStream_t st, hipEvent_t *ev = nullptr) {
     const bool buffered = s->h.write_mode == 3;
     int rc = buffered ? LC_OK : fill64((long long *)F, 3 * n, st);
     if (rc) return rc;
-    if (buffered) {
-        const int64_t need = (int64_t)s->h.rmax * 3 * n;
-        if (need > ws->pbuf_elems) {  // grown once, reused afterwards
-            (void)hipFree(ws->pbuf);
-            ws->pbuf = nullptr;
-            ws->pbuf_elems = 0;
-            if ((rc = dalloc(&ws->pbuf, need))) return rc;
-            ws->pbuf_elems = need;
-        }
-    }
+    if (buffered && (rc = ensure_pbuf(ws, (int64_t)s->h.rmax * 3 * n))) return rc;
     rc = fill64((long long *)ws->part, 3 * kPartSlots, st);
     if (rc) return rc;
     SweepArgs a;
@@ -941,6 +977,11 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     a.foot_rep = s->foot_rep;
     a.pbuf = ws->pbuf;
     a.part = (long long *)ws->part;
+    a.grp_box = nullptr;
+    a.ppar = nullptr;
+    a.ew_box = nullptr;
+    a.ticket = nullptr;
+    a.ngroups = 0;
     a.flags = ws->flags;
     a.pp = pair_params(g);
     // LDS tile: expected particles of the largest footprint with headroom
@@ -1491,4 +1532,413 @@ extern "C" int lc_verlet_step(const lc_grid *g, const lc_schedule *s, double *po
         LAUNCHCHK("k_copy64");
     }
     return LC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// a8: batched boxes
+// ---------------------------------------------------------------------------
+
+struct BoxGeo {
+    double inv[3];
+    int nc[3];
+    int cstart;
+};
+
+__device__ __forceinline__ int box_of(const int64_t *__restrict__ pstart, int nbox, int64_t i) {
+    int lo = 0, hi = nbox;  // pstart[lo] <= i < pstart[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pstart[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_bin_batch(const double *__restrict__ pos, int64_t ntot,
+                            const int64_t *__restrict__ pstart, int nbox,
+                            const BoxGeo *__restrict__ geo, int *__restrict__ cid,
+                            int *__restrict__ rank, int *__restrict__ counts) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntot) return;
+    const BoxGeo gb = geo[box_of(pstart, nbox, i)];
+    int c[3];
+    for (int d = 0; d < 3; ++d) c[d] = cell_of(canon(pos[d * ntot + i], gb.inv[d]), gb.nc[d]);
+    const int cc = gb.cstart + c[0] + gb.nc[0] * (c[1] + gb.nc[1] * c[2]);
+    cid[i] = cc;
+    rank[i] = atomicAdd(&counts[cc], 1);
+}
+
+__global__ void k_scatter_batch(const double *__restrict__ pos, int64_t ntot,
+                                const int64_t *__restrict__ pstart, int nbox,
+                                const BoxGeo *__restrict__ geo, const int *__restrict__ cid,
+                                const int *__restrict__ rank, const int *__restrict__ cell_start,
+                                int *__restrict__ perm, uint32_t *__restrict__ coord) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntot) return;
+    const BoxGeo gb = geo[box_of(pstart, nbox, i)];
+    const int64_t dst = (int64_t)cell_start[cid[i]] + rank[i];
+    perm[dst] = (int)i;
+    for (int d = 0; d < 3; ++d) coord[d * ntot + dst] = canon(pos[d * ntot + i], gb.inv[d]);
+}
+
+struct lc_batch {
+    int device = 0;
+    int ncu = 256;
+    int nbox = 0;
+    int nwhole = 0;
+    int cap = 1024;
+    int64_t ntot = 0, ncell = 0;
+    std::vector<int64_t> pstart, cstart;
+    lcs::HostSchedule h;  // combined groups, global cell ids
+    std::vector<int32_t> grp_box;
+    std::vector<PairParams> ppar;
+    std::vector<BoxGeo> geo;
+    int32_t *d_grp_task = nullptr, *d_grp_foot = nullptr, *d_foot_cells = nullptr;
+    int32_t *d_foot_rep = nullptr, *d_cell_rep = nullptr, *d_grp_box = nullptr;
+    uint32_t *d_task_ab = nullptr;
+    PairParams *d_ppar = nullptr;
+    BoxGeo *d_geo = nullptr;
+    int64_t *d_pstart = nullptr;
+    int *d_ticket = nullptr;
+};
+
+struct lc_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" void lc_batch_free(lc_batch *b) {
+    if (!b) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(b->device);
+    (void)hipFree(b->d_grp_task);
+    (void)hipFree(b->d_grp_foot);
+    (void)hipFree(b->d_foot_cells);
+    (void)hipFree(b->d_foot_rep);
+    (void)hipFree(b->d_cell_rep);
+    (void)hipFree(b->d_grp_box);
+    (void)hipFree(b->d_task_ab);
+    (void)hipFree(b->d_ppar);
+    (void)hipFree(b->d_geo);
+    (void)hipFree(b->d_pstart);
+    (void)hipFree(b->d_ticket);
+    (void)hipSetDevice(cur);
+    delete b;
+}
+
+template <typename T>
+static int upload(T **dst, const std::vector<T> &v) {
+    int rc = dalloc(dst, (int64_t)v.size());
+    if (rc) return rc;
+    if (!v.empty() &&
+        hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(LC_EHIP, "batch upload");
+    return LC_OK;
+}
+
+extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t *modes,
+                               lc_batch **out) {
+    if (!boxes || nbox < 1 || !out) return fail(LC_EINVAL, "lc_batch_create: bad arguments");
+    lc_batch *b = new lc_batch();
+    b->nbox = nbox;
+    b->pstart.assign(1, 0);
+    b->cstart.assign(1, 0);
+    for (int k = 0; k < nbox; ++k) {
+        if (boxes[k].n < 0 || boxes[k].grid.ncell < 27) {
+            delete b;
+            return fail(LC_EINVAL, "lc_batch_create: box %d", k);
+        }
+        b->pstart.push_back(b->pstart.back() + boxes[k].n);
+        b->cstart.push_back(b->cstart.back() + boxes[k].grid.ncell);
+    }
+    b->ntot = b->pstart.back();
+    b->ncell = b->cstart.back();
+    if (b->ntot >= 2147483647LL || b->ncell >= 2147483647LL) {
+        delete b;
+        return fail(LC_ECAPACITY, "lc_batch_create: more than 2^31 particles or cells");
+    }
+    // per-box group lists in global cell ids
+    struct Grp {
+        std::vector<int32_t> cells;  // footprint (global)
+        std::vector<int32_t> rep;    // replica slot per footprint cell
+        std::vector<uint32_t> ab;    // tasks (local footprint indices)
+        int box;
+        double est;                  // expected particles in the footprint
+    };
+    std::vector<Grp> groups;
+    std::vector<int32_t> cell_rep((size_t)b->ncell, 0);
+    double est_max = 0.0;
+    for (int k = 0; k < nbox; ++k) {
+        const lc_grid &g = boxes[k].grid;
+        const double dens = (double)boxes[k].n / (double)g.ncell;
+        const int mode = modes ? modes[k] : LC_BATCH_AUTO;
+        const bool whole = mode == LC_BATCH_WHOLE ||
+                           (mode == LC_BATCH_AUTO && g.ncell <= 36 && boxes[k].n <= 1400);
+        const int32_t c0 = (int32_t)b->cstart[k];
+        if (whole) {
+            if (14 * (int64_t)g.ncell > lcs::kMaxGroupTasks || g.ncell > lcs::kMaxGroupCells) {
+                lc_batch_free(b);
+                return fail(LC_ECAPACITY, "box %d too large for one work-group", k);
+            }
+            std::vector<lcs::Offset> order;
+            std::string err;
+            lcs::stencil_order(LC_SCHED_LEX, false, nullptr, 0, order, err);
+            std::vector<int32_t> A, B;
+            lcs::basic_tasks(g.nc, order, A, B);
+            Grp gr;
+            gr.box = k;
+            for (int32_t c = 0; c < g.ncell; ++c) {
+                gr.cells.push_back(c0 + c);
+                gr.rep.push_back(cell_rep[(size_t)(c0 + c)]++);
+            }
+            for (size_t t = 0; t < A.size(); ++t)
+                gr.ab.push_back((uint32_t)A[t] | ((uint32_t)B[t] << 16));
+            gr.est = dens * g.ncell;
+            est_max = std::max(est_max, gr.est);
+            groups.push_back(std::move(gr));
+            b->nwhole++;
+        } else {
+            lcs::HostSchedule hb;
+            std::string err;
+            int rc = lcs::build_schedule(g.nc, LC_SCHED_BUFFER, nullptr, 0, hb, err);
+            if (rc) {
+                lc_batch_free(b);
+                return fail(rc, "box %d: %s", k, err.c_str());
+            }
+            const int ng = (int)hb.grp_task.size() - 1;
+            for (int q = 0; q < ng; ++q) {
+                Grp gr;
+                gr.box = k;
+                for (int f = hb.grp_foot[q]; f < hb.grp_foot[q + 1]; ++f) {
+                    gr.cells.push_back(c0 + hb.foot_cells[f]);
+                    gr.rep.push_back(hb.foot_rep[f]);
+                }
+                for (int t = hb.grp_task[q]; t < hb.grp_task[q + 1]; ++t) gr.ab.push_back(hb.task_ab[t]);
+                gr.est = dens * (double)gr.cells.size();
+                est_max = std::max(est_max, gr.est);
+                groups.push_back(std::move(gr));
+            }
+            for (int32_t c = 0; c < g.ncell; ++c) cell_rep[(size_t)(c0 + c)] = hb.cell_rep[(size_t)c];
+        }
+        PairParams pp;
+        for (int d = 0; d < 3; ++d) {
+            pp.s[d] = g.scale[d];
+            pp.sd[d] = g.box[d] / 4294967296.0;
+        }
+        pp.rc2 = g.rc2;
+        pp.rc2f = (float)((double)g.rc2 * (1.0 + 1e-4));
+        pp.ecut = g.ecut;
+        pp.rc2d = g.rc * g.rc;
+        const double ic = 1.0 / pp.rc2d, s6 = ic * ic * ic;
+        pp.ecutd = 4.0 * s6 * (s6 - 1.0);
+        b->ppar.push_back(pp);
+        BoxGeo gg;
+        for (int d = 0; d < 3; ++d) {
+            gg.inv[d] = g.inv_box[d];
+            gg.nc[d] = g.nc[d];
+        }
+        gg.cstart = c0;
+        b->geo.push_back(gg);
+    }
+    // one launch: largest groups first
+    std::stable_sort(groups.begin(), groups.end(),
+                     [](const Grp &x, const Grp &y) { return x.ab.size() > y.ab.size(); });
+    lcs::HostSchedule &h = b->h;
+    h.write_mode = 3;
+    h.grp_task.assign(1, 0);
+    h.grp_foot.assign(1, 0);
+    h.phase_grp = {0};
+    for (auto &gr : groups) {
+        h.foot_cells.insert(h.foot_cells.end(), gr.cells.begin(), gr.cells.end());
+        h.foot_rep.insert(h.foot_rep.end(), gr.rep.begin(), gr.rep.end());
+        h.task_ab.insert(h.task_ab.end(), gr.ab.begin(), gr.ab.end());
+        h.grp_task.push_back((int32_t)h.task_ab.size());
+        h.grp_foot.push_back((int32_t)h.foot_cells.size());
+        h.max_tasks = std::max(h.max_tasks, (int)gr.ab.size());
+        h.max_cells = std::max(h.max_cells, (int)gr.cells.size());
+        h.ntask += (int64_t)gr.ab.size();
+        b->grp_box.push_back(gr.box);
+    }
+    h.phase_grp.push_back((int32_t)groups.size());
+    h.cell_rep = cell_rep;
+    for (int32_t r : cell_rep) h.rmax = std::max(h.rmax, r);
+    const double need = est_max * 1.35;
+    b->cap = need <= 1024 ? 1024 : (need <= 2048 ? 2048 : 3072);
+
+    int rc = 0;
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        delete b;
+        return fail(LC_EHIP, "hipGetDevice");
+    }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess &&
+        ncu > 0)
+        b->ncu = ncu;
+    std::vector<int64_t> ps(b->pstart);
+    if ((rc = upload(&b->d_grp_task, h.grp_task)) || (rc = upload(&b->d_grp_foot, h.grp_foot)) ||
+        (rc = upload(&b->d_foot_cells, h.foot_cells)) || (rc = upload(&b->d_foot_rep, h.foot_rep)) ||
+        (rc = upload(&b->d_cell_rep, h.cell_rep)) || (rc = upload(&b->d_grp_box, b->grp_box)) ||
+        (rc = upload(&b->d_task_ab, h.task_ab)) || (rc = upload(&b->d_ppar, b->ppar)) ||
+        (rc = upload(&b->d_geo, b->geo)) || (rc = upload(&b->d_pstart, ps)) ||
+        (rc = dalloc(&b->d_ticket, 1))) {
+        lc_batch_free(b);
+        return rc;
+    }
+    *out = b;
+    return LC_OK;
+}
+
+extern "C" int lc_batch_info_get(const lc_batch *b, lc_batch_info *out) {
+    if (!b || !out) return fail(LC_EINVAL, "null argument");
+    memset(out, 0, sizeof *out);
+    out->nbox = b->nbox;
+    out->nwhole = b->nwhole;
+    out->ntot = b->ntot;
+    out->ncell = b->ncell;
+    out->ngroup = (int64_t)b->grp_box.size();
+    out->ntask = b->h.ntask;
+    out->max_replicas = b->h.rmax;
+    out->lds_tile = b->cap;
+    return LC_OK;
+}
+
+extern "C" int lc_batch_offsets(const lc_batch *b, int64_t *pstart, int64_t *cstart) {
+    if (!b || !pstart || !cstart) return fail(LC_EINVAL, "null argument");
+    for (int k = 0; k <= b->nbox; ++k) {
+        pstart[k] = b->pstart[k];
+        cstart[k] = b->cstart[k];
+    }
+    return LC_OK;
+}
+
+extern "C" int lc_batch_build_cells(const lc_batch *b, const double *pos, int32_t *cell_start,
+                                    int32_t *perm, uint32_t *coord, lc_workspace *ws,
+                                    void *stream) {
+    if (!b || !cell_start || (b->ntot > 0 && (!pos || !perm || !coord)))
+        return fail(LC_EINVAL, "lc_batch_build_cells: null argument");
+    int rc = check_ws(ws, b->ntot, b->ncell);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t m = b->ncell, n = b->ntot;
+    if ((rc = fill32(ws->counts, m, st))) return rc;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_bin_batch, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n,
+                           (const int64_t *)b->d_pstart, b->nbox, (const BoxGeo *)b->d_geo, ws->cid,
+                           ws->rank, ws->counts);
+        LAUNCHCHK("k_bin_batch");
+    }
+    const int nb = (int)((m + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBS), 0, st, ws->counts, m, ws->partial);
+    LAUNCHCHK("k_scan_reduce");
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBS), 0, st, ws->partial, nb);
+    LAUNCHCHK("k_scan_top");
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanBS), 0, st, ws->counts, m, ws->partial,
+                       cell_start);
+    LAUNCHCHK("k_scan_final");
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scatter_batch, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos,
+                           n, (const int64_t *)b->d_pstart, b->nbox, (const BoxGeo *)b->d_geo,
+                           ws->cid, ws->rank, cell_start, perm, coord);
+        LAUNCHCHK("k_scatter_batch");
+    }
+    return LC_OK;
+}
+
+
+static int batch_forces_impl(const lc_batch *b, const int32_t *cell_start, const uint32_t *coord,
+                             int64_t *F, int64_t *ew, int persistent, lc_workspace *ws,
+                             hipStream_t st) {
+    int rc = fill64((long long *)ew, 3 * (int64_t)b->nbox, st);
+    if (rc) return rc;
+    const int ng = (int)b->grp_box.size();
+    SweepArgs a;
+    memset(&a, 0, sizeof a);
+    a.grp_task = b->d_grp_task;
+    a.grp_foot = b->d_grp_foot;
+    a.foot_cells = b->d_foot_cells;
+    a.task_ab = b->d_task_ab;
+    a.grp_base = 0;
+    a.cell_start = cell_start;
+    a.coord = coord;
+    a.n = b->ntot;
+    a.F = (long long *)F;
+    a.foot_rep = b->d_foot_rep;
+    a.pbuf = ws->pbuf;
+    a.part = (long long *)ws->part;
+    a.flags = ws->flags;
+    a.pp = b->ppar[0];
+    a.grp_box = b->d_grp_box;
+    a.ppar = b->d_ppar;
+    a.ew_box = (long long *)ew;
+    a.ngroups = ng;
+    int grid = ng;
+    if (persistent) {
+        if ((rc = fill32(b->d_ticket, 1, st))) return rc;
+        a.ticket = b->d_ticket;
+        const size_t lds = b->cap <= 1024   ? sizeof(SweepLDS<1024, 3, false>)
+                           : b->cap <= 2048 ? sizeof(SweepLDS<2048, 3, false>)
+                                            : sizeof(SweepLDS<3072, 3, false>);
+        const int per_cu = std::max(1, (int)(163840 / (lds + 1024)));
+        grid = std::min(ng, b->ncu * per_cu);
+    }
+    if (ng > 0 && (rc = launch_sweep(b->cap, 3, false, false, a, grid, st))) return rc;
+    if (b->ntot > 0) {
+        hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((b->ntot + 255) / 256)), dim3(256), 0,
+                           st, (const long long *)ws->pbuf, (const int *)b->d_cell_rep, cell_start,
+                           (int)b->ncell, b->ntot, (long long *)F);
+        LAUNCHCHK("k_gather_partials");
+    }
+    return LC_OK;
+}
+
+extern "C" int lc_batch_forces(const lc_batch *b, const int32_t *cell_start, const uint32_t *coord,
+                               int64_t *F, int64_t *ew, int persistent, lc_workspace *ws,
+                               void *stream) {
+    if (!b || !cell_start || !F || !ew || (b->ntot > 0 && !coord))
+        return fail(LC_EINVAL, "lc_batch_forces: null argument");
+    int rc = check_ws(ws, b->ntot, b->ncell);
+    if (rc) return rc;
+    if ((rc = ensure_pbuf(ws, (int64_t)b->h.rmax * 3 * b->ntot))) return rc;
+    return batch_forces_impl(b, cell_start, coord, F, ew, persistent, ws, (hipStream_t)stream);
+}
+
+extern "C" int lc_batch_graph_create(const lc_batch *b, const int32_t *cell_start,
+                                     const uint32_t *coord, int64_t *F, int64_t *ew,
+                                     int persistent, lc_workspace *ws, void *stream,
+                                     lc_graph **out) {
+    if (!b || !out || !stream) return fail(LC_EINVAL, "lc_batch_graph_create: bad arguments");
+    int rc = check_ws(ws, b->ntot, b->ncell);
+    if (rc) return rc;
+    if ((rc = ensure_pbuf(ws, (int64_t)b->h.rmax * 3 * b->ntot))) return rc;  // outside capture
+    hipStream_t st = (hipStream_t)stream;
+    lc_graph *gr = new lc_graph();
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    rc = batch_forces_impl(b, cell_start, coord, F, ew, persistent, ws, st);
+    hipError_t e = hipStreamEndCapture(st, &gr->graph);
+    if (rc || e != hipSuccess) {
+        if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        delete gr;
+        return rc ? rc : fail(LC_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(gr->graph);
+        delete gr;
+        return fail(LC_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    *out = gr;
+    return LC_OK;
+}
+
+extern "C" int lc_graph_launch(lc_graph *gr, void *stream) {
+    if (!gr) return fail(LC_EINVAL, "null graph");
+    HIPCHK(hipGraphLaunch(gr->exec, (hipStream_t)stream));
+    return LC_OK;
+}
+
+extern "C" void lc_graph_free(lc_graph *gr) {
+    if (!gr) return;
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    delete gr;
 }

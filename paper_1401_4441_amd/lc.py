@@ -80,6 +80,15 @@ SYMBOLS = {
     "lc_verlet_step": ([P, P, P, P, P, I64, P, P, P, P, ctypes.c_double, INT,
                         INT, P, P, P], INT),
     "lc_kinetic_energy": ([P, I64, P, P, P], INT),
+    "lc_batch_create": ([P, INT, P, P], INT),
+    "lc_batch_info_get": ([P, P], INT),
+    "lc_batch_offsets": ([P, P, P], INT),
+    "lc_batch_free": ([P], None),
+    "lc_batch_build_cells": ([P, P, P, P, P, P, P], INT),
+    "lc_batch_forces": ([P, P, P, P, P, INT, P, P], INT),
+    "lc_batch_graph_create": ([P, P, P, P, P, INT, P, P, P], INT),
+    "lc_graph_launch": ([P, P], INT),
+    "lc_graph_free": ([P], None),
 }
 
 
@@ -366,3 +375,124 @@ def serialization_degree(dims, kind, offsets=None, hist_len: int = 0) -> dict:
     if hist_len > 0:
         out["level_hist"] = hist
     return out
+
+
+# ---------------------------------------------------------------------------
+# batched boxes
+# ---------------------------------------------------------------------------
+
+class _BoxDesc(ctypes.Structure):
+    _fields_ = [("grid", _Grid), ("n", ctypes.c_int64)]
+
+
+class _BatchInfo(ctypes.Structure):
+    _fields_ = [("nbox", ctypes.c_int32), ("nwhole", ctypes.c_int32),
+                ("ntot", ctypes.c_int64), ("ncell", ctypes.c_int64),
+                ("ngroup", ctypes.c_int64), ("ntask", ctypes.c_int64),
+                ("max_replicas", ctypes.c_int32), ("lds_tile", ctypes.c_int32)]
+
+
+BATCH_MODES = {"auto": 0, "whole": 1, "blocks": 2}
+
+
+class Graph:
+    """A captured HIP graph of one batched force evaluation."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def launch(self, stream=None):
+        _chk(lib().lc_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().lc_graph_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent periodic boxes evaluated in one launch."""
+
+    def __init__(self, grids, ns, modes=None):
+        import numpy as np
+        nbox = len(grids)
+        arr = (_BoxDesc * nbox)()
+        for k, (g, n) in enumerate(zip(grids, ns)):
+            arr[k].grid = g._g
+            arr[k].n = int(n)
+        self.grids = list(grids)
+        self.ns = [int(n) for n in ns]
+        if modes is not None:
+            mv = np.ascontiguousarray(
+                [BATCH_MODES[m] if isinstance(m, str) else int(m) for m in modes], dtype=np.int32)
+            self._modes = mv
+            mp = ctypes.c_void_p(mv.ctypes.data)
+        else:
+            mp = None
+        self._h = ctypes.c_void_p()
+        _chk(lib().lc_batch_create(ctypes.cast(arr, P), nbox, mp, ctypes.byref(self._h)))
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def info(self) -> dict:
+        i = _BatchInfo()
+        _chk(lib().lc_batch_info_get(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in _BatchInfo._fields_}
+
+    def offsets(self):
+        import numpy as np
+        nb = len(self.grids)
+        ps = np.zeros(nb + 1, dtype=np.int64)
+        cs = np.zeros(nb + 1, dtype=np.int64)
+        _chk(lib().lc_batch_offsets(self._h, ctypes.c_void_p(ps.ctypes.data),
+                                    ctypes.c_void_p(cs.ctypes.data)))
+        return ps, cs
+
+    def build_cells(self, pos, ws: Workspace, stream=None):
+        info = self.info()
+        dev = pos.device
+        cs = torch.empty(info["ncell"] + 1, dtype=torch.int32, device=dev)
+        perm = torch.empty(info["ntot"], dtype=torch.int32, device=dev)
+        coord = torch.empty((3, info["ntot"]), dtype=torch.int32, device=dev)
+        _chk(lib().lc_batch_build_cells(self._h, _p(pos), _p(cs), _p(perm), _p(coord), ws.ptr,
+                                        _stream(stream)))
+        return cs, perm, coord
+
+    def forces(self, cell_start, coord, ws: Workspace, F=None, ew=None, persistent=True,
+               stream=None):
+        ntot = coord.shape[1]
+        dev = coord.device
+        if F is None:
+            F = torch.empty((3, ntot), dtype=torch.int64, device=dev)
+        if ew is None:
+            ew = torch.empty((len(self.grids), 3), dtype=torch.int64, device=dev)
+        _chk(lib().lc_batch_forces(self._h, _p(cell_start), _p(coord), _p(F), _p(ew),
+                                   1 if persistent else 0, ws.ptr, _stream(stream)))
+        return F, ew
+
+    def graph(self, cell_start, coord, F, ew, ws: Workspace, stream, persistent=True) -> Graph:
+        """Capture forces() into a HIP graph on `stream` (not the null stream)."""
+        h = ctypes.c_void_p()
+        _chk(lib().lc_batch_graph_create(self._h, _p(cell_start), _p(coord), _p(F), _p(ew),
+                                         1 if persistent else 0, ws.ptr, _stream(stream),
+                                         ctypes.byref(h)))
+        return Graph(h)
+
+    def close(self):
+        if self._h:
+            lib().lc_batch_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
