@@ -46,6 +46,7 @@ WORKLOADS = {
     "fcc4m": dict(n=4_000_000, rho=0.8, rc=2.5, seed=1003, even=True,
                   desc="LJ FCC+jitter N=4000000 rho=0.8 rc=2.5 periodic cube, 68^3 cells"),
 }
+EXTRA_WORKLOADS = ("fcc4m_md", "slab2m", "boxes512")
 
 H3 = ([(1, a, b) for b in (-1, 0, 1) for a in (-1, 0, 1)]
       + [(0, a, 1) for a in (-1, 0, 1)] + [(0, -1, 0)])
@@ -67,7 +68,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="fcc256k", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="fcc256k",
+                    choices=sorted(WORKLOADS) + list(EXTRA_WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the baseline schedules (atomics, paper orders)")
@@ -80,6 +82,12 @@ def main():
     import torch
     from paper_1401_4441_amd import lc, synth
 
+    if args.workload == "fcc4m_md":
+        return bench_md(args)
+    if args.workload == "slab2m":
+        return bench_slab(args)
+    if args.workload == "boxes512":
+        return bench_boxes(args)
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     box = synth.fcc(w["n"], w["rho"], rc=w["rc"], seed=w["seed"])
@@ -207,6 +215,152 @@ def main():
             "sample": f"{len(times)} full serial fixed-point link-cell evaluations of the "
                       f"same {box.n}-particle box (median {t:.3f} s each)"}
     print(json.dumps(out), flush=True)
+
+
+def _time_evals(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _line(metric, value, unit, ms, args, config, dtype="f32 pair math, int64 fixed-point accumulation",
+          **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic (seeded)", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_md(args):
+    """4M-particle crystal, thermal velocities at T = 1: velocity Verlet with
+    dt = 0.005 and a cell rebuild every 10 steps (cells of rc + 0.6 skin)."""
+    import torch
+    from paper_1401_4441_amd import lc, synth
+    box = synth.workload("fcc4m")
+    dev = torch.device("cuda:0")
+    g = lc.Grid(box.L, box.rc, 0.6, True)
+    ws = lc.Workspace(box.n, g.ncell)
+    sched = lc.Schedule(g, "buffer")
+    pos = torch.from_numpy(box.pos).to(dev)
+    vel = torch.from_numpy(box.vel).to(dev)
+    ids = torch.arange(box.n, dtype=torch.int32, device=dev)
+    cs, perm, coord = lc.build_cells(g, pos, ws)  # sets the tile hint
+    nsteps = 100 if args.steps >= 10 else args.steps
+    ws.clear_status()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    trace, F = lc.verlet_step(g, sched, pos, vel, ids, ws, 0.005, nsteps, 10)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / nsteps
+    st = ws.status()
+    tr = trace.cpu().numpy().astype(np.float64) / 2.0 ** 32
+    etot = tr[:, 0] + tr[:, 1]
+    # pairs per evaluation, for the throughput figure
+    cs2, _, co2 = lc.build_cells(g, pos, ws)
+    _, ew = lc.compute_forces(g, sched, cs2, co2, ws)
+    pairs = int(ew[2].item())
+    _line("pair interactions/sec during velocity-Verlet MD (step incl. kick/drift, rebuilds, energies)",
+          pairs / (ms * 1e-3), "pairs/s", ms, args,
+          {"workload": "LJ FCC+jitter N=4000000 rho=0.8 rc=2.5, MB T=1, dt=0.005, "
+                       "rebuild every 10, skin 0.6, 54^3 cells", "nsteps": nsteps,
+           "schedule": "buffer", "status_flags": st},
+          dtype="f32 pairs, int64 forces, f64 positions/velocities/energies",
+          energy={"E0_per_particle": etot[0] / box.n,
+                  "drift_per_particle": (etot[-1] - etot[0]) / box.n,
+                  "fluct_per_particle": float(etot.max() - etot.min()) / box.n,
+                  "KE0": tr[0, 0] / box.n, "PE0": tr[0, 1] / box.n})
+
+
+def bench_slab(args):
+    """2M-particle slab (dense middle third, dilute gas), rc = 3.0."""
+    import torch
+    from paper_1401_4441_amd import lc, synth
+    box = synth.workload("slab2m")
+    dev = torch.device("cuda:0")
+    g = lc.Grid(box.L, box.rc, 0.0, True)
+    ws = lc.Workspace(box.n, g.ncell)
+    pos = torch.from_numpy(box.pos).to(dev)
+    cs, perm, coord = lc.build_cells(g, pos, ws)
+    F = torch.empty((3, box.n), dtype=torch.int64, device=dev)
+    ew = torch.empty(3, dtype=torch.int64, device=dev)
+    res = {}
+    for kind in ("buffer", "block8", "atomic_tile", "atomic_pair"):
+        s = lc.Schedule(g, kind)
+        ws.clear_status()
+        ms = _time_evals(lambda: lc.compute_forces(g, s, cs, coord, ws, "fp32", F, ew),
+                         max(args.steps // 5, 3), 2)
+        res[kind] = {"ms": ms, "status_flags": ws.status()}
+        s.close()
+    pairs = int(ew[2].item())
+    counts = (cs[1:] - cs[:-1]).cpu().numpy()
+    best = min(("buffer", "block8"), key=lambda k: res[k]["ms"])
+    _line("pair interactions/sec (LJ cell-pair force sweep, inhomogeneous slab)",
+          pairs / (res[best]["ms"] * 1e-3), "pairs/s", res[best]["ms"], args,
+          {"workload": "LJ slab N=2000000, rho 0.75 middle third / 0.02 gas, rc=3.0, 64^3 cells",
+           "schedule": best, "pairs_in_cutoff": pairs,
+           "cell_occupancy": {"max": int(counts.max()), "mean": float(counts.mean()),
+                              "empty_frac": float((counts == 0).mean())}},
+          schedules={k: dict(v, pairs_per_s=pairs / (v["ms"] * 1e-3)) for k, v in res.items()})
+
+
+def bench_boxes(args):
+    """512 independent boxes, N ~ U{500..20000}, density ~ U[0.5, 0.9]: one
+    persistent launch (HIP graph replay) against a per-box launch loop."""
+    import torch
+    from paper_1401_4441_amd import autotune, lc, synth
+    boxes = synth.boxes(512, 500, 20000, 0.5, 0.9, rc=2.5, seed=777)
+    dev = torch.device("cuda:0")
+    grids = [lc.Grid(b.L, b.rc) for b in boxes]
+    ns = [b.n for b in boxes]
+    pos_all = torch.from_numpy(np.ascontiguousarray(np.concatenate([b.pos for b in boxes], 1))).to(dev)
+    tune = autotune.tune_batch(grids, ns, pos_all, reps=3)
+    batch = lc.Batch(grids, ns, None if tune["modes"] == "auto" else ["blocks"] * len(ns))
+    info = batch.info()
+    ws = lc.Workspace(info["ntot"], info["ncell"])
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        cs, perm, coord = batch.build_cells(pos_all, ws, stream=side)
+        F = torch.empty((3, info["ntot"]), dtype=torch.int64, device=dev)
+        ew = torch.empty((len(ns), 3), dtype=torch.int64, device=dev)
+        batch.forces(cs, coord, ws, F, ew, tune["persistent"], stream=side)
+    side.synchronize()
+    graph = batch.graph(cs, coord, F, ew, ws, side, tune["persistent"])
+    with torch.cuda.stream(side):
+        ms_graph = _time_evals(lambda: graph.launch(side), args.steps, args.warmup)
+    pairs = int(ew[:, 2].sum().item())
+    # per-box launch loop: every box its own arrays, schedule and launches
+    per = []
+    for b, g in zip(boxes, grids):
+        wsb = lc.Workspace(b.n, g.ncell)
+        p = torch.from_numpy(b.pos).to(dev)
+        c, _, co = lc.build_cells(g, p, wsb)
+        per.append((g, lc.Schedule(g, "buffer"), c, co, wsb))
+
+    def loop():
+        for g, s, c, co, wsb in per:
+            lc.compute_forces(g, s, c, co, wsb)
+    ms_loop = _time_evals(loop, max(args.steps // 10, 2), 1)
+    _line("pair interactions/sec over 512 independent boxes (one persistent graph launch)",
+          pairs / (ms_graph * 1e-3), "pairs/s", ms_graph, args,
+          {"workload": "512 LJ FCC boxes, N~U{500..20000}, rho~U[0.5,0.9], rc=2.5",
+           "ntot": info["ntot"], "groups": info["ngroup"], "whole_box_groups": info["nwhole"],
+           "pairs_in_cutoff": pairs, "autotune": tune},
+          per_box_loop={"ms": ms_loop, "pairs_per_s": pairs / (ms_loop * 1e-3),
+                        "graph_speedup": ms_loop / ms_graph})
 
 
 if __name__ == "__main__":

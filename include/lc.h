@@ -111,6 +111,12 @@ typedef struct lc_workspace lc_workspace;
 int lc_workspace_create(int64_t max_n, int64_t max_cells, lc_workspace **out);
 void lc_workspace_destroy(lc_workspace *ws);
 
+/* LDS tile sizing hint: the largest number of particles in one cell (0 =
+ * estimate from the mean density).  A work-group stages its footprint cells
+ * in LDS when they fit the tile and otherwise runs the (exact but slower)
+ * global-memory path, flagged with LC_FLAG_FALLBACK. */
+int lc_workspace_set_tile_hint(lc_workspace *ws, int32_t max_per_cell);
+
 /* Clear the device status flags (async on stream). */
 int lc_workspace_clear_status(lc_workspace *ws, void *stream);
 /* Synchronise `stream` and return the device status flags (LC_FLAG_*). */
@@ -190,6 +196,14 @@ typedef struct lc_schedule_info {
  * d / -d for every neighbour d); ignored (may be NULL) for other kinds. */
 int lc_make_schedule(const lc_grid *g, int kind, const int8_t *offsets, int n,
                      lc_schedule **out);
+/* As lc_make_schedule, with the smallest block per axis for the block kinds
+ * (LC_SCHED_BLOCK8 / ATOMIC_TILE / BUFFER): block_min [host] 3 x int32, at
+ * least {1, 2, 2} -- the stencil reaches one cell along +x and one cell each
+ * way along y and z, so same-coloured blocks stay a whole block apart.  NULL
+ * = {1, 2, 2}.  Larger blocks mean fewer, bigger work-groups and less
+ * halo write-back per particle; the autotuner picks the shape. */
+int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *offsets,
+                        int n, const int32_t *block_min, lc_schedule **out);
 int lc_schedule_info_get(const lc_schedule *s, lc_schedule_info *out);
 void lc_schedule_free(lc_schedule *s);
 

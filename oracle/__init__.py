@@ -69,9 +69,11 @@ def lib():
         L.orc_dag_lc.argtypes = [ctypes.c_int, P, P, P, P]
         L.orc_verlet_fx.argtypes = [i64, P, P, P, f64, P, P, ctypes.c_int, f64,
                                     ctypes.c_int, P, P]
+        L.orc_forces_subset_fx.argtypes = [i64, P, P, f64, P, i64, P, P]
         for name in ("orc_forces_brute_f64", "orc_forces_brute_fx",
                      "orc_forces_lc_fx", "orc_forces_lc_f64", "orc_lc_tasks",
-                     "orc_dag_generic", "orc_dag_lc", "orc_verlet_fx"):
+                     "orc_dag_generic", "orc_dag_lc", "orc_verlet_fx",
+                     "orc_forces_subset_fx"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -252,6 +254,21 @@ def forces_lc_f64(pos, u, L, rc, nc, stencil=H3):
                                    _ptr(ncv), _ptr(offs), len(offs), _ptr(F),
                                    _ptr(ew), ctypes.byref(np_)), "forces_lc_f64")
     return F, float(ew[0]), float(ew[1]), int(np_.value)
+
+
+def forces_subset_fx(u, L, rc, idx):
+    """Fixed-point force on the particles ``idx`` by brute force over all
+    others (O(N) each): returns (F int64 (3, m), neighbours per particle)."""
+    u = np.ascontiguousarray(u, dtype=np.uint32)
+    n = u.shape[1]
+    Lv = np.ascontiguousarray(np.asarray(L, dtype=np.float64).reshape(3))
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    m = len(idx)
+    F = np.empty((3, m), dtype=np.int64)
+    npair = np.empty(m, dtype=np.int64)
+    _check(lib().orc_forces_subset_fx(n, _ptr(u), _ptr(Lv), rc, _ptr(idx), m, _ptr(F),
+                                      _ptr(npair)), "forces_subset_fx")
+    return F, npair
 
 
 def brute_numpy_f64(pos, L, rc):

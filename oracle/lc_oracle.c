@@ -245,6 +245,36 @@ int orc_forces_brute_fx(int64_t n, const uint32_t *u, const double *L,
     return ovf ? ORC_EOVERFLOW : ORC_OK;
 }
 
+/* Fixed-point force on m selected particles by brute force over all other
+ * particles: F_i = sum over j != i of the force the canonical pair (i, j)
+ * puts on i, i.e. -q(i, j).  Swapping i and j negates the box-fraction
+ * difference exactly (the int32 difference of a pair inside the cutoff is
+ * never -2^31) and round-to-nearest-even is odd, so q(j, i) = -q(i, j) and
+ * this equals what any pair orientation of the sweep accumulates.  F is
+ * 3 x m; npair (may be NULL) receives the neighbours of each particle. */
+int orc_forces_subset_fx(int64_t n, const uint32_t *u, const double *L, double rc,
+                         const int64_t *idx, int64_t m, int64_t *F, int64_t *npair)
+{
+    fx_par p;
+    fx_par_init(&p, L, rc);
+    int ovf = 0;
+    for (int64_t s = 0; s < m; ++s) {
+        const int64_t i = idx[s];
+        if (i < 0 || i >= n) return ORC_EINVAL;
+        int64_t f[3] = {0, 0, 0}, cnt = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            int64_t q[3], qe, qw;
+            if (!pair_fx(u, n, i, j, &p, q, &qe, &qw, &ovf)) continue;
+            for (int d = 0; d < 3; ++d) f[d] -= q[d];
+            ++cnt;
+        }
+        for (int d = 0; d < 3; ++d) F[d * m + s] = f[d];
+        if (npair) npair[s] = cnt;
+    }
+    return ovf ? ORC_EOVERFLOW : ORC_OK;
+}
+
 /* Link-cell grid with linked lists (head of chain per cell, next per
  * particle), the classic formulation of the method. */
 typedef struct {

@@ -1,0 +1,162 @@
+"""Autotuner for the link-cell force sweep.
+
+It times candidate configurations on the device through the C-ABI and keeps
+the fastest: the cell grid (cell side rc, optionally widened, cell counts
+rounded to even or not), the conflict-free schedule (BLOCK8 colouring or
+BUFFER buffer + reduce; ATOMIC_TILE when atomics are allowed) and the block
+shape (smallest block per axis).  For a batch of boxes it picks how boxes
+are split (whole-box work-groups where they fit, or blocks) and whether the
+sweep runs as a persistent launch.  Results are cached in a JSON file keyed
+by the device name and a bucket of (N, density, rc).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import torch
+
+from . import lc
+
+CACHE_ENV = "LC_TUNE_CACHE"
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1401_4441_amd",
+                             "tune.json")
+
+BOX_KINDS_CONFLICT_FREE = ("block8", "buffer")
+BLOCKS = ((1, 2, 2), (2, 2, 2), (1, 3, 3), (2, 3, 3))
+GRIDS = ({"extra": 0.0, "even": True}, {"extra": 0.0, "even": False},
+         {"extra": 0.15, "even": True})
+
+
+def _cache_path() -> str:
+    return os.environ.get(CACHE_ENV, DEFAULT_CACHE)
+
+
+def _load_cache() -> dict:
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(cache: dict) -> None:
+    path = _cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # a read-only home only loses the cache
+
+
+def box_key(n: int, L, rc: float) -> str:
+    """Bucket: log2(N) in quarter steps, density to 0.05, rc to 0.01."""
+    vol = float(L[0]) * float(L[1]) * float(L[2])
+    rho = n / vol
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+    return f"{dev}|n{round(4 * math.log2(max(n, 1)))}|rho{round(rho / 0.05)}|rc{rc:.2f}"
+
+
+def time_forces(grid, sched, cs, coord, ws, reps=5, warmup=2) -> float:
+    """Median-free average ms of one lc_compute_forces over `reps` calls."""
+    for _ in range(warmup):
+        lc.compute_forces(grid, sched, cs, coord, ws)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lc.compute_forces(grid, sched, cs, coord, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
+             reps: int = 5, use_cache: bool = True) -> dict:
+    """Pick grid, schedule kind and block shape for one box.
+
+    pos: (3, N) float64 cuda tensor.  Returns {"grid": {...}, "kind": str,
+    "block": [x, y, z], "ms": float, "trials": [...]}."""
+    n = pos.shape[1]
+    key = box_key(n, L, rc) + ("|atomics" if allow_atomics else "")
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        return cache[key]
+    kinds = BOX_KINDS_CONFLICT_FREE + (("atomic_tile",) if allow_atomics else ())
+    trials = []
+    best = None
+    for gopt in GRIDS:
+        try:
+            grid = lc.Grid(L, rc, gopt["extra"], gopt["even"])
+        except lc.LCError:
+            continue
+        ws = lc.Workspace(n, grid.ncell)
+        cs, perm, coord = lc.build_cells(grid, pos, ws)
+        for kind in kinds:
+            for block in BLOCKS:
+                try:
+                    sched = lc.Schedule(grid, kind, block=block)
+                except lc.LCError:
+                    continue
+                ms = time_forces(grid, sched, cs, coord, ws, reps=reps)
+                ws.clear_status()
+                rec = {"grid": dict(gopt), "kind": kind, "block": list(block), "ms": ms,
+                       "nc": list(grid.nc)}
+                trials.append(rec)
+                if best is None or ms < best["ms"]:
+                    best = rec
+                sched.close()
+        ws.close()
+    if best is None:
+        raise lc.LCError(-1, "autotune: no valid configuration")
+    out = dict(best)
+    out["trials"] = trials
+    if use_cache:
+        cache[key] = out
+        _store_cache(cache)
+    return out
+
+
+def tune_batch(grids, ns, pos_all: torch.Tensor, reps: int = 5) -> dict:
+    """Pick the box split (auto: whole-box work-groups where they fit, or
+    blocks everywhere) and persistent vs one-group-per-work-group launch for a
+    batch.  Returns {"modes": str, "persistent": bool, "ms": float,
+    "trials": [...]}."""
+    trials = []
+    best = None
+    for modes in ("auto", "blocks"):
+        batch = lc.Batch(grids, ns, None if modes == "auto" else ["blocks"] * len(ns))
+        info = batch.info()
+        ws = lc.Workspace(info["ntot"], info["ncell"])
+        cs, perm, coord = batch.build_cells(pos_all, ws)
+        F = torch.empty((3, info["ntot"]), dtype=torch.int64, device=pos_all.device)
+        ew = torch.empty((len(ns), 3), dtype=torch.int64, device=pos_all.device)
+        for persistent in (True, False):
+            for _ in range(2):
+                batch.forces(cs, coord, ws, F, ew, persistent)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                batch.forces(cs, coord, ws, F, ew, persistent)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            rec = {"modes": modes, "persistent": persistent, "ms": ms,
+                   "nwhole": info["nwhole"], "ngroup": info["ngroup"]}
+            trials.append(rec)
+            if best is None or ms < best["ms"]:
+                best = rec
+        batch.close()
+        ws.close()
+    out = dict(best)
+    out["trials"] = trials
+    return out

@@ -82,6 +82,7 @@ struct lc_workspace {
     int32_t *tmpi = nullptr;     // N staging for ids
     long long *pbuf = nullptr;   // replica partial sums (buffer + reduce)
     int64_t pbuf_elems = 0;
+    int32_t max_per_cell = 0;    // tile sizing hint (0: mean density)
 };
 
 struct lc_schedule {
@@ -988,7 +989,8 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     const double mean = g->ncell > 0 ? (double)n / (double)g->ncell : 0.0;
     const bool ff = s->h.compact && precision == LC_PREC_FP32 &&
                     (s->h.write_mode == 0 || s->h.write_mode == 3);
-    const double need = mean * s->h.max_cells * 1.35;
+    const double need = ws->max_per_cell > 0 ? (double)ws->max_per_cell * s->h.max_cells * 0.8
+                                             : mean * s->h.max_cells * 1.35;
     int cap;
     if (ff)
         cap = need <= 768 ? 768 : (need <= 1024 ? 1024 : 2048);
@@ -1192,6 +1194,12 @@ extern "C" int lc_workspace_create(int64_t max_n, int64_t max_cells, lc_workspac
     return LC_OK;
 }
 
+extern "C" int lc_workspace_set_tile_hint(lc_workspace *ws, int32_t max_per_cell) {
+    if (!ws || max_per_cell < 0) return fail(LC_EINVAL, "lc_workspace_set_tile_hint");
+    ws->max_per_cell = max_per_cell;
+    return LC_OK;
+}
+
 extern "C" int lc_workspace_clear_status(lc_workspace *ws, void *stream) {
     if (!ws) return fail(LC_EINVAL, "null workspace");
     return fill32((int *)ws->flags, 1, (hipStream_t)stream);
@@ -1235,12 +1243,17 @@ extern "C" int lc_gather(const int32_t *perm, int64_t n, const double *in3, doub
 
 extern "C" int lc_make_schedule(const lc_grid *g, int kind, const int8_t *offsets, int n,
                                 lc_schedule **out) {
+    return lc_make_schedule_ex(g, kind, offsets, n, nullptr, out);
+}
+
+extern "C" int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *offsets, int n,
+                                   const int32_t *block_min, lc_schedule **out) {
     if (!g || !out) return fail(LC_EINVAL, "lc_make_schedule: null argument");
     if (kind < 0 || kind >= LC_SCHED_COUNT) return fail(LC_EINVAL, "unknown schedule kind %d", kind);
     lc_schedule *s = new lc_schedule();
     for (int d = 0; d < 3; ++d) s->nc[d] = g->nc[d];
     std::string err;
-    int rc = lcs::build_schedule(g->nc, kind, offsets, n, s->h, err);
+    int rc = lcs::build_schedule(g->nc, kind, offsets, n, s->h, err, block_min);
     if (rc) {
         delete s;
         return fail(rc, "lc_make_schedule: %s", err.c_str());

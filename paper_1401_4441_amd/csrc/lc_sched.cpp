@@ -270,7 +270,16 @@ std::vector<int> axis_blocks(int n, int minsize) {
 }  // namespace
 
 int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
-                   int n, HostSchedule &hs, std::string &err) {
+                   int n, HostSchedule &hs, std::string &err, const int32_t *block_min) {
+    int32_t bmin[3] = {1, 2, 2};
+    if (block_min) {
+        for (int d = 0; d < 3; ++d) bmin[d] = block_min[d];
+        if (bmin[0] < 1 || bmin[1] < 2 || bmin[2] < 2 || bmin[0] > 64 || bmin[1] > 64 ||
+            bmin[2] > 64) {
+            err = "block sizes must be >= {1, 2, 2} (the stencil reach) and <= 64";
+            return LC_EINVAL;
+        }
+    }
     hs = HostSchedule();
     hs.kind = kind;
     hs.grp_task.push_back(0);
@@ -283,7 +292,7 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
     if (kind == LC_SCHED_BLOCK8 || kind == LC_SCHED_ATOMIC_TILE || kind == LC_SCHED_BUFFER) {
         hs.write_mode = kind == LC_SCHED_BLOCK8 ? 0 : (kind == LC_SCHED_ATOMIC_TILE ? 1 : 3);
         std::vector<int> bs[3];
-        for (int d = 0; d < 3; ++d) bs[d] = axis_blocks(nc[d], d == 0 ? 1 : 2);
+        for (int d = 0; d < 3; ++d) bs[d] = axis_blocks(nc[d], bmin[d]);
         const int nb[3] = {(int)bs[0].size() - 1, (int)bs[1].size() - 1,
                            (int)bs[2].size() - 1};
         const int ncol[3] = {nb[0] > 1 ? 2 : 1, nb[1] > 1 ? 2 : 1, nb[2] > 1 ? 2 : 1};

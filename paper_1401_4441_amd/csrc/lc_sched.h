@@ -77,8 +77,12 @@ constexpr int kLevelGroupTasks = 16;
 
 // Build the schedule of `kind` on grid `nc` (LC_SCHED_*).  Returns 0 or a
 // negative LC_E* code with `err` set.
+// block_min (may be NULL): smallest block per axis for the block kinds
+// (default {1, 2, 2}; at least 1 along x and 2 along y and z, the stencil's
+// reach on each side).
 int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
-                   int n, HostSchedule &hs, std::string &err);
+                   int n, HostSchedule &hs, std::string &err,
+                   const int32_t *block_min = nullptr);
 
 // Every phase's work-groups write pairwise disjoint cells (required for
 // plain read-modify-write).  Returns true when valid.

@@ -66,10 +66,12 @@ SYMBOLS = {
     "lc_workspace_create": ([I64, I64, P], INT),
     "lc_workspace_destroy": ([P], None),
     "lc_workspace_clear_status": ([P, P], INT),
+    "lc_workspace_set_tile_hint": ([P, ctypes.c_int32], INT),
     "lc_workspace_status": ([P, P, P], INT),
     "lc_build_cells": ([P, P, I64, P, P, P, P, P], INT),
     "lc_gather": ([P, I64, P, P, P, P, P], INT),
     "lc_make_schedule": ([P, INT, P, INT, P], INT),
+    "lc_make_schedule_ex": ([P, INT, P, INT, P, P], INT),
     "lc_schedule_info_get": ([P, P], INT),
     "lc_schedule_free": ([P], None),
     "lc_schedule_plan": ([P, INT, P, INT, P], INT),
@@ -177,6 +179,9 @@ class Workspace:
     def clear_status(self, stream=None):
         _chk(lib().lc_workspace_clear_status(self._h, _stream(stream)))
 
+    def set_tile_hint(self, max_per_cell: int):
+        _chk(lib().lc_workspace_set_tile_hint(self._h, int(max_per_cell)))
+
     def status(self, stream=None) -> int:
         v = ctypes.c_uint32(0)
         _chk(lib().lc_workspace_status(self._h, _stream(stream), ctypes.byref(v)))
@@ -195,7 +200,7 @@ class Workspace:
 
 
 class Schedule:
-    def __init__(self, grid: Grid, kind, offsets=None):
+    def __init__(self, grid: Grid, kind, offsets=None, block=None):
         if isinstance(kind, str):
             kind = KINDS[kind]
         self._h = ctypes.c_void_p()
@@ -207,8 +212,15 @@ class Schedule:
             op, n = ctypes.c_void_p(arr.ctypes.data), arr.shape[0]
         else:
             op, n = None, 0
-        _chk(lib().lc_make_schedule(grid.ptr, int(kind), op, int(n),
-                                    ctypes.byref(self._h)))
+        if block is not None:
+            self._block = (ctypes.c_int32 * 3)(*[int(x) for x in block])
+            bp = ctypes.cast(self._block, P)
+        else:
+            bp = None
+        self.kind = int(kind)
+        self.block = tuple(block) if block is not None else None
+        _chk(lib().lc_make_schedule_ex(grid.ptr, int(kind), op, int(n), bp,
+                                       ctypes.byref(self._h)))
 
     @property
     def ptr(self):
@@ -259,7 +271,7 @@ def validate_phases(ncell: int, phase_grp, grp_foot, foot_cells) -> None:
 
 
 def build_cells(grid: Grid, pos: torch.Tensor, ws: Workspace, cell_start=None,
-                perm=None, coord=None, stream=None):
+                perm=None, coord=None, stream=None, tile_hint: bool = True):
     """Counting sort into cells.  pos: (3, N) float64 cuda.  Returns
     (cell_start int32 [ncell+1], perm int32 [N], coord uint32-as-int32 (3, N))."""
     n = pos.shape[1]
@@ -272,6 +284,9 @@ def build_cells(grid: Grid, pos: torch.Tensor, ws: Workspace, cell_start=None,
         coord = torch.empty((3, n), dtype=torch.int32, device=dev)
     _chk(lib().lc_build_cells(grid.ptr, _p(pos), n, _p(cell_start), _p(perm),
                               _p(coord), ws.ptr, _stream(stream)))
+    if tile_hint:
+        # the largest cell sizes the LDS tile of the sweep (one small sync)
+        ws.set_tile_hint(int((cell_start[1:] - cell_start[:-1]).max().item()))
     return cell_start, perm, coord
 
 

@@ -109,40 +109,35 @@ def slab(n: int, rho_dense: float = 0.75, rho_gas: float = 0.02,
     """Inhomogeneous slab: dense FCC in the middle third along z, dilute FCC
     gas elsewhere, in a periodic cube of side L = (n / (rho_d/3 + 2 rho_g/3))^(1/3).
 
-    Both phases are FCC lattices at their own density (so no two particles
-    overlap), clipped to their region with a gap of ``gap`` at the
-    interfaces; the particle count is then trimmed or topped up from the gas
-    lattice to exactly ``n`` by a seeded choice.
-    """
+    The dense region gets round(rho_d * L^3 / 3) particles and the gas the
+    rest; each phase is a seeded random subset of an FCC lattice fitted to the
+    box that is at least as dense as required (so no two particles overlap),
+    with the gas kept ``gap`` away from the interfaces."""
     rng = np.random.default_rng(seed)
     L = (n / (rho_dense / 3.0 + 2.0 * rho_gas / 3.0)) ** (1.0 / 3.0)
     z0, z1 = L / 3.0, 2.0 * L / 3.0
+    n_dense = min(n, int(round(rho_dense * L ** 3 / 3.0)))
+    n_gas = n - n_dense
 
-    def lattice(rho):
-        a = (4.0 / rho) ** (1.0 / 3.0)
-        m = max(1, int(math.floor(L / a)))
-        a = L / m  # fit the lattice to the box exactly
-        return _fcc_sites(m, a)
+    def lattice(rho, inside, want):
+        m = max(1, int(math.ceil(L * (rho / 4.0) ** (1.0 / 3.0))))
+        while True:
+            sites = _fcc_sites(m, L / m)
+            sites = sites[inside(sites[:, 2])]
+            if sites.shape[0] >= want:
+                keep = np.sort(rng.choice(sites.shape[0], size=want, replace=False))
+                return sites[keep]
+            m += 1
 
-    dense = lattice(rho_dense)
-    dense = dense[(dense[:, 2] >= z0) & (dense[:, 2] < z1)]
-    gas = lattice(rho_gas)
-    gas = gas[(gas[:, 2] < z0 - gap) | (gas[:, 2] >= z1 + gap)]
-    n_gas_target = n - dense.shape[0]
-    if n_gas_target < 0:
-        keep = np.sort(rng.choice(dense.shape[0], size=n, replace=False))
-        sites = dense[keep]
-    else:
-        if n_gas_target > gas.shape[0]:
-            raise ValueError("slab: gas lattice too small for requested n")
-        keep = np.sort(rng.choice(gas.shape[0], size=n_gas_target, replace=False))
-        sites = np.concatenate([dense, gas[keep]], axis=0)
+    dense = lattice(rho_dense, lambda z: (z >= z0) & (z < z1), n_dense)
+    gas = lattice(rho_gas, lambda z: (z < z0 - gap) | (z >= z1 + gap), n_gas)
+    sites = np.concatenate([dense, gas], axis=0)
     sites = sites + rng.uniform(-jitter, jitter, size=sites.shape)
     Lv = np.array([L, L, L])
     pos = _wrap(np.ascontiguousarray(sites.T), Lv)
     return Box(pos=np.ascontiguousarray(pos), L=Lv, rc=rc, seed=seed,
                meta={"kind": "slab", "rho_dense": rho_dense,
-                     "rho_gas": rho_gas, "n_dense": int(dense.shape[0])})
+                     "rho_gas": rho_gas, "n_dense": int(n_dense)})
 
 
 def boxes(count: int = 512, n_lo: int = 500, n_hi: int = 20000,

@@ -203,3 +203,15 @@ def test_grid_rejects_small_or_tight_cells():
         O.forces_lc_fx(u, b.L, b.rc, (2, 3, 3))
     with pytest.raises(O.OracleError):
         O.forces_lc_fx(u, b.L, b.L[0] / 3, (3, 3, 3))  # side == rc, no margin
+
+
+def test_subset_brute_force_matches_sweep():
+    """Per-particle brute force over all partners equals the link-cell sweep
+    bit for bit (the pin used for sampled checks at full size)."""
+    b = _tiny(500, seed=17)
+    u = O.canonical(b.pos, b.L)
+    Fq, _, _, npairs = O.forces_lc_fx(u, b.L, b.rc, O.grid_dims(b.L, b.rc))
+    idx = np.arange(0, b.n, 7)
+    Fs, nn = O.forces_subset_fx(u, b.L, b.rc, idx)
+    assert (Fs == Fq[:, idx]).all()
+    assert nn.sum() <= 2 * npairs
