@@ -52,6 +52,33 @@ H3 = ([(1, a, b) for b in (-1, 0, 1) for a in (-1, 0, 1)]
       + [(0, a, 1) for a in (-1, 0, 1)] + [(0, -1, 0)])
 
 
+def source_hash() -> str:
+    """sha256 over the HIP library sources: identifies the kernel build."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1401_4441_amd", "csrc")
+    for name in ("lc.hip", "lc_sched.cpp", "lc_sched.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_prefix: str, workload: str):
+    """HBM bytes per launch of the kernel from the committed rocprofv3 PMC
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when
+    the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_sweep_{workload}_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256") != source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel_prefix)
+    return None if k is None else k["bytes_per_launch"]
+
+
 def candidate_pairs(cell_start: np.ndarray, nc) -> int:
     """Candidate pairs the half-stencil sweep visits: n_c(n_c-1)/2 per cell
     plus n_c * n_{c+d} per cell and half-stencil offset d."""
@@ -73,7 +100,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the baseline schedules (atomics, paper orders)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 64 MiB device copy three times (the reference "
+                         "that scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        x = torch.ones(64 * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 4, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; "
                           "--gpus must be 1 (multi-GPU sharding is design-only)"}))
@@ -170,7 +209,11 @@ def main():
             "peak": VALU_PEAK_TOPS,
             "unit": "Tops/s (VALU lane-ops)",
             "frac": achieved_tops / VALU_PEAK_TOPS,
-            "traffic": None,
+            "traffic": measured_traffic(f"k_sweep_wmode{sched.info()['write_mode']}", args.workload),
+            "traffic_source": f"profiles/k_sweep_{args.workload}_traffic.json (rocprofv3 --pmc "
+                              "FETCH_SIZE / WRITE_SIZE, scaled by a 64 MiB copy); null if the "
+                              "kernel changed since",
+            "source_sha256": source_hash(),
             "kernel": "k_sweep",
             "kernel_ms_per_step": sweep_ms,
             "launches_per_step": nphase,

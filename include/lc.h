@@ -245,6 +245,22 @@ int lc_serialization_degree(const int32_t dims[3], int kind,
                             const int8_t *offsets, int n, int64_t *level_hist,
                             int64_t hist_len, lc_sd_result *out);
 
+/* [host only] Weighted critical path (relaxes the equal-duration assumption
+ * of Sec. V): task (A, B) lasts n_A * n_B, an intra task n_A (n_A - 1) / 2,
+ * with cell_counts [host] int32 per cell (x fastest, as lc_build_cells
+ * orders cells).  Same creation orders as lc_serialization_degree.
+ * work = sum of durations, cp = weighted longest path, S = work / cp. */
+typedef struct lc_wsd_result {
+    int64_t tasks;
+    double work;
+    double cp;
+    double speedup;
+} lc_wsd_result;
+int lc_serialization_degree_weighted(const int32_t dims[3], int kind,
+                                     const int8_t *offsets, int n,
+                                     const int32_t *cell_counts,
+                                     lc_wsd_result *out);
+
 /* ---- a4-a6: force sweep ------------------------------------------------- */
 
 #define LC_PREC_FP32 0 /* canonical FP32 pair arithmetic (bit-exact)        */

@@ -70,10 +70,11 @@ def lib():
         L.orc_verlet_fx.argtypes = [i64, P, P, P, f64, P, P, ctypes.c_int, f64,
                                     ctypes.c_int, P, P]
         L.orc_forces_subset_fx.argtypes = [i64, P, P, f64, P, i64, P, P]
+        L.orc_dag_lc_weighted.argtypes = [ctypes.c_int, P, P, P, P, P]
         for name in ("orc_forces_brute_f64", "orc_forces_brute_fx",
                      "orc_forces_lc_fx", "orc_forces_lc_f64", "orc_lc_tasks",
                      "orc_dag_generic", "orc_dag_lc", "orc_verlet_fx",
-                     "orc_forces_subset_fx"):
+                     "orc_forces_subset_fx", "orc_dag_lc_weighted"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -323,6 +324,19 @@ def dag_lc(A, B):
     _check(lib().orc_dag_lc(len(A), _ptr(A), _ptr(B), _ptr(depth),
                             ctypes.byref(cp)), "dag_lc")
     return depth, int(cp.value)
+
+
+def dag_lc_weighted(A, B, w):
+    """Weighted critical path by the definition (every earlier task that
+    shares a cell must finish first).  Returns (finish times, cp)."""
+    A = np.ascontiguousarray(A, dtype=np.int32)
+    B = np.ascontiguousarray(B, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    fin = np.empty(len(A))
+    cp = ctypes.c_double(0.0)
+    _check(lib().orc_dag_lc_weighted(len(A), _ptr(A), _ptr(B), _ptr(w), _ptr(fin),
+                                     ctypes.byref(cp)), "dag_lc_weighted")
+    return fin, float(cp.value)
 
 
 IN, OUT, INOUT = 0, 1, 2

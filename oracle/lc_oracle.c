@@ -544,6 +544,27 @@ int orc_dag_lc(int T, const int32_t *cellA, const int32_t *cellB,
     return ORC_OK;
 }
 
+/* Weighted critical path by the same definition: task t can finish no
+ * earlier than w[t] after every earlier task sharing a cell has finished;
+ * returns the largest finish time in *cp. */
+int orc_dag_lc_weighted(int T, const int32_t *cellA, const int32_t *cellB,
+                        const double *w, double *finish, double *cp)
+{
+    double best = 0.0;
+    for (int t = 0; t < T; ++t) {
+        double start = 0.0;
+        for (int s = 0; s < t; ++s) {
+            int share = cellA[s] == cellA[t] || cellA[s] == cellB[t] ||
+                        cellB[s] == cellA[t] || cellB[s] == cellB[t];
+            if (share && finish[s] > start) start = finish[s];
+        }
+        finish[t] = start + w[t];
+        if (finish[t] > best) best = finish[t];
+    }
+    *cp = best;
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------- */
 /* 6. velocity Verlet                                                        */
 /* ------------------------------------------------------------------------- */

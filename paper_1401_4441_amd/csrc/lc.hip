@@ -1405,6 +1405,43 @@ extern "C" int lc_serialization_degree(const int32_t dims[3], int kind, const in
     return LC_OK;
 }
 
+extern "C" int lc_serialization_degree_weighted(const int32_t dims[3], int kind,
+                                                const int8_t *offsets, int n,
+                                                const int32_t *cell_counts, lc_wsd_result *out) {
+    if (!dims || !out || !cell_counts) return fail(LC_EINVAL, "null argument");
+    for (int d = 0; d < 3; ++d)
+        if (dims[d] < 1) return fail(LC_EINVAL, "dims must be >= 1");
+    if (kind != LC_SCHED_LEX && kind != LC_SCHED_OPT && kind != LC_SCHED_BEST &&
+        kind != LC_SCHED_BAD && kind != LC_SCHED_LOOPEX && kind != LC_SCHED_CUSTOM)
+        return fail(LC_EINVAL, "kind %d has no creation order", kind);
+    const bool two_d = dims[2] == 1;
+    std::vector<lcs::Offset> order;
+    std::string err;
+    if (!lcs::stencil_order(kind, two_d, offsets, n, order, err))
+        return fail(LC_EINVAL, "serialization_degree_weighted: %s", err.c_str());
+    std::vector<int32_t> A, B;
+    if (kind == LC_SCHED_LOOPEX) {
+        if (!lcs::loopex_tasks(dims, order, A, B))
+            return fail(LC_EINVAL, "loop exchange needs even dims");
+    } else {
+        lcs::basic_tasks(dims, order, A, B);
+    }
+    std::vector<double> w(A.size());
+    double work = 0.0;
+    for (size_t t = 0; t < A.size(); ++t) {
+        const double na = cell_counts[A[t]], nb = cell_counts[B[t]];
+        w[t] = A[t] == B[t] ? 0.5 * na * (na - 1.0) : na * nb;
+        work += w[t];
+    }
+    const int64_t ncell = (int64_t)dims[0] * dims[1] * dims[2];
+    const double cp = lcs::task_levels_weighted(ncell, A, B, w);
+    out->tasks = (int64_t)A.size();
+    out->work = work;
+    out->cp = cp;
+    out->speedup = cp > 0.0 ? work / cp : 0.0;
+    return LC_OK;
+}
+
 extern "C" int lc_compute_forces(const lc_grid *g, const lc_schedule *s, const int32_t *cell_start,
                                  const uint32_t *coord, int64_t n, int64_t *F, int64_t *ew,
                                  int precision, lc_workspace *ws, void *stream) {

@@ -200,6 +200,19 @@ int64_t task_levels(int64_t ncell, const std::vector<int32_t> &A,
     return cp;
 }
 
+double task_levels_weighted(int64_t ncell, const std::vector<int32_t> &A,
+                            const std::vector<int32_t> &B, const std::vector<double> &w) {
+    std::vector<double> last((size_t)ncell, 0.0);
+    double cp = 0.0;
+    for (size_t t = 0; t < A.size(); ++t) {
+        const double f = w[t] + std::max(last[(size_t)A[t]], last[(size_t)B[t]]);
+        last[(size_t)A[t]] = f;
+        last[(size_t)B[t]] = f;
+        cp = std::max(cp, f);
+    }
+    return cp;
+}
+
 int delta_rule(const std::vector<Offset> &order) {
     auto pos = [&](const Offset &o) -> int {
         for (size_t k = 0; k < order.size(); ++k)

@@ -41,6 +41,11 @@ int64_t task_levels(int64_t ncell, const std::vector<int32_t> &A,
                     const std::vector<int32_t> &B,
                     std::vector<int32_t> &level);
 
+// Weighted version: finish[t] = w[t] + max(finish of the last task on A,
+// on B); returns the largest finish time.
+double task_levels_weighted(int64_t ncell, const std::vector<int32_t> &A,
+                            const std::vector<int32_t> &B, const std::vector<double> &w);
+
 // Stencil displacement Delta of an evaluation order over a periodic row.
 // Stencils at x and x + e_x are both full chains through their centre cell;
 // stencil x+1 touches cell x+d (d in stencil, d - e_x in stencil) with its

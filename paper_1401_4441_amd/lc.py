@@ -48,6 +48,11 @@ class _SchedInfo(ctypes.Structure):
                 ("write_mode", ctypes.c_int32), ("max_replicas", ctypes.c_int32)]
 
 
+class _WSD(ctypes.Structure):
+    _fields_ = [("tasks", ctypes.c_int64), ("work", ctypes.c_double),
+                ("cp", ctypes.c_double), ("speedup", ctypes.c_double)]
+
+
 class _SD(ctypes.Structure):
     _fields_ = [("tasks", ctypes.c_int64), ("cp", ctypes.c_int64),
                 ("speedup", ctypes.c_double), ("degree", ctypes.c_double),
@@ -77,6 +82,7 @@ SYMBOLS = {
     "lc_schedule_plan": ([P, INT, P, INT, P], INT),
     "lc_validate_phases": ([I64, ctypes.c_int32, P, P, P], INT),
     "lc_serialization_degree": ([P, INT, P, INT, P, I64, P], INT),
+    "lc_serialization_degree_weighted": ([P, INT, P, INT, P, P], INT),
     "lc_compute_forces": ([P, P, P, P, I64, P, P, INT, P, P], INT),
     "lc_compute_forces_profiled": ([P, P, P, P, I64, P, P, INT, P, P, P, P], INT),
     "lc_verlet_step": ([P, P, P, P, P, I64, P, P, P, P, ctypes.c_double, INT,
@@ -368,6 +374,26 @@ def kinetic_energy(vel: torch.Tensor, ws: Workspace, out=None, stream=None):
         out = torch.empty(1, dtype=torch.int64, device=vel.device)
     _chk(lib().lc_kinetic_energy(_p(vel), n, _p(out), ws.ptr, _stream(stream)))
     return out
+
+
+def serialization_degree_weighted(dims, kind, cell_counts, offsets=None) -> dict:
+    """Host-only: critical path with task durations n_A n_B (intra:
+    n_A (n_A - 1) / 2) from per-cell particle counts (x fastest)."""
+    import numpy as np
+    if isinstance(kind, str):
+        kind = KINDS[kind]
+    d = (ctypes.c_int32 * 3)(*[int(x) for x in dims])
+    cc = np.ascontiguousarray(np.asarray(cell_counts, dtype=np.int32))
+    if offsets is not None:
+        arr = np.ascontiguousarray(np.asarray(offsets, dtype=np.int8).reshape(-1, 3))
+        op, n = ctypes.c_void_p(arr.ctypes.data), arr.shape[0]
+    else:
+        op, n = None, 0
+    r = _WSD()
+    _chk(lib().lc_serialization_degree_weighted(ctypes.cast(d, P), int(kind), op, int(n),
+                                                ctypes.c_void_p(cc.ctypes.data),
+                                                ctypes.byref(r)))
+    return {k: getattr(r, k) for k, _ in _WSD._fields_}
 
 
 def serialization_degree(dims, kind, offsets=None, hist_len: int = 0) -> dict:

@@ -138,3 +138,20 @@ def test_loopex_needs_even_grid():
     g = lc.Grid((17.0998 * 7 / 6,) * 3, 2.5)  # 7 cells per axis
     with pytest.raises(lc.LCError):
         lc.schedule_plan(g, "loopex")
+
+
+def test_weighted_cp_matches_oracle():
+    """Library weighted critical path == the oracle's definition, for random
+    cell occupancies."""
+    rng = np.random.default_rng(4)
+    for dims, kind, order, loopex in (((6, 4, 1), "lex", O.ORDER2_NAIVE, False),
+                                      ((5, 4, 3), "opt", O.ORDER3_OPT, False),
+                                      ((4, 4, 4), "loopex", O.ORDER3_LEX, True)):
+        counts = rng.integers(0, 30, size=int(np.prod(dims))).astype(np.int32)
+        r = lc.serialization_degree_weighted(dims, kind, counts)
+        A, B = O.lc_tasks(dims, order, loopex)
+        w = np.where(A == B, 0.5 * counts[A] * (counts[A] - 1.0),
+                     counts[A].astype(float) * counts[B])
+        _, cp = O.dag_lc_weighted(A, B, w)
+        assert r["cp"] == pytest.approx(cp)
+        assert r["work"] == pytest.approx(w.sum())

@@ -182,3 +182,20 @@ def test_loop_exchange_colouring():
 def test_loopex_rejects_odd_dims():
     with pytest.raises(O.OracleError):
         O.lc_tasks((5, 4, 1), O.ORDER2_OPT, loopex=True)
+
+
+def test_weighted_dag_reduces_to_unit():
+    """With unit durations the weighted critical path is the task count one;
+    scaling all durations scales it."""
+    import numpy as np
+    A, B = O.lc_tasks((6, 4, 1), O.ORDER2_NAIVE)
+    _, cp = O.dag_lc(A, B)
+    _, cpw = O.dag_lc_weighted(A, B, np.ones(len(A)))
+    assert cpw == cp
+    _, cpw3 = O.dag_lc_weighted(A, B, 3.0 * np.ones(len(A)))
+    assert cpw3 == 3 * cp
+    # one heavy task on the critical chain adds its extra duration
+    w = np.ones(len(A))
+    w[0] = 10.0
+    _, cpw10 = O.dag_lc_weighted(A, B, w)
+    assert cpw10 == cp + 9
