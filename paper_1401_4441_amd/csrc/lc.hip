@@ -489,7 +489,8 @@ __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, 
 template <int CAP, int WMODE, bool FF>
 struct SweepLDS {
     uint4 u[CAP];                                           // box fractions
-    float4 f[FF ? CAP : 1];                                 // filter coordinates
+    float4 f[FF ? CAP + 1 : 1];  // filter coordinates (+1: the look-ahead
+                                 // load of an empty task may touch slot CAP)
     long long acc[WMODE == 2 ? 1 : 3][WMODE == 2 ? 1 : CAP];  // int64 forces
     int fg[kMaxF];          // global first slot of each footprint cell
     int fl[kMaxF + 1];      // local first slot (prefix over the footprint)
@@ -567,9 +568,9 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
         w_sum += qw;
         p_cnt += 1;
         if constexpr (STAGED && WMODE != 2) {
-            atomicAdd((unsigned long long *)&sh.acc[0][il], (unsigned long long)(-qx));
-            atomicAdd((unsigned long long *)&sh.acc[1][il], (unsigned long long)(-qy));
-            atomicAdd((unsigned long long *)&sh.acc[2][il], (unsigned long long)(-qz));
+            atomicSub((unsigned long long *)&sh.acc[0][il], (unsigned long long)qx);
+            atomicSub((unsigned long long *)&sh.acc[1][il], (unsigned long long)qy);
+            atomicSub((unsigned long long *)&sh.acc[2][il], (unsigned long long)qz);
             atomicAdd((unsigned long long *)&sh.acc[0][jl], (unsigned long long)qx);
             atomicAdd((unsigned long long *)&sh.acc[1][jl], (unsigned long long)qy);
             atomicAdd((unsigned long long *)&sh.acc[2][jl], (unsigned long long)qz);
@@ -635,17 +636,29 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
         // i runs over cell A; an intra task keeps each unordered pair once
         // (i before j inside the cell)
         if constexpr (STAGED && FF) {
-            const int kend = valid ? (intra ? jj : (ta >> 16)) : 0;
-            const int kmax = wave_max32(kend);
+            // diagonal order (see below) with the float filter; the next i's
+            // coordinates are loaded while the current pair is tested
+            const int na = valid ? (ta >> 16) : 0;
+            const int kmax = wave_max32(na);
             const float4 fj = valid ? sh.f[jl] : make_float4(0.f, 0.f, 0.f, 0.f);
-            float4 fn = sh.f[min(aoff, CAP - 1)];
+            // i runs over [aoff, aoff + na) starting at aoff + (jj mod na) and
+            // wrapping; an intra task keeps i < j (local index below jj)
+            const int iend = aoff + na;
+            const int ilim = intra ? aoff + jj : iend;
+            int il = na > 0 ? aoff + jj % na : aoff;
+            float4 fn = sh.f[il];
             for (int k = 0; k < kmax; ++k) {
                 const float4 fi = fn;
-                fn = sh.f[min(aoff + k + 1, CAP - 1)];
+                const bool act = (k < na) & (il < ilim);
+                const int icur = il;
+                il = il + 1 == iend ? aoff : il + 1;
+                fn = sh.f[il];
+                // candidate filter: an enlarged-cutoff superset test, so
+                // fused multiply-adds are fine here (the exact canonical
+                // test is repeated when the pair is evaluated)
                 const float dx = fj.x - fi.x, dy = fj.y - fi.y, dz = fj.z - fi.z;
-                float r2 = dx * dx + dy * dy;
-                r2 = r2 + dz * dz;
-                push(k < kend && r2 < pp.rc2f, aoff + k, jbits);
+                const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                push(act & (r2 < pp.rc2f), icur, jbits);
             }
         } else {
             // diagonal order: lane jj visits i = (k + jj) mod na, so lanes of
@@ -918,6 +931,7 @@ static int launch_sweep(int cap, int wmode, bool f64, bool ff, const SweepArgs &
     }
     if (ff) {
         if (wmode == 0) return launch_sweep_c<0, false, true>(cap, a, ngroups, st);
+        if (wmode == 1) return launch_sweep_c<1, false, true>(cap, a, ngroups, st);
         if (wmode == 3) return launch_sweep_c<3, false, true>(cap, a, ngroups, st);
     }
     if (wmode == 0) return launch_sweep_c<0, false, false>(cap, a, ngroups, st);
@@ -987,8 +1001,7 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     a.pp = pair_params(g);
     // LDS tile: expected particles of the largest footprint with headroom
     const double mean = g->ncell > 0 ? (double)n / (double)g->ncell : 0.0;
-    const bool ff = s->h.compact && precision == LC_PREC_FP32 &&
-                    (s->h.write_mode == 0 || s->h.write_mode == 3);
+    const bool ff = s->h.compact && precision == LC_PREC_FP32 && s->h.write_mode != 2;
     const double need = ws->max_per_cell > 0 ? (double)ws->max_per_cell * s->h.max_cells * 0.8
                                              : mean * s->h.max_cells * 1.35;
     int cap;
