@@ -173,6 +173,14 @@ def main():
     status = ws.status()
     value = pairs / (ms * 1e-3)
 
+    # ---- the 1e-5 gate: FP32 pair math (int64 sums) against FP64 pair
+    # arithmetic on the same box fractions and pair set
+    F64, ew64 = lc.compute_forces(g, sched, cs, coord, ws, "fp64")
+    F32, ew32 = lc.compute_forces(g, sched, cs, coord, ws, "fp32")
+    d = (F32 - F64).double()
+    err_norm = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(F64.double()))
+    err_energy = abs(int(ew32[0]) - int(ew64[0])) / abs(int(ew64[0]))
+
     # ---- dominant kernel: the sweep phases, HIP events around each launch
     sweep_ms = []
     for _ in range(5):
@@ -203,6 +211,9 @@ def main():
         "config": {"workload": w["desc"], "n": box.n, "cells": list(g.nc),
                    "schedule": best, "schedule_trial_ms": trial, "pairs_in_cutoff": pairs,
                    "candidate_pairs": ncand, "status_flags": status},
+        "accuracy": {"force_normwise_rel_err_vs_fp64": err_norm,
+                     "energy_rel_err_vs_fp64": err_energy, "gate": 1e-5,
+                     "pass": err_norm <= 1e-5 and err_energy <= 1e-5},
         "roofline": {
             "bound": "alu",
             "achieved": achieved_tops,
@@ -236,6 +247,10 @@ def main():
                            "time_vs_headline": kms / ms}
             s.close()
         out["schedules"] = extra
+        out["conflict_free_vs_atomics"] = {
+            "speedup_over_atomic_pair": extra["atomic_pair"]["ms_per_step"] / ms,
+            "speedup_over_atomic_tile": extra["atomic_tile"]["ms_per_step"] / ms,
+            "target": ">= 3x over the plain atomics baseline (atomic_pair)"}
         # the paper's serialisation degree on this grid (host computation)
         sd = {k: lc.serialization_degree(g.nc, k) for k in ("lex", "opt", "best", "bad", "loopex")}
         out["serialization_degree"] = {k: {"cp": v["cp"], "S": v["speedup"],
