@@ -103,10 +103,13 @@ constexpr int kPartSlots = 1024;    // spread slots for global int64 sums
 constexpr int kWG = 512;            // threads per sweep work-group
 constexpr int kNW = kWG / 64;       // waves per sweep work-group
 constexpr int kQ = 128;             // per-wave pair queue (>= 64 + 63)
+constexpr int kFPad = 64;           // filter rows past the footprint (see SweepLDS)
+constexpr int kFFCell = kFPad - 4;  // largest cell the filter path stages
 constexpr int kMaxT = lcs::kMaxGroupTasks;
 constexpr int kMaxF = lcs::kMaxGroupCells;
 
 static_assert(kMaxT <= kWG && kMaxF <= kWG, "tables scanned one item per thread");
+static_assert(kMaxF <= 256, "footprint cell of a particle is stored in one byte");
 
 struct PairParams {
     float s[3];    // (float)(L * 2^-32)
@@ -489,17 +492,22 @@ __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, 
 template <int CAP, int WMODE, bool FF>
 struct SweepLDS {
     uint4 u[CAP];                                           // box fractions
-    float4 f[FF ? CAP + 1 : 1];  // filter coordinates (+1: the look-ahead
-                                 // load of an empty task may touch slot CAP)
+    // filter coordinates; the filter reads rows aoff .. aoff + kmax + 3 for
+    // every lane (kmax: the wave's largest cell A), so it runs past the
+    // footprint by less than kFPad when no cell holds more than kFFCell
+    float4 f[FF ? CAP + kFPad : 1];
     long long acc[WMODE == 2 ? 1 : 3][WMODE == 2 ? 1 : CAP];  // int64 forces
     int fg[kMaxF];          // global first slot of each footprint cell
     int fl[kMaxF + 1];      // local first slot (prefix over the footprint)
+    int frep[WMODE == 3 ? kMaxF : 1];  // replica slot of each footprint cell
+    uint8_t pc[CAP];        // footprint cell of each staged particle
     int ta[kMaxT];          // task: local first slot of A | (count of A << 16)
     int tb[kMaxT];          // task: local first slot of B, bit 31 = intra
     int tslot[kMaxT + 1];   // prefix of |B| over the tasks
     uint32_t q[kNW][kQ];    // per-wave queue of in-cutoff pairs (i | j << 16)
     long long red[kNW][3];
     int w[kNW + 1];
+    int big;  // a footprint cell holds more than kFFCell particles
 };
 
 // Global slot of a local footprint index.
@@ -540,7 +548,8 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
                                             const PairParams &pp, int f0, int nf, int nt,
                                             int nslot, long long &e_sum, long long &w_sum,
                                             long long &p_cnt, uint32_t &ovf) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t n = a.n;
     uint32_t *q = sh.q[wave];
     int qn = 0;  // wave-uniform queue length
@@ -580,8 +589,8 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             int64_t gi = foot_gidx(sh, nf, il), gj = foot_gidx(sh, nf, jl);
             unsigned long long *Fi = (unsigned long long *)a.F, *Fj = Fi;
             if constexpr (WMODE == 3) {
-                const int ri = a.foot_rep[f0 + foot_cell(sh, nf, il)];
-                const int rj = a.foot_rep[f0 + foot_cell(sh, nf, jl)];
+                const int ri = sh.frep[foot_cell(sh, nf, il)];
+                const int rj = sh.frep[foot_cell(sh, nf, jl)];
                 Fi = (unsigned long long *)a.pbuf + (int64_t)ri * 3 * n;
                 Fj = (unsigned long long *)a.pbuf + (int64_t)rj * 3 * n;
             }
@@ -594,15 +603,15 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
         }
     };
 
-    // queue an in-cutoff pair; evaluate 64 at a time
-    auto push = [&](bool in, int il, uint32_t jbits) {
-        const unsigned long long m = __ballot(in);
+    // queue an in-cutoff pair (m: the wave's ballot of in); evaluate 64 at
+    // a time
+    auto push_ent = [&](unsigned long long m, bool in, uint32_t ent) {
         if (in) {
             const int below = (int)__builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            q[qn + below] = (uint32_t)il | jbits;
+            q[qn + below] = ent;
         }
-        qn = __builtin_amdgcn_readfirstlane(qn + (int)__popcll(m));
+        qn += (int)__popcll(m);
         if (qn >= 64) {
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -616,16 +625,23 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         }
     };
+    auto push = [&](bool in, int il, uint32_t jbits) {
+        push_ent(__ballot(in), in, (uint32_t)il | jbits);
+    };
 
     for (int base = wave * 64; base < nslot; base += kNW * 64) {
         const int s = base + lane;
         const bool valid = s < nslot;
+        // task of the chunk's first slot (one wave-uniform search), then each
+        // lane steps forward to its own task (a chunk spans a few tasks)
         int lo = 0, hi = nt;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (sh.tslot[mid] <= s) lo = mid; else hi = mid;
+            if (sh.tslot[mid] <= base) lo = mid; else hi = mid;
         }
-        const int t = lo;
+        int t = __builtin_amdgcn_readfirstlane(lo);
+        const int slast = min(s, nslot - 1);
+        while (sh.tslot[t + 1] <= slast) ++t;
         const int jj = s - sh.tslot[t];
         const int bo = sh.tb[t];
         const bool intra = bo < 0;
@@ -636,29 +652,52 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
         // i runs over cell A; an intra task keeps each unordered pair once
         // (i before j inside the cell)
         if constexpr (STAGED && FF) {
-            // diagonal order (see below) with the float filter; the next i's
-            // coordinates are loaded while the current pair is tested
+            // Two stages per block of up to 32 i.  A tight float filter (an
+            // enlarged-cutoff superset test, so fused multiply-adds are fine
+            // here: the exact canonical test is repeated when the pair is
+            // evaluated) shifts one bit per candidate i into a mask, first i
+            // highest; all lanes of a task read the same row, which LDS
+            // broadcasts.  The set bits are then queued, each lane starting
+            // at its own bit so that a batch's i-side adds spread over
+            // addresses.
             const int na = valid ? (ta >> 16) : 0;
-            const int kmax = wave_max32(na);
+            const int a0 = valid ? aoff : 0;
+            const int kmax = __builtin_amdgcn_readfirstlane(wave_max32(na));
             const float4 fj = valid ? sh.f[jl] : make_float4(0.f, 0.f, 0.f, 0.f);
-            // i runs over [aoff, aoff + na) starting at aoff + (jj mod na) and
-            // wrapping; an intra task keeps i < j (local index below jj)
-            const int iend = aoff + na;
-            const int ilim = intra ? aoff + jj : iend;
-            int il = na > 0 ? aoff + jj % na : aoff;
-            float4 fn = sh.f[il];
-            for (int k = 0; k < kmax; ++k) {
-                const float4 fi = fn;
-                const bool act = (k < na) & (il < ilim);
-                const int icur = il;
-                il = il + 1 == iend ? aoff : il + 1;
-                fn = sh.f[il];
-                // candidate filter: an enlarged-cutoff superset test, so
-                // fused multiply-adds are fine here (the exact canonical
-                // test is repeated when the pair is evaluated)
-                const float dx = fj.x - fi.x, dy = fj.y - fi.y, dz = fj.z - fi.z;
-                const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-                push(act & (r2 < pp.rc2f), icur, jbits);
+            const int lim = intra ? min(jj, na) : na;  // intra: i before j
+            const uint32_t rot = (uint32_t)jj & 31u;
+            for (int k0 = 0; k0 < kmax; k0 += 32) {
+                const int kr = min(kmax - k0 + 3, 32) & ~3;  // rows read, uniform
+                const float4 *fa = &sh.f[a0 + k0];
+                uint32_t m = 0u;
+                for (int k = 0; k < kr; k += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const float4 fi = fa[k + u];
+                        const float dx = fj.x - fi.x, dy = fj.y - fi.y, dz = fj.z - fi.z;
+                        // r2 - rc2f: negative (sign bit set) inside the
+                        // enlarged cutoff; the sign bit is shifted into m
+                        const float t = __builtin_fmaf(
+                            dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, -pp.rc2f)));
+                        m = __builtin_amdgcn_alignbit(m, __float_as_uint(t), 31);
+                    }
+                }
+                // row k sits at bit kr - 1 - k; keep rows k < lim - k0
+                const int nv = lim - k0;
+                m = nv <= 0 ? 0u : nv >= kr ? m : m & ~((1u << (kr - nv)) - 1u);
+                m = __builtin_amdgcn_alignbit(m, m, rot);  // rotate right
+                // entry of the bit at (rotated) position p: (i | j << 16) with
+                // i = a0 + k0 + kr - 1 - ((p + rot) & 31), no borrow into j
+                const uint32_t ebase = (uint32_t)(a0 + k0 + kr - 1) | jbits;
+                for (;;) {
+                    const bool has = m != 0u;
+                    const unsigned long long bal = __ballot(has);
+                    if (!bal) break;
+                    const uint32_t e =
+                        ebase - (((uint32_t)__builtin_ctz(m | 0x80000000u) + rot) & 31u);
+                    m &= m - 1u;
+                    push_ent(bal, has, e);
+                }
             }
         } else {
             // diagonal order: lane jj visits i = (k + jj) mod na, so lanes of
@@ -701,11 +740,15 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
     int cnt = 0;
     if (tid < nf) {
         const int c = a.foot_cells[f0 + tid];
+        if constexpr (WMODE == 3) sh.frep[tid] = a.foot_rep[f0 + tid];
         const int gs = a.cell_start[c];
         cnt = a.cell_start[c + 1] - gs;
         sh.fg[tid] = gs;
     }
     int total;
+    if constexpr (FF) {
+        if (tid == 0) sh.big = 0;  // ordered before the scan's barriers
+    }
     const int lofs = block_scan_excl<kWG>(cnt, sh.w, total);
     if (tid < nf) sh.fl[tid] = lofs;
     if (tid == 0) sh.fl[nf] = total;
@@ -713,9 +756,15 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
         if (tid == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_OVERFLOW);
         return;
     }
-    const bool staged = total <= CAP;
-    if (!staged && tid == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_FALLBACK);
+    if constexpr (FF) {
+        if (cnt > kFFCell) sh.big = 1;
+    }
+    if (total <= CAP)  // footprint cell of every particle (nf <= 256)
+        for (int r = 0; r < cnt; ++r) sh.pc[lofs + r] = (uint8_t)tid;
     __syncthreads();
+    bool staged = total <= CAP;
+    if constexpr (FF) staged = staged && !sh.big;
+    if (!staged && tid == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_FALLBACK);
 
     // Stage the footprint: one particle per thread, all global loads in
     // flight together.  With plain write-back (WMODE 0) the accumulators
@@ -730,7 +779,8 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
             oz = a.coord[2 * n + g0];
         }
         for (int k = tid; k < total; k += kWG) {
-            const int64_t gi = foot_gidx(sh, nf, k);
+            const int f = sh.pc[k];
+            const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
             const uint32_t ux = a.coord[gi], uy = a.coord[n + gi], uz = a.coord[2 * n + gi];
             if constexpr (WMODE == 0) {
                 const long long fx = a.F[gi], fy = a.F[n + gi], fz = a.F[2 * n + gi];
@@ -753,7 +803,7 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
             for (int k = tid; k < total; k += kWG) {
                 const int f = foot_cell(sh, nf, k);
                 const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
-                long long *P = a.pbuf + (int64_t)a.foot_rep[f0 + f] * 3 * n;
+                long long *P = a.pbuf + (int64_t)sh.frep[f] * 3 * n;
                 P[gi] = 0;
                 P[n + gi] = 0;
                 P[2 * n + gi] = 0;
@@ -808,9 +858,9 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
     if constexpr (WMODE == 3) {
         if (!staged) return;
         for (int k = tid; k < total; k += kWG) {
-            const int f = foot_cell(sh, nf, k);
+            const int f = sh.pc[k];
             const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
-            long long *P = a.pbuf + (int64_t)a.foot_rep[f0 + f] * 3 * n;
+            long long *P = a.pbuf + (int64_t)sh.frep[f] * 3 * n;
             P[gi] = sh.acc[0][k];
             P[n + gi] = sh.acc[1][k];
             P[2 * n + gi] = sh.acc[2][k];
@@ -819,7 +869,8 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
         if (!staged) return;
         unsigned long long *F = (unsigned long long *)a.F;
         for (int k = tid; k < total; k += kWG) {
-            const int64_t gi = foot_gidx(sh, nf, k);
+            const int f = sh.pc[k];
+            const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
             for (int d = 0; d < 3; ++d) {
                 const unsigned long long v = (unsigned long long)sh.acc[d][k];
                 if constexpr (WMODE == 0)
