@@ -103,6 +103,7 @@ constexpr int kPartSlots = 1024;    // spread slots for global int64 sums
 constexpr int kWG = 512;            // threads per sweep work-group
 constexpr int kNW = kWG / 64;       // waves per sweep work-group
 constexpr int kQ = 128;             // per-wave pair queue (>= 64 + 63)
+constexpr int kWB0 = lcs::kMaxGroupCells;  // first thread of the write-back waves
 constexpr int kFPad = 64;           // filter rows past the footprint (see SweepLDS)
 constexpr int kFFCell = kFPad - 4;  // largest cell the filter path stages
 constexpr int kMaxT = lcs::kMaxGroupTasks;
@@ -110,6 +111,7 @@ constexpr int kMaxF = lcs::kMaxGroupCells;
 
 static_assert(kMaxT <= kWG && kMaxF <= kWG, "tables scanned one item per thread");
 static_assert(kMaxF <= 256, "footprint cell of a particle is stored in one byte");
+static_assert(kWB0 % 64 == 0 && kWB0 >= kMaxF && kWB0 + 64 <= kWG, "write-back waves");
 
 struct PairParams {
     float s[3];    // (float)(L * 2^-32)
@@ -724,26 +726,76 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
     if (lane < qn) eval(q[lane]);
 }
 
-// All work of one task group (see k_sweep).
-template <int CAP, int WMODE, bool F64, bool FF>
+// What a group's setup reads from global memory before its LDS work: the
+// group's task and footprint ranges, each thread's task entry and footprint
+// cell (with its replica slot and particle range).  The reads form a chain
+// of three dependent round trips (ranges; entries; cell starts); a
+// persistent work-group runs the chain for its next group while it works on
+// the current one.
+struct GroupPre {
+    int g, box;           // group, its box (batched launches)
+    int t0, nt, f0, nf;   // task and footprint ranges
+    int hv;               // ranges as loaded, one value per lane (see pre_head)
+    uint32_t ab;          // task entry of this thread (tid < nt)
+    int c, rep;           // footprint cell of this thread (-1: none), replica slot
+    int gs, ge;           // its particle range
+};
+
+// The ranges are read with one vector load (lanes 0-4 fetch the five
+// values), not scalar loads: a wait for scalar loads is also a wait for LDS,
+// so scalar prefetches would stall the current group's first barrier.
+__device__ __forceinline__ void pre_head(const SweepArgs &a, int g, GroupPre &p) {
+    const int lane = threadIdx.x & 63;
+    const int *src = lane == 1   ? a.grp_task + g + 1
+                     : lane == 2 ? a.grp_foot + g
+                     : lane == 3 ? a.grp_foot + g + 1
+                     : lane == 4 && a.grp_box ? a.grp_box + g
+                                              : a.grp_task + g;
+    p.g = g;
+    p.hv = *src;
+}
+
+__device__ __forceinline__ void pre_head_done(const SweepArgs &a, GroupPre &p) {
+    p.t0 = __builtin_amdgcn_readlane(p.hv, 0);
+    p.nt = __builtin_amdgcn_readlane(p.hv, 1) - p.t0;
+    p.f0 = __builtin_amdgcn_readlane(p.hv, 2);
+    p.nf = __builtin_amdgcn_readlane(p.hv, 3) - p.f0;
+    p.box = a.grp_box ? __builtin_amdgcn_readlane(p.hv, 4) : 0;
+}
+
+template <int WMODE>
+__device__ __forceinline__ void pre_foot(const SweepArgs &a, GroupPre &p) {
+    const int tid = threadIdx.x;
+    p.ab = tid < p.nt ? a.task_ab[p.t0 + tid] : 0u;
+    p.c = tid < p.nf ? a.foot_cells[p.f0 + tid] : -1;
+    p.rep = (WMODE == 3 && tid < p.nf) ? a.foot_rep[p.f0 + tid] : 0;
+}
+
+__device__ __forceinline__ void pre_cells(const SweepArgs &a, GroupPre &p) {
+    p.gs = p.c >= 0 ? a.cell_start[p.c] : 0;
+    p.ge = p.c >= 0 ? a.cell_start[p.c + 1] : 0;
+}
+
+// All work of one task group (see k_sweep).  p: the group's prefetched
+// setup data.  With PF the next group's chain (nx, whose ranges are already
+// loaded) is advanced at two points of this group's work, so that its loads
+// are in flight while this group computes; *stage counts the links done.
+template <int CAP, int WMODE, bool F64, bool FF, bool PF>
 __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const SweepArgs &a,
-                                            const int g) {
+                                            const GroupPre &p, GroupPre &nx, int &stage) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const PairParams pp = a.ppar ? a.ppar[a.grp_box[g]] : a.pp;
-    const int t0 = a.grp_task[g], nt = a.grp_task[g + 1] - t0;
-    const int f0 = a.grp_foot[g], nf = a.grp_foot[g + 1] - f0;
+    const int g = p.g;
+    const PairParams pp = a.ppar ? a.ppar[p.box] : a.pp;
+    const int nt = p.nt, f0 = p.f0, nf = p.nf;
     const int64_t n = a.n;
 
-    // footprint table and local layout (the task entry is fetched now so
-    // that its load overlaps the footprint's)
-    const uint32_t my_ab = tid < nt ? a.task_ab[t0 + tid] : 0u;
+    // footprint table and local layout
+    const uint32_t my_ab = p.ab;
     int cnt = 0;
     if (tid < nf) {
-        const int c = a.foot_cells[f0 + tid];
-        if constexpr (WMODE == 3) sh.frep[tid] = a.foot_rep[f0 + tid];
-        const int gs = a.cell_start[c];
-        cnt = a.cell_start[c + 1] - gs;
-        sh.fg[tid] = gs;
+        if constexpr (WMODE == 3) sh.frep[tid] = p.rep;
+        cnt = p.ge - p.gs;
+        sh.fg[tid] = p.gs;
     }
     int total;
     if constexpr (FF) {
@@ -766,36 +818,38 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
     if constexpr (FF) staged = staged && !sh.big;
     if (!staged && tid == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_FALLBACK);
 
-    // Stage the footprint: one particle per thread, all global loads in
-    // flight together.  With plain write-back (WMODE 0) the accumulators
-    // start from the current forces, which no other work-group of this phase
-    // touches, so the write-back below is a plain store.
+    // Stage the footprint, one particle per thread and round.  The global
+    // loads are issued first, all in flight together, and land in registers
+    // while the task table is built; the LDS stores follow.  With plain
+    // write-back (WMODE 0) the accumulators start from the current forces,
+    // which no other work-group of this phase touches, so the write-back
+    // below is a plain store.
+    constexpr int NK = (CAP + kWG - 1) / kWG;
+    uint32_t su[NK][3];
+    long long sfo[WMODE == 0 ? NK : 1][3];
+    uint32_t ox = 0, oy = 0, oz = 0;
     if (staged) {
-        uint32_t ox = 0, oy = 0, oz = 0;
         if constexpr (FF) {  // group origin: the first particle of the footprint
             const int64_t g0 = sh.fg[0];
             ox = a.coord[g0];
             oy = a.coord[n + g0];
             oz = a.coord[2 * n + g0];
         }
-        for (int k = tid; k < total; k += kWG) {
-            const int f = sh.pc[k];
-            const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
-            const uint32_t ux = a.coord[gi], uy = a.coord[n + gi], uz = a.coord[2 * n + gi];
-            if constexpr (WMODE == 0) {
-                const long long fx = a.F[gi], fy = a.F[n + gi], fz = a.F[2 * n + gi];
-                sh.acc[0][k] = fx;
-                sh.acc[1][k] = fy;
-                sh.acc[2][k] = fz;
-            } else if constexpr (WMODE == 1 || WMODE == 3) {
-                sh.acc[0][k] = 0;
-                sh.acc[1][k] = 0;
-                sh.acc[2][k] = 0;
+#pragma unroll
+        for (int r = 0; r < NK; ++r) {
+            const int k = tid + r * kWG;
+            if (k < total) {
+                const int f = sh.pc[k];
+                const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
+                su[r][0] = a.coord[gi];
+                su[r][1] = a.coord[n + gi];
+                su[r][2] = a.coord[2 * n + gi];
+                if constexpr (WMODE == 0) {
+                    sfo[r][0] = a.F[gi];
+                    sfo[r][1] = a.F[n + gi];
+                    sfo[r][2] = a.F[2 * n + gi];
+                }
             }
-            sh.u[k] = make_uint4(ux, uy, uz, 0u);
-            if constexpr (FF)
-                sh.f[k] = make_float4(canon_d(ux, ox, pp.s[0]), canon_d(uy, oy, pp.s[1]),
-                                      canon_d(uz, oz, pp.s[2]), 0.f);
         }
     }
     if constexpr (WMODE == 3) {
@@ -823,7 +877,31 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
     const int so = block_scan_excl<kWG>(nb, sh.w, nslot);
     if (tid < nt) sh.tslot[tid] = so;
     if (tid == 0) sh.tslot[nt] = nslot;
+    if (staged) {
+#pragma unroll
+        for (int r = 0; r < NK; ++r) {
+            const int k = tid + r * kWG;
+            if (k < total) {
+                const uint32_t ux = su[r][0], uy = su[r][1], uz = su[r][2];
+                for (int d = 0; d < 3; ++d) {
+                    if constexpr (WMODE == 0)
+                        sh.acc[d][k] = sfo[r][d];
+                    else if constexpr (WMODE == 1 || WMODE == 3)
+                        sh.acc[d][k] = 0;
+                }
+                sh.u[k] = make_uint4(ux, uy, uz, 0u);
+                if constexpr (FF)
+                    sh.f[k] = make_float4(canon_d(ux, ox, pp.s[0]), canon_d(uy, oy, pp.s[1]),
+                                          canon_d(uz, oz, pp.s[2]), 0.f);
+            }
+        }
+    }
     __syncthreads();
+    if constexpr (PF) {  // next group: task entries and footprint cells
+        pre_head_done(a, nx);
+        pre_foot<WMODE>(a, nx);
+        stage = 2;
+    }
 
     long long e_sum = 0, w_sum = 0, p_cnt = 0;
     uint32_t ovf = 0;
@@ -833,6 +911,10 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
     else
         sweep_pairs<CAP, WMODE, F64, false, FF>(sh, a, pp, f0, nf, nt, nslot, e_sum, w_sum, p_cnt,
                                                 ovf);
+    if constexpr (PF) {  // next group: particle ranges of its footprint cells
+        pre_cells(a, nx);
+        stage = 3;
+    }
 
     // energy, virial, pair count: reduce over the work-group, then one
     // atomic per sum into a slot spread by group index (same-address global
@@ -847,17 +929,24 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
     }
     if (__ballot(ovf != 0u) && lane == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_OVERFLOW);
     __syncthreads();
-    if (tid < 3) {
+    // With a next group in flight (PF) the global stores and atomics of the
+    // tail are issued by the waves from kWB0 on only.  The first waves hold
+    // the next group's footprint loads, and one counter tracks a wave's
+    // loads and stores alike, so a wait for those loads would otherwise also
+    // wait for this group's stores to complete.
+    constexpr int wb0 = PF ? kWB0 : 0;
+    const int wt = tid - wb0;
+    if (wt >= 0 && wt < 3) {
         long long v = 0;
-        for (int k = 0; k < kNW; ++k) v += sh.red[k][tid];
-        long long *dst = a.ew_box ? &a.ew_box[a.grp_box[g] * 3 + tid]
-                                  : &a.part[(g % kPartSlots) * 3 + tid];
+        for (int k = 0; k < kNW; ++k) v += sh.red[k][wt];
+        long long *dst = a.ew_box ? &a.ew_box[p.box * 3 + wt]
+                                  : &a.part[(g % kPartSlots) * 3 + wt];
         atomicAdd((unsigned long long *)dst, (unsigned long long)v);
     }
 
     if constexpr (WMODE == 3) {
         if (!staged) return;
-        for (int k = tid; k < total; k += kWG) {
+        for (int k = wt < 0 ? total : wt; k < total; k += kWG - wb0) {
             const int f = sh.pc[k];
             const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
             long long *P = a.pbuf + (int64_t)sh.frep[f] * 3 * n;
@@ -868,7 +957,7 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
     } else if constexpr (WMODE != 2) {
         if (!staged) return;
         unsigned long long *F = (unsigned long long *)a.F;
-        for (int k = tid; k < total; k += kWG) {
+        for (int k = wt < 0 ? total : wt; k < total; k += kWG - wb0) {
             const int f = sh.pc[k];
             const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
             for (int d = 0; d < 3; ++d) {
@@ -893,19 +982,51 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
 template <int CAP, int WMODE, bool F64, bool FF>
 __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
     __shared__ SweepLDS<CAP, WMODE, FF> sh;
+    __shared__ int s_tk[1];
+    GroupPre p, nx;
+    int stage = 0;
     if (!a.ticket) {
-        sweep_group<CAP, WMODE, F64, FF>(sh, a, a.grp_base + blockIdx.x);
+        pre_head(a, a.grp_base + blockIdx.x, p);
+        pre_head_done(a, p);
+        pre_foot<WMODE>(a, p);
+        pre_cells(a, p);
+        sweep_group<CAP, WMODE, F64, FF, false>(sh, a, p, nx, stage);
         return;
     }
-    __shared__ int s_next;
+    // Persistent: tickets are drawn one group ahead, so the next group is
+    // known while the current one runs and its setup reads overlap it.  The
+    // first two groups of every work-group are fixed (no burst of atomics on
+    // the one counter at launch); the counter hands out the rest.
+    const int grid = (int)gridDim.x;
+    int k = (int)blockIdx.x, kn = k + grid;
+    if (k >= a.ngroups) return;
+    pre_head(a, a.grp_base + k, p);
+    pre_head_done(a, p);
+    pre_foot<WMODE>(a, p);
+    pre_cells(a, p);
     for (;;) {
-        if (threadIdx.x == 0) s_next = atomicAdd(a.ticket, 1);
+        const bool more = kn < a.ngroups;  // uniform
+        int tk = 0;
+        if (more) {
+            pre_head(a, a.grp_base + kn, nx);
+            if (threadIdx.x == 0) tk = 2 * grid + atomicAdd(a.ticket, 1);  // after next
+        }
+        stage = 1;
+        if (more)
+            sweep_group<CAP, WMODE, F64, FF, true>(sh, a, p, nx, stage);
+        else
+            sweep_group<CAP, WMODE, F64, FF, false>(sh, a, p, nx, stage);
+        if (threadIdx.x == 0) s_tk[0] = tk;
         __syncthreads();
-        const int k = s_next;
-        __syncthreads();
-        if (k >= a.ngroups) break;
-        sweep_group<CAP, WMODE, F64, FF>(sh, a, a.grp_base + k);
-        __syncthreads();
+        if (!more) break;
+        const int knn = s_tk[0];  // rewritten only after the next group's barriers
+        if (stage < 2) {  // the group left early
+            pre_head_done(a, nx);
+            pre_foot<WMODE>(a, nx);
+        }
+        if (stage < 3) pre_cells(a, nx);
+        p = nx;
+        kn = knn;
     }
 }
 
@@ -950,9 +1071,32 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const long long *__restric
     }
 }
 
+// A phase with more groups than the device holds at once runs persistent:
+// as many work-groups as fit (occupancy x compute units), each drawing
+// groups from the phase's ticket counter, which the caller has zeroed.
+// Otherwise one work-group per group.
 template <int CAP, int WMODE, bool F64, bool FF>
-static int launch_sweep_t(const SweepArgs &a, int ngroups, hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep<CAP, WMODE, F64, FF>), dim3(ngroups), dim3(kWG), 0, st, a);
+static int launch_sweep_t(SweepArgs a, int ngroups, int ncu, int *ticket, hipStream_t st) {
+    static int per_cu = 0;  // resident work-groups per compute unit (0: not known yet)
+    int res = per_cu;
+    if (res == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, reinterpret_cast<const void *>(&k_sweep<CAP, WMODE, F64, FF>), kWG, 0) ==
+                hipSuccess &&
+            nb >= 1)
+            per_cu = res = nb;
+        else
+            res = 1;  // query refused (e.g. during capture): one per CU, not cached
+    }
+    int grid = ngroups;
+    a.ticket = nullptr;
+    a.ngroups = ngroups;
+    if (ticket && ngroups > res * ncu) {
+        grid = res * ncu;
+        a.ticket = ticket;
+    }
+    hipLaunchKernelGGL((k_sweep<CAP, WMODE, F64, FF>), dim3(grid), dim3(kWG), 0, st, a);
     LAUNCHCHK("k_sweep");
     return LC_OK;
 }
@@ -960,35 +1104,35 @@ static int launch_sweep_t(const SweepArgs &a, int ngroups, hipStream_t st) {
 // LDS tile capacities (particles): with the float filter tile {768, 1024,
 // 2048}, without {1024, 2048, 3072}.
 template <int WMODE, bool F64, bool FF>
-static int launch_sweep_c(int cap, const SweepArgs &a, int ngroups, hipStream_t st) {
+static int launch_sweep_c(int cap, const SweepArgs &a, int ng, int ncu, int *tk, hipStream_t st) {
     if constexpr (FF) {
-        if (cap <= 768) return launch_sweep_t<768, WMODE, F64, true>(a, ngroups, st);
-        if (cap <= 1024) return launch_sweep_t<1024, WMODE, F64, true>(a, ngroups, st);
-        return launch_sweep_t<2048, WMODE, F64, true>(a, ngroups, st);
+        if (cap <= 768) return launch_sweep_t<768, WMODE, F64, true>(a, ng, ncu, tk, st);
+        if (cap <= 1024) return launch_sweep_t<1024, WMODE, F64, true>(a, ng, ncu, tk, st);
+        return launch_sweep_t<2048, WMODE, F64, true>(a, ng, ncu, tk, st);
     } else {
-        if (cap <= 1024) return launch_sweep_t<1024, WMODE, F64, false>(a, ngroups, st);
-        if (cap <= 2048) return launch_sweep_t<2048, WMODE, F64, false>(a, ngroups, st);
-        return launch_sweep_t<3072, WMODE, F64, false>(a, ngroups, st);
+        if (cap <= 1024) return launch_sweep_t<1024, WMODE, F64, false>(a, ng, ncu, tk, st);
+        if (cap <= 2048) return launch_sweep_t<2048, WMODE, F64, false>(a, ng, ncu, tk, st);
+        return launch_sweep_t<3072, WMODE, F64, false>(a, ng, ncu, tk, st);
     }
 }
 
-static int launch_sweep(int cap, int wmode, bool f64, bool ff, const SweepArgs &a, int ngroups,
-                        hipStream_t st) {
+static int launch_sweep(int cap, int wmode, bool f64, bool ff, const SweepArgs &a, int ng,
+                        int ncu, int *tk, hipStream_t st) {
     if (f64) {
-        if (wmode == 0) return launch_sweep_c<0, true, false>(cap, a, ngroups, st);
-        if (wmode == 1) return launch_sweep_c<1, true, false>(cap, a, ngroups, st);
-        if (wmode == 3) return launch_sweep_c<3, true, false>(cap, a, ngroups, st);
-        return launch_sweep_c<2, true, false>(cap, a, ngroups, st);
+        if (wmode == 0) return launch_sweep_c<0, true, false>(cap, a, ng, ncu, tk, st);
+        if (wmode == 1) return launch_sweep_c<1, true, false>(cap, a, ng, ncu, tk, st);
+        if (wmode == 3) return launch_sweep_c<3, true, false>(cap, a, ng, ncu, tk, st);
+        return launch_sweep_c<2, true, false>(cap, a, ng, ncu, tk, st);
     }
     if (ff) {
-        if (wmode == 0) return launch_sweep_c<0, false, true>(cap, a, ngroups, st);
-        if (wmode == 1) return launch_sweep_c<1, false, true>(cap, a, ngroups, st);
-        if (wmode == 3) return launch_sweep_c<3, false, true>(cap, a, ngroups, st);
+        if (wmode == 0) return launch_sweep_c<0, false, true>(cap, a, ng, ncu, tk, st);
+        if (wmode == 1) return launch_sweep_c<1, false, true>(cap, a, ng, ncu, tk, st);
+        if (wmode == 3) return launch_sweep_c<3, false, true>(cap, a, ng, ncu, tk, st);
     }
-    if (wmode == 0) return launch_sweep_c<0, false, false>(cap, a, ngroups, st);
-    if (wmode == 1) return launch_sweep_c<1, false, false>(cap, a, ngroups, st);
-    if (wmode == 3) return launch_sweep_c<3, false, false>(cap, a, ngroups, st);
-    return launch_sweep_c<2, false, false>(cap, a, ngroups, st);
+    if (wmode == 0) return launch_sweep_c<0, false, false>(cap, a, ng, ncu, tk, st);
+    if (wmode == 1) return launch_sweep_c<1, false, false>(cap, a, ng, ncu, tk, st);
+    if (wmode == 3) return launch_sweep_c<3, false, false>(cap, a, ng, ncu, tk, st);
+    return launch_sweep_c<2, false, false>(cap, a, ng, ncu, tk, st);
 }
 
 static PairParams pair_params(const lc_grid *g) {
@@ -1031,6 +1175,7 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     if (buffered && (rc = ensure_pbuf(ws, (int64_t)s->h.rmax * 3 * n))) return rc;
     rc = fill64((long long *)ws->part, 3 * kPartSlots, st);
     if (rc) return rc;
+    const int nphase = (int)s->h.phase_grp.size() - 1;
     SweepArgs a;
     a.grp_task = s->grp_task;
     a.grp_foot = s->grp_foot;
@@ -1060,14 +1205,15 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
         cap = need <= 768 ? 768 : (need <= 1024 ? 1024 : 2048);
     else
         cap = need <= 1024 ? 1024 : (need <= 2048 ? 2048 : 3072);
-    const int nphase = (int)s->h.phase_grp.size() - 1;
     for (int p = 0; p < nphase; ++p) {
         const int ng = s->h.phase_grp[p + 1] - s->h.phase_grp[p];
         if (ng <= 0) continue;
         a.grp_base = s->h.phase_grp[p];
         if (ev) HIPCHK(hipEventRecord(ev[2 * p], st));
+        // one work-group per group: the hardware refills a compute unit as
+        // soon as a group ends, which balances better than a persistent loop
         rc = launch_sweep(cap, s->h.write_mode, precision == LC_PREC_FP64, ff && need <= 2048, a,
-                          ng, st);
+                          ng, s->ncu, nullptr, st);
         if (rc) return rc;
         if (ev) HIPCHK(hipEventRecord(ev[2 * p + 1], st));
     }
@@ -1985,17 +2131,12 @@ static int batch_forces_impl(const lc_batch *b, const int32_t *cell_start, const
     a.ppar = b->d_ppar;
     a.ew_box = (long long *)ew;
     a.ngroups = ng;
-    int grid = ng;
+    int *tk = nullptr;
     if (persistent) {
         if ((rc = fill32(b->d_ticket, 1, st))) return rc;
-        a.ticket = b->d_ticket;
-        const size_t lds = b->cap <= 1024   ? sizeof(SweepLDS<1024, 3, false>)
-                           : b->cap <= 2048 ? sizeof(SweepLDS<2048, 3, false>)
-                                            : sizeof(SweepLDS<3072, 3, false>);
-        const int per_cu = std::max(1, (int)(163840 / (lds + 1024)));
-        grid = std::min(ng, b->ncu * per_cu);
+        tk = b->d_ticket;
     }
-    if (ng > 0 && (rc = launch_sweep(b->cap, 3, false, false, a, grid, st))) return rc;
+    if (ng > 0 && (rc = launch_sweep(b->cap, 3, false, false, a, ng, b->ncu, tk, st))) return rc;
     if (b->ntot > 0) {
         hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((b->ntot + 255) / 256)), dim3(256), 0,
                            st, (const long long *)ws->pbuf, (const int *)b->d_cell_rep, cell_start,
