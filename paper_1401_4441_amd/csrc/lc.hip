@@ -113,10 +113,12 @@ static_assert(kMaxT <= kWG && kMaxF <= kWG, "tables scanned one item per thread"
 static_assert(kMaxF <= 256, "footprint cell of a particle is stored in one byte");
 static_assert(kWB0 % 64 == 0 && kWB0 >= kMaxF && kWB0 + 64 <= kWG, "write-back waves");
 
+typedef short short2v __attribute__((ext_vector_type(2)));
+
 struct PairParams {
     float s[3];    // (float)(L * 2^-32)
     float rc2;     // (float)(rc * rc)
-    float rc2f;    // enlarged cutoff of the float candidate filter
+    int thr16;     // candidate filter bound in (unit16)^2, see filter16_bound
     float ecut;    // canonical pair energy at rc2
     double sd[3];  // L * 2^-32 (exact) for the FP64 variant
     double rc2d;   // rc * rc
@@ -489,15 +491,16 @@ __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, 
     return true;
 }
 
-// Shared memory of one sweep work-group.  FF: the tile also holds float
-// coordinates relative to the group origin for the candidate filter.
+// Shared memory of one sweep work-group.  FF: the tile also holds the
+// 16-bit coordinates of the candidate filter.
 template <int CAP, int WMODE, bool FF>
 struct SweepLDS {
     uint4 u[CAP];                                           // box fractions
-    // filter coordinates; the filter reads rows aoff .. aoff + kmax + 3 for
-    // every lane (kmax: the wave's largest cell A), so it runs past the
-    // footprint by less than kFPad when no cell holds more than kFFCell
-    float4 f[FF ? CAP + kFPad : 1];
+    // filter coordinates: the top 16 bits of the box fractions, x | y << 16
+    // and z; the filter reads rows aoff .. aoff + kmax + 3 for every lane
+    // (kmax: the wave's largest cell A), so it runs past the footprint by
+    // less than kFPad when no cell holds more than kFFCell
+    uint2 h[FF ? CAP + kFPad : 1];
     long long acc[WMODE == 2 ? 1 : 3][WMODE == 2 ? 1 : CAP];  // int64 forces
     int fg[kMaxF];          // global first slot of each footprint cell
     int fl[kMaxF + 1];      // local first slot (prefix over the footprint)
@@ -654,34 +657,38 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
         // i runs over cell A; an intra task keeps each unordered pair once
         // (i before j inside the cell)
         if constexpr (STAGED && FF) {
-            // Two stages per block of up to 32 i.  A tight float filter (an
-            // enlarged-cutoff superset test, so fused multiply-adds are fine
-            // here: the exact canonical test is repeated when the pair is
-            // evaluated) shifts one bit per candidate i into a mask, first i
-            // highest; all lanes of a task read the same row, which LDS
-            // broadcasts.  The set bits are then queued, each lane starting
-            // at its own bit so that a batch's i-side adds spread over
-            // addresses.
+            // Two stages per block of up to 32 i.  A tight integer filter
+            // (a superset of the cutoff sphere, see filter16_bound; the exact
+            // canonical test is repeated when the pair is evaluated) shifts
+            // one bit per candidate i into a mask, first i highest; all lanes
+            // of a task read the same row, which LDS broadcasts.  The set
+            // bits are then queued, each lane starting at its own bit so that
+            // a batch's i-side adds spread over addresses.
             const int na = valid ? (ta >> 16) : 0;
             const int a0 = valid ? aoff : 0;
             const int kmax = __builtin_amdgcn_readfirstlane(wave_max32(na));
-            const float4 fj = valid ? sh.f[jl] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const uint2 hj = valid ? sh.h[jl] : make_uint2(0u, 0u);
             const int lim = intra ? min(jj, na) : na;  // intra: i before j
             const uint32_t rot = (uint32_t)jj & 31u;
             for (int k0 = 0; k0 < kmax; k0 += 32) {
                 const int kr = min(kmax - k0 + 3, 32) & ~3;  // rows read, uniform
-                const float4 *fa = &sh.f[a0 + k0];
+                const uint2 *ha = &sh.h[a0 + k0];
                 uint32_t m = 0u;
                 for (int k = 0; k < kr; k += 4) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        const float4 fi = fa[k + u];
-                        const float dx = fj.x - fi.x, dy = fj.y - fi.y, dz = fj.z - fi.z;
-                        // r2 - rc2f: negative (sign bit set) inside the
-                        // enlarged cutoff; the sign bit is shifted into m
-                        const float t = __builtin_fmaf(
-                            dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, -pp.rc2f)));
-                        m = __builtin_amdgcn_alignbit(m, __float_as_uint(t), 31);
+                        const uint2 hi = ha[k + u];
+                        // 16-bit differences wrap modulo the box: the
+                        // minimum image up to one unit per axis
+                        const short2v dxy = __builtin_bit_cast(short2v, hj.x) -
+                                            __builtin_bit_cast(short2v, hi.x);
+                        const short2v dz0 = __builtin_bit_cast(short2v, hj.y) -
+                                            __builtin_bit_cast(short2v, hi.y);
+                        // r2 - bound: negative (sign bit set) inside; the sign
+                        // bit is shifted into m
+                        int t = __builtin_amdgcn_sdot2(dz0, dz0, -pp.thr16, false);
+                        t = __builtin_amdgcn_sdot2(dxy, dxy, t, false);
+                        m = __builtin_amdgcn_alignbit(m, (uint32_t)t, 31);
                     }
                 }
                 // row k sits at bit kr - 1 - k; keep rows k < lim - k0
@@ -827,14 +834,7 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
     constexpr int NK = (CAP + kWG - 1) / kWG;
     uint32_t su[NK][3];
     long long sfo[WMODE == 0 ? NK : 1][3];
-    uint32_t ox = 0, oy = 0, oz = 0;
     if (staged) {
-        if constexpr (FF) {  // group origin: the first particle of the footprint
-            const int64_t g0 = sh.fg[0];
-            ox = a.coord[g0];
-            oy = a.coord[n + g0];
-            oz = a.coord[2 * n + g0];
-        }
 #pragma unroll
         for (int r = 0; r < NK; ++r) {
             const int k = tid + r * kWG;
@@ -890,9 +890,7 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
                         sh.acc[d][k] = 0;
                 }
                 sh.u[k] = make_uint4(ux, uy, uz, 0u);
-                if constexpr (FF)
-                    sh.f[k] = make_float4(canon_d(ux, ox, pp.s[0]), canon_d(uy, oy, pp.s[1]),
-                                          canon_d(uz, oz, pp.s[2]), 0.f);
+                if constexpr (FF) sh.h[k] = make_uint2((ux >> 16) | (uy & 0xffff0000u), uz >> 16);
             }
         }
     }
@@ -1135,6 +1133,22 @@ static int launch_sweep(int cap, int wmode, bool f64, bool ff, const SweepArgs &
     return launch_sweep_c<2, false, false>(cap, a, ng, ncu, tk, st);
 }
 
+// Bound of the integer candidate filter.  A coordinate's top 16 bits differ
+// between two particles by the exact minimum-image difference in units of
+// L/2^16 to within one unit, so a pair inside the cutoff has a 16-bit
+// squared distance below (rc/u + sqrt 3)^2, u the smallest axis unit; the
+// bound uses rc slightly enlarged (the canonical FP32 r2 may round below the
+// exact one) and +2 units.  0: the filter is not used (axes whose units
+// differ by more than 25% would make the superset needlessly wide).
+static int filter16_bound(const double box[3], float rc2) {
+    const double umin = std::min(box[0], std::min(box[1], box[2])) / 65536.0;
+    const double umax = std::max(box[0], std::max(box[1], box[2])) / 65536.0;
+    if (!(umin > 0.0) || umax > 1.25 * umin) return 0;
+    const double ru = std::sqrt((double)rc2) * (1.0 + 1e-5) / umin + 2.0;
+    const double t = std::ceil(ru * ru) + 1.0;
+    return t < 2.0e9 ? (int)t : 0;
+}
+
 static PairParams pair_params(const lc_grid *g) {
     PairParams p;
     for (int d = 0; d < 3; ++d) {
@@ -1142,11 +1156,7 @@ static PairParams pair_params(const lc_grid *g) {
         p.sd[d] = g->box[d] / 4294967296.0;
     }
     p.rc2 = g->rc2;
-    // The float filter's r^2 differs from the canonical one by a few 1e-6
-    // of rc^2 (group-relative coordinates up to ~10 cells carry ~1e-6
-    // absolute rounding); 1e-4 relative headroom keeps every pair the
-    // canonical test accepts.
-    p.rc2f = (float)((double)g->rc2 * (1.0 + 1e-4));
+    p.thr16 = filter16_bound(g->box, g->rc2);
     p.ecut = g->ecut;
     p.rc2d = g->rc * g->rc;
     const double ic = 1.0 / p.rc2d;
@@ -1197,7 +1207,7 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     a.pp = pair_params(g);
     // LDS tile: expected particles of the largest footprint with headroom
     const double mean = g->ncell > 0 ? (double)n / (double)g->ncell : 0.0;
-    const bool ff = s->h.compact && precision == LC_PREC_FP32 && s->h.write_mode != 2;
+    const bool ff = a.pp.thr16 > 0 && precision == LC_PREC_FP32 && s->h.write_mode != 2;
     const double need = ws->max_per_cell > 0 ? (double)ws->max_per_cell * s->h.max_cells * 0.8
                                              : mean * s->h.max_cells * 1.35;
     int cap;
@@ -1846,6 +1856,7 @@ struct lc_batch {
     int nbox = 0;
     int nwhole = 0;
     int cap = 1024;
+    bool ff = true;  // every box admits the integer candidate filter
     int64_t ntot = 0, ncell = 0;
     std::vector<int64_t> pstart, cstart;
     lcs::HostSchedule h;  // combined groups, global cell ids
@@ -1928,6 +1939,7 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
     std::vector<Grp> groups;
     std::vector<int32_t> cell_rep((size_t)b->ncell, 0);
     double est_max = 0.0;
+    bool filt = true;
     for (int k = 0; k < nbox; ++k) {
         const lc_grid &g = boxes[k].grid;
         const double dens = (double)boxes[k].n / (double)g.ncell;
@@ -1986,7 +1998,8 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
             pp.sd[d] = g.box[d] / 4294967296.0;
         }
         pp.rc2 = g.rc2;
-        pp.rc2f = (float)((double)g.rc2 * (1.0 + 1e-4));
+        pp.thr16 = filter16_bound(g.box, g.rc2);
+        if (pp.thr16 == 0) filt = false;
         pp.ecut = g.ecut;
         pp.rc2d = g.rc * g.rc;
         const double ic = 1.0 / pp.rc2d, s6 = ic * ic * ic;
@@ -2024,6 +2037,7 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
     for (int32_t r : cell_rep) h.rmax = std::max(h.rmax, r);
     const double need = est_max * 1.35;
     b->cap = need <= 1024 ? 1024 : (need <= 2048 ? 2048 : 3072);
+    b->ff = filt && b->cap <= 2048;
 
     int rc = 0;
     if (hipGetDevice(&b->device) != hipSuccess) {
@@ -2136,7 +2150,7 @@ static int batch_forces_impl(const lc_batch *b, const int32_t *cell_start, const
         if ((rc = fill32(b->d_ticket, 1, st))) return rc;
         tk = b->d_ticket;
     }
-    if (ng > 0 && (rc = launch_sweep(b->cap, 3, false, false, a, ng, b->ncu, tk, st))) return rc;
+    if (ng > 0 && (rc = launch_sweep(b->cap, 3, false, b->ff, a, ng, b->ncu, tk, st))) return rc;
     if (b->ntot > 0) {
         hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((b->ntot + 255) / 256)), dim3(256), 0,
                            st, (const long long *)ws->pbuf, (const int *)b->d_cell_rep, cell_start,
