@@ -196,12 +196,16 @@ typedef struct lc_schedule_info {
  * d / -d for every neighbour d); ignored (may be NULL) for other kinds. */
 int lc_make_schedule(const lc_grid *g, int kind, const int8_t *offsets, int n,
                      lc_schedule **out);
-/* As lc_make_schedule, with the smallest block per axis for the block kinds
- * (LC_SCHED_BLOCK8 / ATOMIC_TILE / BUFFER): block_min [host] 3 x int32, at
- * least {1, 2, 2} -- the stencil reaches one cell along +x and one cell each
- * way along y and z, so same-coloured blocks stay a whole block apart.  NULL
- * = {1, 2, 2}.  Larger blocks mean fewer, bigger work-groups and less
- * halo write-back per particle; the autotuner picks the shape. */
+/* As lc_make_schedule, with the block shape of the block kinds: block_min
+ * [host] 3 x int32.  LC_SCHED_BLOCK8: the smallest block per axis, at least
+ * {1, 2, 2} -- the stencil reaches one cell along +x and one cell each way
+ * along y and z, so same-coloured blocks stay a whole block apart -- with an
+ * even block count per axis.  LC_SCHED_ATOMIC_TILE / BUFFER (uncoloured):
+ * the largest block per axis, at least {1, 1, 1}; each axis is cut into
+ * ceil(n / size) near-equal blocks.  NULL = the BLOCK8 partition with
+ * {1, 2, 2} for all three.  Larger blocks mean fewer, bigger work-groups and
+ * less halo write-back per particle; smaller ones fit denser boxes into the
+ * LDS tile.  The autotuner picks the shape. */
 int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *offsets,
                         int n, const int32_t *block_min, lc_schedule **out);
 int lc_schedule_info_get(const lc_schedule *s, lc_schedule_info *out);
@@ -211,6 +215,10 @@ void lc_schedule_free(lc_schedule *s);
  * lc_make_schedule, without touching a device; fills *out. */
 int lc_schedule_plan(const lc_grid *g, int kind, const int8_t *offsets, int n,
                      lc_schedule_info *out);
+/* [host only] As lc_schedule_plan, with the block shape of
+ * lc_make_schedule_ex (NULL = default). */
+int lc_schedule_plan_ex(const lc_grid *g, int kind, const int8_t *offsets, int n,
+                        const int32_t *block_min, lc_schedule_info *out);
 
 /* [host only] The schedule validator on an explicit phase list: phase p runs
  * work-groups phase_grp[p] .. phase_grp[p+1]-1, group k writes the cells
@@ -332,7 +340,8 @@ typedef struct lc_box_desc {
 
 /* How a box is split into work-groups. */
 #define LC_BATCH_AUTO 0   /* whole box in one work-group when it has <= 36
-                             cells and fits the LDS tile, else blocks      */
+                             cells and <= 1024 particles, else blocks
+                             sized to the box density                     */
 #define LC_BATCH_WHOLE 1  /* one work-group owns the whole box            */
 #define LC_BATCH_BLOCKS 2 /* buffer + reduce blocks (as LC_SCHED_BUFFER)  */
 

@@ -1542,11 +1542,16 @@ extern "C" int lc_schedule_info_get(const lc_schedule *s, lc_schedule_info *out)
 
 extern "C" int lc_schedule_plan(const lc_grid *g, int kind, const int8_t *offsets, int n,
                                 lc_schedule_info *out) {
+    return lc_schedule_plan_ex(g, kind, offsets, n, nullptr, out);
+}
+
+extern "C" int lc_schedule_plan_ex(const lc_grid *g, int kind, const int8_t *offsets, int n,
+                                   const int32_t *block_min, lc_schedule_info *out) {
     if (!g || !out) return fail(LC_EINVAL, "lc_schedule_plan: null argument");
     if (kind < 0 || kind >= LC_SCHED_COUNT) return fail(LC_EINVAL, "unknown schedule kind %d", kind);
     lcs::HostSchedule h;
     std::string err;
-    int rc = lcs::build_schedule(g->nc, kind, offsets, n, h, err);
+    int rc = lcs::build_schedule(g->nc, kind, offsets, n, h, err, block_min);
     if (rc) return fail(rc, "lc_schedule_plan: %s", err.c_str());
     if (!lcs::validate(h, g->ncell, err)) return fail(LC_ESCHED, "lc_schedule_plan: %s", err.c_str());
     memset(out, 0, sizeof *out);
@@ -1945,7 +1950,7 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
         const double dens = (double)boxes[k].n / (double)g.ncell;
         const int mode = modes ? modes[k] : LC_BATCH_AUTO;
         const bool whole = mode == LC_BATCH_WHOLE ||
-                           (mode == LC_BATCH_AUTO && g.ncell <= 36 && boxes[k].n <= 1400);
+                           (mode == LC_BATCH_AUTO && g.ncell <= 36 && boxes[k].n <= 1024);
         const int32_t c0 = (int32_t)b->cstart[k];
         if (whole) {
             if (14 * (int64_t)g.ncell > lcs::kMaxGroupTasks || g.ncell > lcs::kMaxGroupCells) {
@@ -1965,14 +1970,23 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
             }
             for (size_t t = 0; t < A.size(); ++t)
                 gr.ab.push_back((uint32_t)A[t] | ((uint32_t)B[t] << 16));
-            gr.est = dens * g.ncell;
+            gr.est = (double)boxes[k].n;  // the footprint is the box: exact
             est_max = std::max(est_max, gr.est);
             groups.push_back(std::move(gr));
             b->nwhole++;
         } else {
+            // the largest blocks whose footprint is expected (box density,
+            // 35% headroom) to fit a 1024-particle tile; dense boxes take
+            // smaller blocks (more replicas, but two work-groups per CU)
+            static const int32_t kShapes[][3] = {{2, 3, 3}, {1, 3, 3}, {1, 2, 2}, {1, 1, 2},
+                                                 {1, 1, 1}};
             lcs::HostSchedule hb;
             std::string err;
-            int rc = lcs::build_schedule(g.nc, LC_SCHED_BUFFER, nullptr, 0, hb, err);
+            int rc = 0;
+            for (const auto &shape : kShapes) {
+                rc = lcs::build_schedule(g.nc, LC_SCHED_BUFFER, nullptr, 0, hb, err, shape);
+                if (rc || dens * hb.max_cells * 1.35 <= 1024.0) break;
+            }
             if (rc) {
                 lc_batch_free(b);
                 return fail(rc, "box %d: %s", k, err.c_str());
@@ -1986,7 +2000,7 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
                     gr.rep.push_back(hb.foot_rep[f]);
                 }
                 for (int t = hb.grp_task[q]; t < hb.grp_task[q + 1]; ++t) gr.ab.push_back(hb.task_ab[t]);
-                gr.est = dens * (double)gr.cells.size();
+                gr.est = dens * (double)gr.cells.size() * 1.35;
                 est_max = std::max(est_max, gr.est);
                 groups.push_back(std::move(gr));
             }
@@ -2035,7 +2049,7 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
     h.phase_grp.push_back((int32_t)groups.size());
     h.cell_rep = cell_rep;
     for (int32_t r : cell_rep) h.rmax = std::max(h.rmax, r);
-    const double need = est_max * 1.35;
+    const double need = est_max;
     b->cap = need <= 1024 ? 1024 : (need <= 2048 ? 2048 : 3072);
     b->ff = filt && b->cap <= 2048;
 

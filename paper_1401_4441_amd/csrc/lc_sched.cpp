@@ -266,6 +266,20 @@ bool add_group(HostSchedule &hs, const std::vector<int32_t> &A,
 // at least as wide as the stencil reaches on that side (minsize: 1 along x,
 // where the half stencil is one-sided, 2 along y and z).  Returns block start
 // offsets with n appended.
+// n cells cut into ceil(n / maxsize) near-equal blocks of at most maxsize
+// (the uncoloured block kinds: no parity or spacing constraint).
+std::vector<int> axis_blocks_max(int n, int maxsize) {
+    const int m = (n + maxsize - 1) / maxsize;
+    const int base = n / m, extra = n % m;
+    std::vector<int> s(1, 0);
+    int pos = 0;
+    for (int b = 0; b < m; ++b) {
+        pos += base + (b < extra ? 1 : 0);
+        s.push_back(pos);
+    }
+    return s;
+}
+
 std::vector<int> axis_blocks(int n, int minsize) {
     if (n < 2 * minsize) return {0, n};
     int m = n / minsize;
@@ -284,12 +298,18 @@ std::vector<int> axis_blocks(int n, int minsize) {
 
 int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
                    int n, HostSchedule &hs, std::string &err, const int32_t *block_min) {
+    // BLOCK8 colours its blocks, so their sizes are lower bounds (the
+    // stencil reach) with an even block count per axis; the uncoloured kinds
+    // take explicit sizes as upper bounds.
+    const bool coloured = kind == LC_SCHED_BLOCK8;
     int32_t bmin[3] = {1, 2, 2};
     if (block_min) {
         for (int d = 0; d < 3; ++d) bmin[d] = block_min[d];
-        if (bmin[0] < 1 || bmin[1] < 2 || bmin[2] < 2 || bmin[0] > 64 || bmin[1] > 64 ||
-            bmin[2] > 64) {
-            err = "block sizes must be >= {1, 2, 2} (the stencil reach) and <= 64";
+        const int lo_yz = coloured ? 2 : 1;
+        if (bmin[0] < 1 || bmin[1] < lo_yz || bmin[2] < lo_yz || bmin[0] > 64 ||
+            bmin[1] > 64 || bmin[2] > 64) {
+            err = coloured ? "block sizes must be >= {1, 2, 2} (the stencil reach) and <= 64"
+                           : "block sizes must be >= 1 and <= 64";
             return LC_EINVAL;
         }
     }
@@ -305,7 +325,9 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
     if (kind == LC_SCHED_BLOCK8 || kind == LC_SCHED_ATOMIC_TILE || kind == LC_SCHED_BUFFER) {
         hs.write_mode = kind == LC_SCHED_BLOCK8 ? 0 : (kind == LC_SCHED_ATOMIC_TILE ? 1 : 3);
         std::vector<int> bs[3];
-        for (int d = 0; d < 3; ++d) bs[d] = axis_blocks(nc[d], bmin[d]);
+        for (int d = 0; d < 3; ++d)
+            bs[d] = (block_min && !coloured) ? axis_blocks_max(nc[d], bmin[d])
+                                             : axis_blocks(nc[d], bmin[d]);
         const int nb[3] = {(int)bs[0].size() - 1, (int)bs[1].size() - 1,
                            (int)bs[2].size() - 1};
         const int ncol[3] = {nb[0] > 1 ? 2 : 1, nb[1] > 1 ? 2 : 1, nb[2] > 1 ? 2 : 1};

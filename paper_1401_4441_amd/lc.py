@@ -80,6 +80,7 @@ SYMBOLS = {
     "lc_schedule_info_get": ([P, P], INT),
     "lc_schedule_free": ([P], None),
     "lc_schedule_plan": ([P, INT, P, INT, P], INT),
+    "lc_schedule_plan_ex": ([P, INT, P, INT, P, P], INT),
     "lc_validate_phases": ([I64, ctypes.c_int32, P, P, P], INT),
     "lc_serialization_degree": ([P, INT, P, INT, P, I64, P], INT),
     "lc_serialization_degree_weighted": ([P, INT, P, INT, P, P], INT),
@@ -249,8 +250,9 @@ class Schedule:
             pass
 
 
-def schedule_plan(grid: Grid, kind, offsets=None) -> dict:
-    """Host-only: build and validate a schedule, return its shape."""
+def schedule_plan(grid: Grid, kind, offsets=None, block=None) -> dict:
+    """Host-only: build and validate a schedule, return its shape.  block:
+    the block shape of the block kinds (see Schedule)."""
     import numpy as np
     if isinstance(kind, str):
         kind = KINDS[kind]
@@ -259,8 +261,12 @@ def schedule_plan(grid: Grid, kind, offsets=None) -> dict:
         op, n = ctypes.c_void_p(arr.ctypes.data), arr.shape[0]
     else:
         op, n = None, 0
+    bp = None
+    if block is not None:
+        barr = np.ascontiguousarray(np.asarray(block, dtype=np.int32).reshape(3))
+        bp = ctypes.c_void_p(barr.ctypes.data)
     i = _SchedInfo()
-    _chk(lib().lc_schedule_plan(grid.ptr, int(kind), op, int(n), ctypes.byref(i)))
+    _chk(lib().lc_schedule_plan_ex(grid.ptr, int(kind), op, int(n), bp, ctypes.byref(i)))
     return {k: getattr(i, k) for k, _ in _SchedInfo._fields_ if k != "pad"}
 
 

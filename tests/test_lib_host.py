@@ -126,6 +126,33 @@ def test_block8_on_odd_and_small_grids():
         assert info["ntask"] == 14 * g.ncell
 
 
+@pytest.mark.parametrize("kind", ["buffer", "atomic_tile"])
+def test_uncoloured_block_sizes_are_upper_bounds(kind):
+    """Uncoloured block kinds cut each axis into ceil(n / size) near-equal
+    blocks of at most `size` cells (down to single cells); every task is
+    kept and the footprint of a single-cell block is the cell and its 13
+    half-shell neighbours."""
+    g = lc.Grid((7 * 2.6,) * 3, 2.5)  # 7 cells per axis
+    assert tuple(g.nc) == (7, 7, 7)
+    one = lc.schedule_plan(g, kind, block=(1, 1, 1))
+    assert one["ngroup"] == 343 and one["ntask"] == 14 * 343
+    assert one["max_group_cells"] == 14 and one["max_group_tasks"] == 14
+    two = lc.schedule_plan(g, kind, block=(1, 1, 2))
+    assert two["ngroup"] == 7 * 7 * 4 and two["ntask"] == 14 * 343
+    big = lc.schedule_plan(g, kind, block=(2, 3, 3))
+    assert big["ngroup"] == 4 * 3 * 3 and big["ntask"] == 14 * 343
+    if kind == "buffer":  # a cell is in 14 single-cell footprints
+        assert one["max_replicas"] == 14
+
+
+def test_block8_sizes_are_lower_bounds():
+    g = lc.Grid((7 * 2.6,) * 3, 2.5)
+    with pytest.raises(lc.LCError):
+        lc.schedule_plan(g, "block8", block=(1, 1, 2))
+    info = lc.schedule_plan(g, "block8", block=(1, 2, 2))
+    assert info["nphase"] == 8 and info["ntask"] == 14 * 343
+
+
 def test_validator_rejects_shared_write():
     # phase 0: groups {0,1} and {2,3}; phase 1: {1,2}
     lc.validate_phases(4, [0, 2, 3], [0, 2, 4, 6], [0, 1, 2, 3, 1, 2])
