@@ -2,11 +2,12 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload fcc256k]
 
-A step is one whole force evaluation (lc_compute_forces under the faster of
-the two conflict-free schedules, BLOCK8 colouring or BUFFER buffer+reduce,
-picked by a short trial and named in the output) over a
-256,000-particle Lennard-Jones FCC crystal at density 0.8 with rc = 2.5 in a
-periodic cube (26^3 cells), cells prebuilt and all inputs resident in HBM.
+A step is one whole force evaluation (lc_compute_forces under the fastest
+conflict-free configuration -- BLOCK8 colouring or BUFFER buffer+reduce, with
+the cell grid and block shape the autotuner picks, all named in the output)
+over a 256,000-particle Lennard-Jones FCC crystal at density 0.8 with
+rc = 2.5 in a periodic cube (26^3 or 27^3 cells), cells prebuilt and all
+inputs resident in HBM.
 Prints ONE JSON line: pair interactions per second (pairs inside the cutoff
 evaluated per second), the roofline of the dominant kernel (the tile sweep,
 bound by vector ALU work), the same evaluation under the atomics baselines
@@ -39,12 +40,12 @@ OPS_PER_CANDIDATE = 10
 OPS_PER_PAIR = 50
 
 WORKLOADS = {
-    "fcc256k": dict(n=256000, rho=0.8, rc=2.5, seed=1002, even=True,
-                    desc="LJ FCC+jitter N=256000 rho=0.8 rc=2.5 periodic cube, 26^3 cells"),
-    "fcc4k": dict(n=4000, rho=0.8, rc=2.5, seed=1001, even=True,
-                  desc="LJ FCC+jitter N=4000 rho=0.8 rc=2.5 periodic cube, 6^3 cells"),
-    "fcc4m": dict(n=4_000_000, rho=0.8, rc=2.5, seed=1003, even=True,
-                  desc="LJ FCC+jitter N=4000000 rho=0.8 rc=2.5 periodic cube, 68^3 cells"),
+    "fcc256k": dict(n=256000, rho=0.8, rc=2.5, seed=1002,
+                    desc="LJ FCC+jitter N=256000 rho=0.8 rc=2.5 periodic cube"),
+    "fcc4k": dict(n=4000, rho=0.8, rc=2.5, seed=1001,
+                  desc="LJ FCC+jitter N=4000 rho=0.8 rc=2.5 periodic cube"),
+    "fcc4m": dict(n=4_000_000, rho=0.8, rc=2.5, seed=1003,
+                  desc="LJ FCC+jitter N=4000000 rho=0.8 rc=2.5 periodic cube"),
 }
 EXTRA_WORKLOADS = ("fcc4m_md", "slab2m", "boxes512")
 
@@ -63,10 +64,11 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_prefix: str, workload: str):
+def measured_traffic(kernel_prefix: str, workload: str, config: dict):
     """HBM bytes per launch of the kernel from the committed rocprofv3 PMC
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when
-    the kernel sources changed since the counters were taken."""
+    the kernel sources or the configuration (schedule, cells, block shape)
+    differ from the ones the counters were taken on."""
     path = os.path.join(ROOT, "profiles", f"k_sweep_{workload}_traffic.json")
     try:
         with open(path) as f:
@@ -75,8 +77,11 @@ def measured_traffic(kernel_prefix: str, workload: str):
         return None
     if d.get("source_sha256") != source_hash():
         return None
-    k = d.get("kernels", {}).get(kernel_prefix)
-    return None if k is None else k["bytes_per_launch"]
+    for entry in d.get("configs", []):
+        if entry.get("config") == config:
+            k = entry.get("kernels", {}).get(kernel_prefix)
+            return None if k is None else k["bytes_per_launch"]
+    return None
 
 
 def candidate_pairs(cell_start: np.ndarray, nc) -> int:
@@ -100,6 +105,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the baseline schedules (atomics, paper orders)")
+    ap.add_argument("--schedule", choices=("block8", "buffer"),
+                    help="fix the headline schedule instead of autotuning (with --block and "
+                         "--grid; used to profile one configuration)")
+    ap.add_argument("--block", default=None, help="block shape X,Y,Z for --schedule")
+    ap.add_argument("--grid", default="natural", choices=("even", "natural", "wide"),
+                    help="cell grid for --schedule: even counts, natural (side >= rc), "
+                         "or widened 15%% with even counts")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 64 MiB device copy three times (the reference "
                          "that scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
@@ -119,7 +131,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1401_4441_amd import lc, synth
+    from paper_1401_4441_amd import autotune, lc, synth
 
     if args.workload == "fcc4m_md":
         return bench_md(args)
@@ -130,18 +142,36 @@ def main():
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     box = synth.fcc(w["n"], w["rho"], rc=w["rc"], seed=w["seed"])
-    g = lc.Grid(box.L, box.rc, 0.0, w["even"])
-    ws = lc.Workspace(box.n, g.ncell)
     pos = torch.from_numpy(box.pos).to(dev)
+
+    # ---- pick the configuration: the autotuner times every cell grid x
+    # schedule kind x block shape (conflict-free kinds, and ATOMIC_TILE for
+    # the baseline table); the fastest conflict-free one is the headline
+    if args.schedule:
+        gopt = {"even": {"extra": 0.0, "even": True}, "natural": {"extra": 0.0, "even": False},
+                "wide": {"extra": 0.15, "even": True}}[args.grid]
+        blk0 = [int(x) for x in args.block.split(",")] if args.block else [1, 2, 2]
+        pick = {"kind": args.schedule, "block": blk0, "grid": gopt}
+        tune = {"trials": [dict(pick, nc=[0, 0, 0], ms=0.0)]}
+    else:
+        tune = autotune.tune_box(pos, box.L, box.rc, allow_atomics=True, reps=5, use_cache=False)
+        cf = [t for t in tune["trials"] if t["kind"] in autotune.BOX_KINDS_CONFLICT_FREE]
+        pick = min(cf, key=lambda t: t["ms"])
+    g = lc.Grid(box.L, box.rc, pick["grid"]["extra"], pick["grid"]["even"])
+    ws = lc.Workspace(box.n, g.ncell)
     cs, perm, coord = lc.build_cells(g, pos, ws)
+
+    def best_block(kind):
+        on_grid = [t for t in tune["trials"] if t["kind"] == kind and t["grid"] == pick["grid"]]
+        return tuple(min(on_grid, key=lambda t: t["ms"])["block"]) if on_grid else None
     torch.cuda.synchronize()
     ncand = candidate_pairs(cs.cpu().numpy(), g.nc)
     F = torch.empty((3, box.n), dtype=torch.int64, device=dev)
     ew = torch.empty(3, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
 
-    def time_sched(kind, steps, warmup):
-        s = lc.Schedule(g, kind)
+    def time_sched(kind, steps, warmup, block=None):
+        s = lc.Schedule(g, kind, block=block)
         for _ in range(warmup):
             lc.compute_forces(g, s, cs, coord, ws, "fp32", F, ew)
         torch.cuda.synchronize()
@@ -157,18 +187,11 @@ def main():
         ms = e0.elapsed_time(e1) / steps
         return s, ms, wall
 
-    # ---- pick the conflict-free schedule: BLOCK8 (two-strided colouring,
-    # 8 phases) or BUFFER (buffer + reduce, one phase); short trial of each
-    trial = {}
-    for kind in ("block8", "buffer"):
-        s_, kms, _ = time_sched(kind, 5, 2)
-        trial[kind] = kms
-        s_.close()
-    best = min(trial, key=trial.get)
+    best, blk = pick["kind"], tuple(pick["block"])
 
     # ---- the timed region: K evaluations under that schedule
     ws.clear_status()
-    sched, ms, wall = time_sched(best, args.steps, args.warmup)
+    sched, ms, wall = time_sched(best, args.steps, args.warmup, blk)
     pairs = int(ew[2].item())
     status = ws.status()
     value = pairs / (ms * 1e-3)
@@ -209,7 +232,10 @@ def main():
         "dtype": "f32 pair math, int64 fixed-point accumulation",
         "data": "synthetic (seeded FCC lattice + uniform jitter)",
         "config": {"workload": w["desc"], "n": box.n, "cells": list(g.nc),
-                   "schedule": best, "schedule_trial_ms": trial, "pairs_in_cutoff": pairs,
+                   "schedule": best, "block": list(blk), "grid_choice": pick["grid"],
+                   "autotune_trials": [[t["kind"], t["nc"][0], t["block"], round(t["ms"], 4)]
+                                       for t in tune["trials"]],
+                   "pairs_in_cutoff": pairs,
                    "candidate_pairs": ncand, "status_flags": status},
         "accuracy": {"force_normwise_rel_err_vs_fp64": err_norm,
                      "energy_rel_err_vs_fp64": err_energy, "gate": 1e-5,
@@ -220,7 +246,8 @@ def main():
             "peak": VALU_PEAK_TOPS,
             "unit": "Tops/s (VALU lane-ops)",
             "frac": achieved_tops / VALU_PEAK_TOPS,
-            "traffic": measured_traffic(f"k_sweep_wmode{sched.info()['write_mode']}", args.workload),
+            "traffic": measured_traffic(f"k_sweep_wmode{sched.info()['write_mode']}", args.workload,
+                                        {"kind": best, "nc": list(g.nc), "block": list(blk)}),
             "traffic_source": f"profiles/k_sweep_{args.workload}_traffic.json (rocprofv3 --pmc "
                               "FETCH_SIZE / WRITE_SIZE, scaled by a 64 MiB copy); null if the "
                               "kernel changed since",
@@ -241,9 +268,14 @@ def main():
         for kind, st, wu in (("block8", 20, 3), ("buffer", 20, 3), ("atomic_tile", 20, 3),
                              ("atomic_pair", 20, 3), ("loopex", 10, 2), ("opt", 2, 1),
                              ("lex", 1, 1)):
-            s, kms, _ = time_sched(kind, st, wu)
+            kb = best_block(kind)
+            try:
+                s, kms, _ = time_sched(kind, st, wu, kb)
+            except lc.LCError as e:  # loop exchange needs even cell counts
+                extra[kind] = {"skipped": str(e)}
+                continue
             extra[kind] = {"ms_per_step": kms, "pairs_per_s": pairs / (kms * 1e-3),
-                           "phases": s.info()["nphase"],
+                           "phases": s.info()["nphase"], "block": list(kb) if kb else None,
                            "time_vs_headline": kms / ms}
             s.close()
         out["schedules"] = extra
@@ -252,10 +284,15 @@ def main():
             "speedup_over_atomic_tile": extra["atomic_tile"]["ms_per_step"] / ms,
             "target": ">= 3x over the plain atomics baseline (atomic_pair)"}
         # the paper's serialisation degree on this grid (host computation)
-        sd = {k: lc.serialization_degree(g.nc, k) for k in ("lex", "opt", "best", "bad", "loopex")}
-        out["serialization_degree"] = {k: {"cp": v["cp"], "S": v["speedup"],
-                                           "delta": v["delta"], "S_eq2": v["s_eq2"]}
-                                       for k, v in sd.items()}
+        sdo = {}
+        for k in ("lex", "opt", "best", "bad", "loopex"):
+            try:
+                v = lc.serialization_degree(g.nc, k)
+            except lc.LCError as e:  # loop exchange needs even cell counts
+                sdo[k] = {"skipped": str(e)}
+                continue
+            sdo[k] = {"cp": v["cp"], "S": v["speedup"], "delta": v["delta"], "S_eq2": v["s_eq2"]}
+        out["serialization_degree"] = sdo
 
     # ---- CPU baseline: the serial oracle on the host (rank 0, N=1 only)
     if not args.no_cpu:

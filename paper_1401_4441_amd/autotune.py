@@ -4,7 +4,8 @@ It times candidate configurations on the device through the C-ABI and keeps
 the fastest: the cell grid (cell side rc, optionally widened, cell counts
 rounded to even or not), the conflict-free schedule (BLOCK8 colouring or
 BUFFER buffer + reduce; ATOMIC_TILE when atomics are allowed) and the block
-shape (smallest block per axis).  For a batch of boxes it picks how boxes
+shape (for BLOCK8 the smallest block per axis, for the uncoloured kinds the
+largest).  For a batch of boxes it picks how boxes
 are split (whole-box work-groups where they fit, or blocks) and whether the
 sweep runs as a persistent launch.  Results are cached in a JSON file keyed
 by the device name and a bucket of (N, density, rc).
@@ -25,7 +26,16 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1401_4441
                              "tune.json")
 
 BOX_KINDS_CONFLICT_FREE = ("block8", "buffer")
-BLOCKS = ((1, 2, 2), (2, 2, 2), (1, 3, 3), (2, 3, 3))
+# BLOCK8: lower bounds per axis (even block counts); uncoloured kinds: upper
+# bounds.  Shapes whose footprint outgrows the LDS tile lose on their own
+# (one work-group per compute unit), so they need no pruning here.
+BLOCKS = {"block8": ((1, 2, 2), (2, 2, 2), (1, 3, 3), (2, 3, 3)),
+          "uncoloured": ((1, 2, 2), (1, 2, 3), (1, 3, 3), (2, 2, 2), (2, 2, 3), (1, 3, 4),
+                         (1, 4, 4), (2, 3, 3))}
+
+
+def shapes_for(kind: str):
+    return BLOCKS["block8"] if kind == "block8" else BLOCKS["uncoloured"]
 GRIDS = ({"extra": 0.0, "even": True}, {"extra": 0.0, "even": False},
          {"extra": 0.15, "even": True})
 
@@ -84,7 +94,7 @@ def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
     pos: (3, N) float64 cuda tensor.  Returns {"grid": {...}, "kind": str,
     "block": [x, y, z], "ms": float, "trials": [...]}."""
     n = pos.shape[1]
-    key = box_key(n, L, rc) + ("|atomics" if allow_atomics else "")
+    key = box_key(n, L, rc) + ("|atomics" if allow_atomics else "") + "|v2"
     cache = _load_cache() if use_cache else {}
     if key in cache:
         return cache[key]
@@ -99,7 +109,7 @@ def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
         ws = lc.Workspace(n, grid.ncell)
         cs, perm, coord = lc.build_cells(grid, pos, ws)
         for kind in kinds:
-            for block in BLOCKS:
+            for block in shapes_for(kind):
                 try:
                     sched = lc.Schedule(grid, kind, block=block)
                 except lc.LCError:
