@@ -340,8 +340,8 @@ typedef struct lc_box_desc {
 
 /* How a box is split into work-groups. */
 #define LC_BATCH_AUTO 0   /* whole box in one work-group when it has <= 36
-                             cells and <= 1024 particles, else blocks
-                             sized to the box density                     */
+                             cells and <= 768 particles, else blocks sized
+                             to the box density                           */
 #define LC_BATCH_WHOLE 1  /* one work-group owns the whole box            */
 #define LC_BATCH_BLOCKS 2 /* buffer + reduce blocks (as LC_SCHED_BUFFER)  */
 

@@ -977,8 +977,14 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
 //        atomic write-back; 2 = every pair adds into global memory with
 //        atomics; 3 = accumulate in LDS, plain stores into the group's
 //        replica slots (buffer + reduce).
+// Occupancy: a 768-particle tile leaves LDS for three work-groups per
+// compute unit, which also needs at most 80 VGPRs (six waves per SIMD); the
+// register allocator then spills a few values outside the pair loops, which
+// costs far less than the latency the third work-group hides.  Larger tiles
+// are held to two work-groups by LDS anyway.
 template <int CAP, int WMODE, bool F64, bool FF>
-__global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CAP <= 768 ? 6 : 1)))
+void k_sweep(SweepArgs a) {
     __shared__ SweepLDS<CAP, WMODE, FF> sh;
     __shared__ int s_tk[1];
     GroupPre p, nx;
@@ -1950,7 +1956,7 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
         const double dens = (double)boxes[k].n / (double)g.ncell;
         const int mode = modes ? modes[k] : LC_BATCH_AUTO;
         const bool whole = mode == LC_BATCH_WHOLE ||
-                           (mode == LC_BATCH_AUTO && g.ncell <= 36 && boxes[k].n <= 1024);
+                           (mode == LC_BATCH_AUTO && g.ncell <= 36 && boxes[k].n <= 768);
         const int32_t c0 = (int32_t)b->cstart[k];
         if (whole) {
             if (14 * (int64_t)g.ncell > lcs::kMaxGroupTasks || g.ncell > lcs::kMaxGroupCells) {
@@ -1976,8 +1982,9 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
             b->nwhole++;
         } else {
             // the largest blocks whose footprint is expected (box density,
-            // 35% headroom) to fit a 1024-particle tile; dense boxes take
-            // smaller blocks (more replicas, but two work-groups per CU)
+            // 35% headroom) to fit a 768-particle tile, which runs three
+            // work-groups per CU; dense boxes take smaller blocks (more
+            // replicas)
             static const int32_t kShapes[][3] = {{2, 3, 3}, {1, 3, 3}, {1, 2, 2}, {1, 1, 2},
                                                  {1, 1, 1}};
             lcs::HostSchedule hb;
@@ -1985,7 +1992,7 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
             int rc = 0;
             for (const auto &shape : kShapes) {
                 rc = lcs::build_schedule(g.nc, LC_SCHED_BUFFER, nullptr, 0, hb, err, shape);
-                if (rc || dens * hb.max_cells * 1.35 <= 1024.0) break;
+                if (rc || dens * hb.max_cells * 1.35 <= 768.0) break;
             }
             if (rc) {
                 lc_batch_free(b);
@@ -2050,7 +2057,7 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
     h.cell_rep = cell_rep;
     for (int32_t r : cell_rep) h.rmax = std::max(h.rmax, r);
     const double need = est_max;
-    b->cap = need <= 1024 ? 1024 : (need <= 2048 ? 2048 : 3072);
+    b->cap = need <= 768 ? 768 : need <= 1024 ? 1024 : (need <= 2048 ? 2048 : 3072);
     b->ff = filt && b->cap <= 2048;
 
     int rc = 0;
