@@ -1034,11 +1034,43 @@ void k_sweep(SweepArgs a) {
     }
 }
 
+// Sum the spread partial slots into out[0..ncomp) in a fixed order (one
+// work-group of 256 threads), then clear the slots it read: every
+// evaluation leaves them zero for the next, so no clearing launch is
+// needed (the workspace zeroes them once when it is created).
+__device__ __forceinline__ void reduce_parts_wg(long long *__restrict__ part, int ncomp,
+                                                long long *__restrict__ out) {
+    __shared__ long long s_w[4];
+    for (int c = 0; c < ncomp; ++c) {
+        long long v = 0;
+        for (int k = threadIdx.x; k < kPartSlots; k += 256) {
+            v += part[k * ncomp + c];
+            part[k * ncomp + c] = 0;
+        }
+        v = wave_sum64(v);
+        if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) out[c] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_parts(long long *__restrict__ part, int ncomp,
+                                                      long long *__restrict__ out) {
+    reduce_parts_wg(part, ncomp, out);
+}
+
 // Buffer + reduce: F of every particle = sum of its cell's replica slots.
-__global__ void k_gather_partials(const long long *__restrict__ pbuf,
-                                  const int *__restrict__ cell_rep,
-                                  const int *__restrict__ cell_start, int ncell, int64_t n,
-                                  long long *__restrict__ F) {
+// With part != NULL one extra work-group (the last) sums the energy slots
+// instead, which saves a launch.
+__global__ __launch_bounds__(256) void k_gather_partials(
+    const long long *__restrict__ pbuf, const int *__restrict__ cell_rep,
+    const int *__restrict__ cell_start, int ncell, int64_t n, long long *__restrict__ F,
+    long long *__restrict__ part, long long *__restrict__ ew) {
+    if (part && blockIdx.x == gridDim.x - 1) {
+        reduce_parts_wg(part, 3, ew);
+        return;
+    }
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     int lo = 0, hi = ncell;  // cell_start[lo] <= p < cell_start[hi]
@@ -1057,22 +1089,6 @@ __global__ void k_gather_partials(const long long *__restrict__ pbuf,
     F[p] = fx;
     F[n + p] = fy;
     F[2 * n + p] = fz;
-}
-
-// Sum the spread partial slots into out[0..ncomp): one work-group,
-// fixed order.
-__global__ __launch_bounds__(256) void k_reduce_parts(const long long *__restrict__ part,
-                                                      int ncomp, long long *__restrict__ out) {
-    __shared__ long long s_w[4];
-    for (int c = 0; c < ncomp; ++c) {
-        long long v = 0;
-        for (int k = threadIdx.x; k < kPartSlots; k += 256) v += part[k * ncomp + c];
-        v = wave_sum64(v);
-        if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) out[c] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
-        __syncthreads();
-    }
 }
 
 // A phase with more groups than the device holds at once runs persistent:
@@ -1189,8 +1205,6 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     int rc = buffered ? LC_OK : fill64((long long *)F, 3 * n, st);
     if (rc) return rc;
     if (buffered && (rc = ensure_pbuf(ws, (int64_t)s->h.rmax * 3 * n))) return rc;
-    rc = fill64((long long *)ws->part, 3 * kPartSlots, st);
-    if (rc) return rc;
     const int nphase = (int)s->h.phase_grp.size() - 1;
     SweepArgs a;
     a.grp_task = s->grp_task;
@@ -1233,13 +1247,14 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
         if (rc) return rc;
         if (ev) HIPCHK(hipEventRecord(ev[2 * p + 1], st));
     }
-    if (buffered && n > 0) {
-        hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                           (const long long *)ws->pbuf, (const int *)s->cell_rep, cell_start,
-                           g->ncell, n, (long long *)F);
+    if (buffered && n > 0) {  // gather + the energy sums in one launch
+        hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((n + 255) / 256 + 1)), dim3(256), 0,
+                           st, (const long long *)ws->pbuf, (const int *)s->cell_rep, cell_start,
+                           g->ncell, n, (long long *)F, (long long *)ws->part, (long long *)ew);
         LAUNCHCHK("k_gather_partials");
+        return LC_OK;
     }
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (const long long *)ws->part, 3,
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (long long *)ws->part, 3,
                        (long long *)ew);
     LAUNCHCHK("k_reduce_parts");
     return LC_OK;
@@ -1412,7 +1427,8 @@ extern "C" int lc_workspace_create(int64_t max_n, int64_t max_cells, lc_workspac
         lc_workspace_destroy(ws);
         return rc;
     }
-    if (hipMemset(ws->flags, 0, sizeof(uint32_t)) != hipSuccess) {
+    if (hipMemset(ws->flags, 0, sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(ws->part, 0, 3 * kPartSlots * sizeof(int64_t)) != hipSuccess) {
         lc_workspace_destroy(ws);
         return fail(LC_EHIP, "hipMemset flags");
     }
@@ -1428,7 +1444,9 @@ extern "C" int lc_workspace_set_tile_hint(lc_workspace *ws, int32_t max_per_cell
 
 extern "C" int lc_workspace_clear_status(lc_workspace *ws, void *stream) {
     if (!ws) return fail(LC_EINVAL, "null workspace");
-    return fill32((int *)ws->flags, 1, (hipStream_t)stream);
+    // also the energy slots, which a failed evaluation may have left dirty
+    int rc = fill64((long long *)ws->part, 3 * kPartSlots, (hipStream_t)stream);
+    return rc ? rc : fill32((int *)ws->flags, 1, (hipStream_t)stream);
 }
 
 extern "C" int lc_workspace_status(lc_workspace *ws, void *stream, uint32_t *flags) {
@@ -1735,15 +1753,13 @@ extern "C" int lc_kinetic_energy(const double *vel, int64_t n, int64_t *ke, lc_w
     if (!ke || (n > 0 && !vel)) return fail(LC_EINVAL, "lc_kinetic_energy: null argument");
     hipStream_t st = (hipStream_t)stream;
     if (!ws) return fail(LC_EINVAL, "lc_kinetic_energy: null workspace");
-    int rc = fill64((long long *)ws->part, kPartSlots, st);
-    if (rc) return rc;
     if (n > 0) {
         hipLaunchKernelGGL(k_kick_ke, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                            (double *)vel, (const long long *)nullptr, n, 0.0, 0,
                            (unsigned long long *)ws->part);
         LAUNCHCHK("k_kick_ke");
     }
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (const long long *)ws->part, 1,
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (long long *)ws->part, 1,
                        (long long *)ke);
     LAUNCHCHK("k_reduce_parts");
     return LC_OK;
@@ -1800,14 +1816,13 @@ extern "C" int lc_verlet_step(const lc_grid *g, const lc_schedule *s, double *po
                 return rc;
         }
         long long *row = (long long *)trace + 2 * step;
-        if ((rc = fill64((long long *)ws->part, kPartSlots, st))) return rc;
         if (n > 0) {
             hipLaunchKernelGGL(k_kick_ke, dim3(nbk), dim3(256), 0, st, vel, (const long long *)F, n,
                                hdt, step > 0 ? 1 : 0, (unsigned long long *)ws->part);
             LAUNCHCHK("k_kick_ke");
         }
-        hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (const long long *)ws->part,
-                           1, row);
+        hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (long long *)ws->part, 1,
+                           row);
         LAUNCHCHK("k_reduce_parts");
         hipLaunchKernelGGL(k_copy64, dim3(1), dim3(64), 0, st, (const long long *)ws->ew, row + 1, 1);
         LAUNCHCHK("k_copy64");
@@ -2175,7 +2190,8 @@ static int batch_forces_impl(const lc_batch *b, const int32_t *cell_start, const
     if (b->ntot > 0) {
         hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((b->ntot + 255) / 256)), dim3(256), 0,
                            st, (const long long *)ws->pbuf, (const int *)b->d_cell_rep, cell_start,
-                           (int)b->ncell, b->ntot, (long long *)F);
+                           (int)b->ncell, b->ntot, (long long *)F, (long long *)nullptr,
+                           (long long *)nullptr);
         LAUNCHCHK("k_gather_partials");
     }
     return LC_OK;
