@@ -175,7 +175,16 @@ int lc_gather(const int32_t *perm, int64_t n, const double *in3, double *out3,
                                    replicas of every particle.  No colours,
                                    no atomics; R_max x 24 B per particle of
                                    workspace memory (grown on first use)    */
-#define LC_SCHED_COUNT 10
+#define LC_SCHED_FULLSHELL 10   /* comparison baseline without Newton's third
+                                   law: each home cell with all 27 cells of
+                                   its full shell, forces kept on the home
+                                   side only (every pair evaluated twice);
+                                   blocks of home cells in ONE phase, plain
+                                   stores, no colours, no atomics, no
+                                   replicas.  Forces are bit-identical to the
+                                   Newton-3 kinds (the reversed pair negates
+                                   the separation exactly)                  */
+#define LC_SCHED_COUNT 11
 
 typedef struct lc_schedule lc_schedule;
 
@@ -202,7 +211,7 @@ int lc_make_schedule(const lc_grid *g, int kind, const int8_t *offsets, int n,
  * [host] 3 x int32.  LC_SCHED_BLOCK8: the smallest block per axis, at least
  * {1, 2, 2} -- the stencil reaches one cell along +x and one cell each way
  * along y and z, so same-coloured blocks stay a whole block apart -- with an
- * even block count per axis.  LC_SCHED_ATOMIC_TILE / BUFFER (uncoloured):
+ * even block count per axis.  LC_SCHED_ATOMIC_TILE / BUFFER / FULLSHELL (uncoloured):
  * the largest block per axis, at least {1, 1, 1}; each axis is cut into
  * ceil(n / size) near-equal blocks.  NULL = the BLOCK8 partition with
  * {1, 2, 2} for all three.  Larger blocks mean fewer, bigger work-groups and

@@ -72,35 +72,45 @@ def box_key(n: int, L, rc: float) -> str:
     return f"{dev}|n{round(4 * math.log2(max(n, 1)))}|rho{round(rho / 0.05)}|rc{rc:.2f}"
 
 
-def time_forces(grid, sched, cs, coord, ws, reps=5, warmup=2) -> float:
-    """Median-free average ms of one lc_compute_forces over `reps` calls."""
+def time_forces(grid, sched, cs, coord, ws, reps=5, warmup=2, rounds=3) -> float:
+    """ms of one lc_compute_forces: the fastest of `rounds` averages over
+    `reps` back-to-back calls (the minimum discards rounds slowed by other
+    work or clock changes)."""
     for _ in range(warmup):
         lc.compute_forces(grid, sched, cs, coord, ws)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        lc.compute_forces(grid, sched, cs, coord, ws)
-    e1.record()
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps
+    best = float("inf")
+    for _ in range(rounds):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            lc.compute_forces(grid, sched, cs, coord, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / reps)
+    return best
 
 
 def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
-             reps: int = 5, use_cache: bool = True) -> dict:
+             reps: int = 5, use_cache: bool = True, kinds=None) -> dict:
     """Pick grid, schedule kind and block shape for one box.
 
-    pos: (3, N) float64 cuda tensor.  Returns {"grid": {...}, "kind": str,
-    "block": [x, y, z], "ms": float, "trials": [...]}."""
+    pos: (3, N) float64 cuda tensor.  kinds: the schedule kinds to try
+    (default: the conflict-free ones, plus ATOMIC_TILE with allow_atomics).
+    Returns {"grid": {...}, "kind": str, "block": [x, y, z], "ms": float,
+    "trials": [...]} for the fastest of all trials."""
     n = pos.shape[1]
-    key = box_key(n, L, rc) + ("|atomics" if allow_atomics else "") + "|v2"
+    if kinds is None:
+        kinds = BOX_KINDS_CONFLICT_FREE + (("atomic_tile",) if allow_atomics else ())
+    kinds = tuple(kinds)
+    key = box_key(n, L, rc) + "|" + ",".join(kinds) + "|v3"
     cache = _load_cache() if use_cache else {}
     if key in cache:
         return cache[key]
-    kinds = BOX_KINDS_CONFLICT_FREE + (("atomic_tile",) if allow_atomics else ())
     trials = []
     best = None
+    warmed = False
     for gopt in GRIDS:
         try:
             grid = lc.Grid(L, rc, gopt["extra"], gopt["even"])
@@ -108,6 +118,13 @@ def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
             continue
         ws = lc.Workspace(n, grid.ncell)
         cs, perm, coord = lc.build_cells(grid, pos, ws)
+        if not warmed:  # bring the clocks up before the first trial counts
+            s0 = lc.Schedule(grid, kinds[0])
+            t_end = time.perf_counter() + 0.3
+            while time.perf_counter() < t_end:
+                time_forces(grid, s0, cs, coord, ws, reps=10, warmup=0, rounds=1)
+            s0.close()
+            warmed = True
         for kind in kinds:
             for block in shapes_for(kind):
                 try:

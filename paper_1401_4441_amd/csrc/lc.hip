@@ -504,7 +504,7 @@ struct SweepLDS {
     long long acc[WMODE == 2 ? 1 : 3][WMODE == 2 ? 1 : CAP];  // int64 forces
     int fg[kMaxF];          // global first slot of each footprint cell
     int fl[kMaxF + 1];      // local first slot (prefix over the footprint)
-    int frep[WMODE == 3 ? kMaxF : 1];  // replica slot of each footprint cell
+    int frep[WMODE >= 3 ? kMaxF : 1];  // replica slot (3) / home flag (4) of each footprint cell
     uint8_t pc[CAP];        // footprint cell of each staged particle
     int ta[kMaxT];          // task: local first slot of A | (count of A << 16)
     int tb[kMaxT];          // task: local first slot of B, bit 31 = intra
@@ -585,9 +585,11 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             atomicSub((unsigned long long *)&sh.acc[0][il], (unsigned long long)qx);
             atomicSub((unsigned long long *)&sh.acc[1][il], (unsigned long long)qy);
             atomicSub((unsigned long long *)&sh.acc[2][il], (unsigned long long)qz);
-            atomicAdd((unsigned long long *)&sh.acc[0][jl], (unsigned long long)qx);
-            atomicAdd((unsigned long long *)&sh.acc[1][jl], (unsigned long long)qy);
-            atomicAdd((unsigned long long *)&sh.acc[2][jl], (unsigned long long)qz);
+            if constexpr (WMODE != 4) {  // full shell: j gets its force from (j, i)
+                atomicAdd((unsigned long long *)&sh.acc[0][jl], (unsigned long long)qx);
+                atomicAdd((unsigned long long *)&sh.acc[1][jl], (unsigned long long)qy);
+                atomicAdd((unsigned long long *)&sh.acc[2][jl], (unsigned long long)qz);
+            }
         } else {
             // global path: into F, or (buffer + reduce) into this group's
             // replica slots, which no other group writes
@@ -602,9 +604,11 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             atomicAdd(&Fi[gi], (unsigned long long)(-qx));
             atomicAdd(&Fi[n + gi], (unsigned long long)(-qy));
             atomicAdd(&Fi[2 * n + gi], (unsigned long long)(-qz));
-            atomicAdd(&Fj[gj], (unsigned long long)qx);
-            atomicAdd(&Fj[n + gj], (unsigned long long)qy);
-            atomicAdd(&Fj[2 * n + gj], (unsigned long long)qz);
+            if constexpr (WMODE != 4) {
+                atomicAdd(&Fj[gj], (unsigned long long)qx);
+                atomicAdd(&Fj[n + gj], (unsigned long long)qy);
+                atomicAdd(&Fj[2 * n + gj], (unsigned long long)qz);
+            }
         }
     };
 
@@ -668,7 +672,9 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             const int a0 = valid ? aoff : 0;
             const int kmax = __builtin_amdgcn_readfirstlane(wave_max32(na));
             const uint2 hj = valid ? sh.h[jl] : make_uint2(0u, 0u);
-            const int lim = intra ? min(jj, na) : na;  // intra: i before j
+            // intra: i before j (each unordered pair once), or, in the full
+            // shell, every i but j itself
+            const int lim = (intra && WMODE != 4) ? min(jj, na) : na;
             const uint32_t rot = (uint32_t)jj & 31u;
             for (int k0 = 0; k0 < kmax; k0 += 32) {
                 const int kr = min(kmax - k0 + 3, 32) & ~3;  // rows read, uniform
@@ -694,6 +700,10 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
                 // row k sits at bit kr - 1 - k; keep rows k < lim - k0
                 const int nv = lim - k0;
                 m = nv <= 0 ? 0u : nv >= kr ? m : m & ~((1u << (kr - nv)) - 1u);
+                if constexpr (WMODE == 4) {  // drop the self pair
+                    const int sj = jj - k0;
+                    if (intra && sj >= 0 && sj < kr) m &= ~(1u << (kr - 1 - sj));
+                }
                 m = __builtin_amdgcn_alignbit(m, m, rot);  // rotate right
                 // entry of the bit at (rotated) position p: (i | j << 16) with
                 // i = a0 + k0 + kr - 1 - ((p + rot) & 31), no borrow into j
@@ -717,7 +727,7 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             const int kdiag = wave_max32(na);
             int ik = na > 0 ? jj % na : 0;
             for (int k = 0; k < kdiag; ++k) {
-                const bool act = k < na && (!intra || ik < jj);
+                const bool act = k < na && (!intra || (WMODE == 4 ? ik != jj : ik < jj));
                 bool in = false;
                 if (act) {
                     const uint4 ui = load_u(aoff + ik);
@@ -775,7 +785,7 @@ __device__ __forceinline__ void pre_foot(const SweepArgs &a, GroupPre &p) {
     const int tid = threadIdx.x;
     p.ab = tid < p.nt ? a.task_ab[p.t0 + tid] : 0u;
     p.c = tid < p.nf ? a.foot_cells[p.f0 + tid] : -1;
-    p.rep = (WMODE == 3 && tid < p.nf) ? a.foot_rep[p.f0 + tid] : 0;
+    p.rep = (WMODE >= 3 && tid < p.nf) ? a.foot_rep[p.f0 + tid] : 0;
 }
 
 __device__ __forceinline__ void pre_cells(const SweepArgs &a, GroupPre &p) {
@@ -800,7 +810,7 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
     const uint32_t my_ab = p.ab;
     int cnt = 0;
     if (tid < nf) {
-        if constexpr (WMODE == 3) sh.frep[tid] = p.rep;
+        if constexpr (WMODE >= 3) sh.frep[tid] = p.rep;
         cnt = p.ge - p.gs;
         sh.fg[tid] = p.gs;
     }
@@ -865,6 +875,20 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
             __syncthreads();
         }
     }
+    if constexpr (WMODE == 4) {
+        if (!staged) {  // the global path adds into F: clear the home particles
+            for (int k = tid; k < total; k += kWG) {
+                const int f = foot_cell(sh, nf, k);
+                if (!sh.frep[f]) continue;
+                const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
+                a.F[gi] = 0;
+                a.F[n + gi] = 0;
+                a.F[2 * n + gi] = 0;
+            }
+            __threadfence();
+            __syncthreads();
+        }
+    }
     // task table
     int nb = 0;
     if (tid < nt) {
@@ -886,7 +910,7 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
                 for (int d = 0; d < 3; ++d) {
                     if constexpr (WMODE == 0)
                         sh.acc[d][k] = sfo[r][d];
-                    else if constexpr (WMODE == 1 || WMODE == 3)
+                    else if constexpr (WMODE == 1 || WMODE >= 3)
                         sh.acc[d][k] = 0;
                 }
                 sh.u[k] = make_uint4(ux, uy, uz, 0u);
@@ -952,6 +976,16 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
             P[n + gi] = sh.acc[1][k];
             P[2 * n + gi] = sh.acc[2][k];
         }
+    } else if constexpr (WMODE == 4) {
+        if (!staged) return;
+        for (int k = wt < 0 ? total : wt; k < total; k += kWG - wb0) {
+            const int f = sh.pc[k];
+            if (!sh.frep[f]) continue;  // home particles only
+            const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
+            a.F[gi] = sh.acc[0][k];
+            a.F[n + gi] = sh.acc[1][k];
+            a.F[2 * n + gi] = sh.acc[2][k];
+        }
     } else if constexpr (WMODE != 2) {
         if (!staged) return;
         unsigned long long *F = (unsigned long long *)a.F;
@@ -976,7 +1010,8 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
 //        (the phase must be conflict-free); 1 = accumulate in LDS, global
 //        atomic write-back; 2 = every pair adds into global memory with
 //        atomics; 3 = accumulate in LDS, plain stores into the group's
-//        replica slots (buffer + reduce).
+//        replica slots (buffer + reduce); 4 = full shell: only the i side
+//        accumulates, plain stores of the group's home particles.
 // Occupancy: a 768-particle tile leaves LDS for three work-groups per
 // compute unit, which also needs at most 80 VGPRs (six waves per SIMD); the
 // register allocator then spills a few values outside the pair loops, which
@@ -1039,7 +1074,7 @@ void k_sweep(SweepArgs a) {
 // evaluation leaves them zero for the next, so no clearing launch is
 // needed (the workspace zeroes them once when it is created).
 __device__ __forceinline__ void reduce_parts_wg(long long *__restrict__ part, int ncomp,
-                                                long long *__restrict__ out) {
+                                                long long *__restrict__ out, int half = 0) {
     __shared__ long long s_w[4];
     for (int c = 0; c < ncomp; ++c) {
         long long v = 0;
@@ -1050,14 +1085,16 @@ __device__ __forceinline__ void reduce_parts_wg(long long *__restrict__ part, in
         v = wave_sum64(v);
         if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
         __syncthreads();
-        if (threadIdx.x == 0) out[c] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        // half: every pair was counted twice (full shell), so the sum is
+        // even and halves exactly
+        if (threadIdx.x == 0) out[c] = (s_w[0] + s_w[1] + s_w[2] + s_w[3]) >> half;
         __syncthreads();
     }
 }
 
 __global__ __launch_bounds__(256) void k_reduce_parts(long long *__restrict__ part, int ncomp,
-                                                      long long *__restrict__ out) {
-    reduce_parts_wg(part, ncomp, out);
+                                                      long long *__restrict__ out, int half) {
+    reduce_parts_wg(part, ncomp, out, half);
 }
 
 // Buffer + reduce: F of every particle = sum of its cell's replica slots.
@@ -1142,16 +1179,19 @@ static int launch_sweep(int cap, int wmode, bool f64, bool ff, const SweepArgs &
         if (wmode == 0) return launch_sweep_c<0, true, false>(cap, a, ng, ncu, tk, st);
         if (wmode == 1) return launch_sweep_c<1, true, false>(cap, a, ng, ncu, tk, st);
         if (wmode == 3) return launch_sweep_c<3, true, false>(cap, a, ng, ncu, tk, st);
+        if (wmode == 4) return launch_sweep_c<4, true, false>(cap, a, ng, ncu, tk, st);
         return launch_sweep_c<2, true, false>(cap, a, ng, ncu, tk, st);
     }
     if (ff) {
         if (wmode == 0) return launch_sweep_c<0, false, true>(cap, a, ng, ncu, tk, st);
         if (wmode == 1) return launch_sweep_c<1, false, true>(cap, a, ng, ncu, tk, st);
         if (wmode == 3) return launch_sweep_c<3, false, true>(cap, a, ng, ncu, tk, st);
+        if (wmode == 4) return launch_sweep_c<4, false, true>(cap, a, ng, ncu, tk, st);
     }
     if (wmode == 0) return launch_sweep_c<0, false, false>(cap, a, ng, ncu, tk, st);
     if (wmode == 1) return launch_sweep_c<1, false, false>(cap, a, ng, ncu, tk, st);
     if (wmode == 3) return launch_sweep_c<3, false, false>(cap, a, ng, ncu, tk, st);
+    if (wmode == 4) return launch_sweep_c<4, false, false>(cap, a, ng, ncu, tk, st);
     return launch_sweep_c<2, false, false>(cap, a, ng, ncu, tk, st);
 }
 
@@ -1202,7 +1242,8 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
                        const uint32_t *coord, int64_t n, int64_t *F, int64_t *ew, int precision,
                        lc_workspace *ws, hipStream_t st, hipEvent_t *ev = nullptr) {
     const bool buffered = s->h.write_mode == 3;
-    int rc = buffered ? LC_OK : fill64((long long *)F, 3 * n, st);
+    const bool fullshell = s->h.write_mode == 4;  // writes every particle itself
+    int rc = (buffered || fullshell) ? LC_OK : fill64((long long *)F, 3 * n, st);
     if (rc) return rc;
     if (buffered && (rc = ensure_pbuf(ws, (int64_t)s->h.rmax * 3 * n))) return rc;
     const int nphase = (int)s->h.phase_grp.size() - 1;
@@ -1255,7 +1296,7 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
         return LC_OK;
     }
     hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (long long *)ws->part, 3,
-                       (long long *)ew);
+                       (long long *)ew, fullshell ? 1 : 0);
     LAUNCHCHK("k_reduce_parts");
     return LC_OK;
 }
@@ -1760,7 +1801,7 @@ extern "C" int lc_kinetic_energy(const double *vel, int64_t n, int64_t *ke, lc_w
         LAUNCHCHK("k_kick_ke");
     }
     hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (long long *)ws->part, 1,
-                       (long long *)ke);
+                       (long long *)ke, 0);
     LAUNCHCHK("k_reduce_parts");
     return LC_OK;
 }
@@ -1822,7 +1863,7 @@ extern "C" int lc_verlet_step(const lc_grid *g, const lc_schedule *s, double *po
             LAUNCHCHK("k_kick_ke");
         }
         hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (long long *)ws->part, 1,
-                           row);
+                           row, 0);
         LAUNCHCHK("k_reduce_parts");
         hipLaunchKernelGGL(k_copy64, dim3(1), dim3(64), 0, st, (const long long *)ws->ew, row + 1, 1);
         LAUNCHCHK("k_copy64");

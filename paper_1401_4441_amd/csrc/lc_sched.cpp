@@ -301,7 +301,7 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
     // BLOCK8 colours its blocks, so their sizes are lower bounds (the
     // stencil reach) with an even block count per axis; the uncoloured kinds
     // take explicit sizes as upper bounds.
-    const bool coloured = kind == LC_SCHED_BLOCK8;
+    const bool coloured = kind == LC_SCHED_BLOCK8;  // FULLSHELL: uncoloured
     int32_t bmin[3] = {1, 2, 2};
     if (block_min) {
         for (int d = 0; d < 3; ++d) bmin[d] = block_min[d];
@@ -319,6 +319,57 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
     hs.grp_foot.push_back(0);
     hs.phase_grp.push_back(0);
     const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+
+    if (kind == LC_SCHED_FULLSHELL) {
+        // Blocks of home cells (sizes as upper bounds; default 1 x 2 x 2),
+        // each home cell with its intra task and its 26 full-shell
+        // neighbours; foot_rep marks the home cells (1), which alone are
+        // written.
+        static const int32_t dflt[3] = {1, 2, 2};
+        const int32_t *sz = block_min ? bmin : dflt;
+        std::vector<int> bs[3];
+        for (int d = 0; d < 3; ++d) bs[d] = axis_blocks_max(nc[d], sz[d]);
+        std::vector<Offset> shell(1, Offset{{0, 0, 0}});
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx)
+                    if (dx || dy || dz) shell.push_back(Offset{{(int8_t)dx, (int8_t)dy, (int8_t)dz}});
+        hs.write_mode = 4;
+        struct G {
+            std::vector<int32_t> A, B;
+        };
+        std::vector<G> groups;
+        for (size_t bz = 0; bz + 1 < bs[2].size(); ++bz)
+            for (size_t by = 0; by + 1 < bs[1].size(); ++by)
+                for (size_t bx = 0; bx + 1 < bs[0].size(); ++bx) {
+                    G gr;
+                    for (int z = bs[2][bz]; z < bs[2][bz + 1]; ++z)
+                        for (int y = bs[1][by]; y < bs[1][by + 1]; ++y)
+                            for (int x = bs[0][bx]; x < bs[0][bx + 1]; ++x) {
+                                const int32_t a = x + nc[0] * (y + nc[1] * z);
+                                for (const Offset &o : shell) {
+                                    gr.A.push_back(a);
+                                    gr.B.push_back((int32_t)(
+                                        wrap(x + o.d[0], nc[0]) +
+                                        nc[0] * (wrap(y + o.d[1], nc[1]) +
+                                                 nc[1] * wrap(z + o.d[2], nc[2]))));
+                                }
+                            }
+                    groups.push_back(std::move(gr));
+                }
+        std::stable_sort(groups.begin(), groups.end(),
+                         [](const G &x, const G &y) { return x.A.size() > y.A.size(); });
+        for (const G &gr : groups) {
+            const size_t f0 = hs.foot_cells.size();
+            if (!add_group(hs, gr.A, gr.B, err)) return LC_ECAPACITY;
+            for (size_t f = f0; f < hs.foot_cells.size(); ++f)
+                hs.foot_rep.push_back(
+                    std::find(gr.A.begin(), gr.A.end(), hs.foot_cells[f]) != gr.A.end() ? 1 : 0);
+        }
+        hs.phase_grp.push_back((int32_t)(hs.grp_task.size() - 1));
+        return LC_OK;
+    }
+
     std::vector<Offset> order;
     if (!stencil_order(kind, false, offsets, n, order, err)) return LC_EINVAL;
 
@@ -448,6 +499,26 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
 }
 
 bool validate(const HostSchedule &hs, int64_t ncell, std::string &err) {
+    if (hs.write_mode == 4) {
+        // full shell: every cell is the home (written) cell of exactly one
+        // work-group
+        std::vector<int32_t> home((size_t)ncell, 0);
+        for (size_t f = 0; f < hs.foot_cells.size(); ++f) {
+            const int32_t c = hs.foot_cells[f];
+            if (c < 0 || c >= ncell || f >= hs.foot_rep.size()) {
+                err = "footprint cell out of range";
+                return false;
+            }
+            if (hs.foot_rep[f]) home[(size_t)c]++;
+        }
+        for (int64_t c = 0; c < ncell; ++c)
+            if (home[(size_t)c] != 1) {
+                err = "cell " + std::to_string(c) + " is the home cell of " +
+                      std::to_string(home[(size_t)c]) + " work-groups";
+                return false;
+            }
+        return true;
+    }
     if (hs.write_mode != 0) return true;  // atomic write-back needs no colouring
     std::vector<int32_t> owner((size_t)ncell, -1);
     std::vector<int32_t> stamp((size_t)ncell, -1);

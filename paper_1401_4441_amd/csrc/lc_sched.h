@@ -57,7 +57,7 @@ int delta_rule(const std::vector<Offset> &order);
 // Device-ready schedule in host memory.
 struct HostSchedule {
     int kind = 0;
-    int write_mode = 0;               // 0 plain, 1 atomic tile, 2 atomic pair
+    int write_mode = 0;  // 0 plain, 1 atomic tile, 2 atomic pair, 3 replicas, 4 home only
     std::vector<int32_t> phase_grp;   // nphase + 1
     std::vector<int32_t> grp_task;    // ngroup + 1 (index into task_ab)
     std::vector<int32_t> grp_foot;    // ngroup + 1 (index into foot_cells)
@@ -70,7 +70,8 @@ struct HostSchedule {
     // (group-relative float coordinates then reproduce minimum images)
     bool compact = false;
     // buffer + reduce: replica slot of every footprint entry (parallel to
-    // foot_cells), replica count per cell, and its maximum
+    // foot_cells), replica count per cell, and its maximum; full shell
+    // (write mode 4): foot_rep = 1 for the group's home cells
     std::vector<int32_t> foot_rep;
     std::vector<int32_t> cell_rep;
     int rmax = 0;

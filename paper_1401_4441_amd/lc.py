@@ -17,10 +17,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblc.so")
 
 # schedule kinds (LC_SCHED_*)
-LEX, OPT, BEST, BAD, LOOPEX, BLOCK8, ATOMIC_TILE, ATOMIC_PAIR, CUSTOM, BUFFER = range(10)
+LEX, OPT, BEST, BAD, LOOPEX, BLOCK8, ATOMIC_TILE, ATOMIC_PAIR, CUSTOM, BUFFER, FULLSHELL = \
+    range(11)
 KINDS = {"lex": LEX, "opt": OPT, "best": BEST, "bad": BAD, "loopex": LOOPEX,
          "block8": BLOCK8, "atomic_tile": ATOMIC_TILE, "atomic_pair": ATOMIC_PAIR,
-         "custom": CUSTOM, "buffer": BUFFER}
+         "custom": CUSTOM, "buffer": BUFFER, "fullshell": FULLSHELL}
 PREC = {"fp32": 0, "fp64": 1}
 FLAG_OVERFLOW, FLAG_DISP, FLAG_FALLBACK = 1, 2, 4
 SCALE = 2.0 ** 32

@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 lc = pytest.importorskip("paper_1401_4441_amd.lc")
 
 DEV = torch.device("cuda:0")
-KINDS = ["block8", "buffer", "atomic_tile", "atomic_pair", "loopex", "opt", "lex"]
+KINDS = ["block8", "buffer", "atomic_tile", "atomic_pair", "loopex", "opt", "lex", "fullshell"]
 
 
 def _say(*a):
@@ -45,8 +45,8 @@ class Setup:
         out[:, self.perm_h] = Fh
         return out
 
-    def forces(self, kind, precision="fp32"):
-        s = lc.Schedule(self.g, kind)
+    def forces(self, kind, precision="fp32", block=None):
+        s = lc.Schedule(self.g, kind, block=block)
         self.ws.clear_status()
         F, ew = lc.compute_forces(self.g, s, self.cs, self.coord, self.ws, precision)
         torch.cuda.synchronize()
@@ -117,7 +117,7 @@ def test_c2_full_size_all_schedules():
     S = Setup(box, even=True)
     _say("fcc256k nc", S.g.nc)
     Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
-    for kind in ["block8", "buffer", "atomic_tile", "atomic_pair", "loopex", "lex"]:
+    for kind in ["block8", "buffer", "atomic_tile", "atomic_pair", "loopex", "lex", "fullshell"]:
         _say("  fcc256k", kind)
         F, ew, st = S.forces(kind)
         assert (F == Fo).all(), kind
@@ -132,7 +132,7 @@ def test_ragged_and_vacancies():
         S = Setup(box)
         _say("ragged", n, rho, S.g.nc)
         Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
-        for kind in ("block8", "buffer", "atomic_pair", "opt"):
+        for kind in ("block8", "buffer", "atomic_pair", "opt", "fullshell"):
             F, ew, _ = S.forces(kind)
             assert (F == Fo).all() and ew == [Eo, Wo, npo], (n, kind)
 
@@ -146,7 +146,7 @@ def test_minimum_grid_and_empty_cells():
         S = Setup(box)
         _say("small", box.n, S.g.nc)
         Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
-        for kind in ("block8", "buffer", "atomic_tile", "atomic_pair", "lex"):
+        for kind in ("block8", "buffer", "atomic_tile", "atomic_pair", "lex", "fullshell"):
             F, ew, _ = S.forces(kind)
             assert (F == Fo).all() and ew == [Eo, Wo, npo], kind
 
@@ -158,10 +158,24 @@ def test_lds_overflow_falls_back_exactly():
     S = Setup(box)
     _say("fallback nc", S.g.nc)
     Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
-    for kind in ("block8", "buffer", "atomic_tile"):
+    for kind in ("block8", "buffer", "atomic_tile", "fullshell"):
         F, ew, st = S.forces(kind)
         assert st & lc.FLAG_FALLBACK
         assert (F == Fo).all() and ew == [Eo, Wo, npo], kind
+
+
+@pytest.mark.parametrize("kind", ["buffer", "atomic_tile", "fullshell"])
+def test_block_shapes_bit_exact(kind):
+    """Uncoloured kinds over block shapes from single cells to blocks
+    larger than half the grid, on a ragged box with odd cell counts."""
+    box = synth.fcc(5003, 0.85, rc=2.5, seed=5)
+    S = Setup(box)
+    Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
+    for block in ((1, 1, 1), (1, 2, 3), (2, 2, 2), (1, 4, 4)):
+        _say("shape", kind, block, S.g.nc)
+        F, ew, st = S.forces(kind, block=block)
+        assert st & lc.FLAG_OVERFLOW == 0
+        assert (F == Fo).all() and ew == [Eo, Wo, npo], (kind, block)
 
 
 def test_overflow_flag():

@@ -145,6 +145,20 @@ def test_uncoloured_block_sizes_are_upper_bounds(kind):
         assert one["max_replicas"] == 14
 
 
+def test_fullshell_plan():
+    """Full shell: 27 tasks per cell in one phase, home cells written only
+    (every cell the home of exactly one group, checked by the validator)."""
+    g = lc.Grid((7 * 2.6,) * 3, 2.5)
+    info = lc.schedule_plan(g, "fullshell")
+    assert info["nphase"] == 1 and info["write_mode"] == 4
+    assert info["ntask"] == 27 * 343
+    one = lc.schedule_plan(g, "fullshell", block=(1, 1, 1))
+    assert one["ngroup"] == 343 and one["max_group_cells"] == 27
+    assert one["max_group_tasks"] == 27
+    big = lc.schedule_plan(g, "fullshell", block=(2, 2, 2))
+    assert big["ngroup"] == 4 * 4 * 4 and big["max_group_cells"] == 64
+
+
 def test_block8_sizes_are_lower_bounds():
     g = lc.Grid((7 * 2.6,) * 3, 2.5)
     with pytest.raises(lc.LCError):
