@@ -70,6 +70,8 @@ extern "C" {
 #define LC_FLAG_DISP 2u      /* displacement since rebuild > skin / 2        */
 #define LC_FLAG_FALLBACK 4u  /* a cell group exceeded the LDS tile and ran
                                 through the global-memory path (info only)   */
+#define LC_FLAG_ABORT 8u     /* a dataflow wait exceeded its time limit: the
+                                evaluation was abandoned, forces incomplete  */
 
 /* Last error message of the calling thread (never NULL). */
 const char *lc_last_error(void);
@@ -311,6 +313,38 @@ int lc_compute_forces_profiled(const lc_grid *g, const lc_schedule *s,
                                int64_t n, int64_t *F, int64_t *ew, int precision,
                                lc_workspace *ws, void *stream, double *sweep_ms,
                                double *phase_ms);
+
+/* ---- Sec. VI strategy 2 and the mutual exclusion of Sec. VII: dataflow
+ * execution of a creation order on the device -------------------------- */
+#define LC_DF_ORDERED 0 /* the StarSs inout dependences of the creation order:
+                           a task starts once every earlier task on either of
+                           its cells has finished (per-cell sequence
+                           counters); the run follows the order's critical
+                           path without one launch per DAG level          */
+#define LC_DF_MUTEX 1   /* the tasks in creation order under mutual exclusion
+                           on the two cells they write (the clause Sec. VII
+                           asks for): no order between them, no two at once
+                           on one cell                                     */
+#define LC_DF_NESTED 2  /* Sec. VI strategy 2: per cell one chain, intra
+                           then the stencil neighbours in order, each chain
+                           started as soon as a runner is free; the writes
+                           of concurrent chains are kept apart by the same
+                           per-cell mutual exclusion (not for LOOPEX)      */
+/* One force evaluation by the dataflow executor `mode` (LC_DF_*) over the
+ * tasks of schedule s, which must be a creation-order kind (LEX, OPT, BEST,
+ * BAD, CUSTOM, LOOPEX).  One persistent launch of single-wave task runners
+ * takes work units (a task, or a chain for NESTED) in creation order; each
+ * waits for its cells (counters or locks, lower cell first), evaluates the
+ * cell pair with the canonical pair arithmetic and adds into F directly.
+ * Results are bit-identical to lc_compute_forces.  Every wait is bounded by
+ * limit_ms of wall time: on expiry the evaluation is abandoned (all runners
+ * stop, LC_FLAG_ABORT is set, F is incomplete) instead of hanging.  Cells may
+ * hold at most 256 particles (LC_ECAPACITY when the workspace's tile hint
+ * says more).  Arguments otherwise as lc_compute_forces (FP32 pair math). */
+int lc_compute_forces_dataflow(const lc_grid *g, const lc_schedule *s, int mode,
+                               const int32_t *cell_start, const uint32_t *coord, int64_t n,
+                               int64_t *F, int64_t *ew, double limit_ms, lc_workspace *ws,
+                               void *stream);
 
 /* ---- a7: velocity Verlet ------------------------------------------------ */
 

@@ -83,6 +83,8 @@ struct lc_workspace {
     long long *pbuf = nullptr;   // replica partial sums (buffer + reduce)
     int64_t pbuf_elems = 0;
     int32_t max_per_cell = 0;    // tile sizing hint (0: mean density)
+    int32_t *df_sync = nullptr;  // dataflow: per-cell counter or lock
+    int32_t *df_ctl = nullptr;   // dataflow: ticket, abort
 };
 
 struct lc_schedule {
@@ -93,6 +95,9 @@ struct lc_schedule {
     int32_t *grp_task = nullptr, *grp_foot = nullptr, *foot_cells = nullptr;
     uint32_t *task_ab = nullptr;
     int32_t *foot_rep = nullptr, *cell_rep = nullptr;  // buffer + reduce
+    // creation-order kinds: tasks in creation order and, per task, how many
+    // earlier tasks touch its cells A and B (dataflow executors)
+    int32_t *df_a = nullptr, *df_b = nullptr, *df_seqa = nullptr, *df_seqb = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -1128,6 +1133,216 @@ __global__ __launch_bounds__(256) void k_gather_partials(
     F[2 * n + p] = fz;
 }
 
+// ---------------------------------------------------------------------------
+// Dataflow executors: one persistent launch of single-wave task runners that
+// take work units in creation order (Sec. VI strategy 2, and the mutual
+// exclusion Sec. VII asks for).
+// ---------------------------------------------------------------------------
+constexpr int kDfCell = 256;  // largest cell a runner stages (LDS)
+
+struct DfArgs {
+    const int32_t *ta, *tb;      // tasks in creation order: cells A, B
+    const int32_t *seqa, *seqb;  // earlier tasks touching A, B (ORDERED)
+    int64_t nunit;               // work units (tasks, or chains for NESTED)
+    int chain;                   // tasks per unit (NESTED)
+    const int32_t *cell_start;
+    const uint32_t *coord;
+    int64_t n;
+    long long *F;
+    long long *part;             // spread energy slots
+    int *sync;                   // per cell: completed tasks (ORDERED) or lock
+    int *ctl;                    // [0] unit ticket, [1] abort
+    uint32_t *flags;
+    PairParams pp;
+    unsigned long long limit;    // longest wait in s_memrealtime ticks (100 MHz)
+};
+
+// Bounded wait of lane 0 for `ok(v)` on *p, or (cas) for the lock at *p to
+// be free and taken (only lane 0 polls, inside a divergent branch, so the
+// accesses are vector memory operations).  Gives up when another runner has
+// aborted or after a.limit ticks, then aborts everyone.  Returns the verdict
+// to all lanes.  No fence: the force adds are device atomics, so the waits
+// carry no data, only the strategy's scheduling constraint.
+template <class OK>
+__device__ __forceinline__ bool df_wait(const DfArgs &a, int *p, OK ok, bool cas) {
+    int got = 1;
+    if (threadIdx.x == 0) {
+        const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+        for (;;) {
+            if (cas) {  // test, then test-and-set
+                if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
+                    atomicCAS(p, 0, 1) == 0)
+                    break;
+            } else if (ok(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                break;
+            }
+            if (__hip_atomic_load(&a.ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                got = 0;
+                break;
+            }
+            if (__builtin_amdgcn_s_memrealtime() - t0 > a.limit) {
+                __hip_atomic_store(&a.ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                atomicOr(a.flags, (uint32_t)LC_FLAG_ABORT);
+                got = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+    }
+    got = __builtin_amdgcn_readfirstlane(got);
+    return got != 0;
+}
+
+// One cell-pair task by one wave: A's box fractions staged in LDS, lanes own
+// B's particles 64 at a time and visit A in diagonal order (at each step the
+// lanes add into different A particles).  Intra tasks keep i before j.  The
+// sums go into F with device atomics: plain read-modify-writes would need a
+// device-scope release and acquire around every task, which on a GPU of
+// several L2 caches (one per XCD) writes back and invalidates a whole L2
+// each time; integer adds commute, so the result is the same.
+__device__ __forceinline__ void df_task(const DfArgs &a, int A, int B, uint32_t (*su)[kDfCell],
+                                        long long (*acc)[kDfCell], long long &e_sum,
+                                        long long &w_sum, long long &p_cnt, uint32_t &ovf) {
+    const int lane = threadIdx.x;
+    const int64_t n = a.n;
+    const int sA = a.cell_start[A], na = a.cell_start[A + 1] - sA;
+    const int sB = a.cell_start[B], nb = a.cell_start[B + 1] - sB;
+    if (na > kDfCell || nb > kDfCell) {  // the host checks the tile hint first
+        if (lane == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_OVERFLOW);
+        return;
+    }
+    for (int k = lane; k < na; k += 64) {
+        su[0][k] = a.coord[sA + k];
+        su[1][k] = a.coord[n + sA + k];
+        su[2][k] = a.coord[2 * n + sA + k];
+        acc[0][k] = acc[1][k] = acc[2][k] = 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    const bool intra = A == B;
+    for (int j0 = 0; j0 < nb; j0 += 64) {
+        const int jl = j0 + lane;
+        const bool vj = jl < nb;
+        uint4 uj = make_uint4(0u, 0u, 0u, 0u);
+        if (vj) uj = make_uint4(a.coord[sB + jl], a.coord[n + sB + jl], a.coord[2 * n + sB + jl], 0u);
+        long long fx = 0, fy = 0, fz = 0;
+        int i = na > 0 ? lane % na : 0;  // diagonal: lane + k modulo na
+        for (int k = 0; k < na; ++k, i = i + 1 == na ? 0 : i + 1) {
+            if (!vj || (intra && i >= jl)) continue;
+            const uint4 ui = make_uint4(su[0][i], su[1][i], su[2][i], 0u);
+            long long qx, qy, qz, qe, qw;
+            if (!pair_terms_fast(ui, uj, a.pp, qx, qy, qz, qe, qw, ovf)) continue;
+            e_sum += qe;
+            w_sum += qw;
+            p_cnt += 1;
+            atomicSub((unsigned long long *)&acc[0][i], (unsigned long long)qx);
+            atomicSub((unsigned long long *)&acc[1][i], (unsigned long long)qy);
+            atomicSub((unsigned long long *)&acc[2][i], (unsigned long long)qz);
+            fx += qx;
+            fy += qy;
+            fz += qz;
+        }
+        if (vj) {
+            if (intra) {  // j is a particle of A as well
+                atomicAdd((unsigned long long *)&acc[0][jl], (unsigned long long)fx);
+                atomicAdd((unsigned long long *)&acc[1][jl], (unsigned long long)fy);
+                atomicAdd((unsigned long long *)&acc[2][jl], (unsigned long long)fz);
+            } else {
+                atomicAdd((unsigned long long *)&a.F[sB + jl], (unsigned long long)fx);
+                atomicAdd((unsigned long long *)&a.F[n + sB + jl], (unsigned long long)fy);
+                atomicAdd((unsigned long long *)&a.F[2 * n + sB + jl], (unsigned long long)fz);
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    for (int k = lane; k < na; k += 64) {
+        atomicAdd((unsigned long long *)&a.F[sA + k], (unsigned long long)acc[0][k]);
+        atomicAdd((unsigned long long *)&a.F[n + sA + k], (unsigned long long)acc[1][k]);
+        atomicAdd((unsigned long long *)&a.F[2 * n + sA + k], (unsigned long long)acc[2][k]);
+    }
+}
+
+// MODE 0: ordered (sequence counters), 1: mutual exclusion per task,
+// 2: nested (a chain per unit, mutual exclusion per task).
+template <int MODE>
+__global__ __launch_bounds__(64) void k_dataflow(DfArgs a) {
+    __shared__ uint32_t su[3][kDfCell];
+    __shared__ long long acc[3][kDfCell];
+    const int lane = threadIdx.x;
+    long long e_sum = 0, w_sum = 0, p_cnt = 0;
+    uint32_t ovf = 0;
+    bool stop = false;
+    // Units come in creation order, kBatch per ticket (fewer atomics on the
+    // one counter, and consecutive tasks, which often share a cell, stay on
+    // one runner); a runner takes its units in increasing order.  Every
+    // unit held belongs to a running runner, and the smallest unfinished
+    // unit is its runner's current one with all its predecessors done, so
+    // the ordered waits always progress; locks are taken lower cell first,
+    // so mutual exclusion cannot deadlock either.
+    constexpr int kBatch = MODE == 2 ? 1 : 8;
+    int64_t unit = 0, uend = 0;
+    while (!stop) {
+        if (unit == uend) {
+            int u = 0;
+            if (lane == 0) u = atomicAdd(&a.ctl[0], kBatch);
+            unit = __builtin_amdgcn_readfirstlane(u);
+            uend = unit + kBatch;
+        }
+        if (unit >= a.nunit) break;
+        const int64_t t0 = MODE == 2 ? unit * a.chain : unit;
+        const int64_t t1 = MODE == 2 ? t0 + a.chain : t0 + 1;
+        ++unit;
+        for (int64_t t = t0; t < t1; ++t) {
+            const int A = a.ta[t], B = a.tb[t];
+            const int lo = A < B ? A : B, hi = A < B ? B : A;
+            if constexpr (MODE == 0) {
+                const int qa = a.seqa[t], qb = a.seqb[t];
+                if (!df_wait(a, &a.sync[A], [qa](int v) { return v == qa; }, false) ||
+                    (B != A && !df_wait(a, &a.sync[B], [qb](int v) { return v == qb; }, false))) {
+                    stop = true;
+                    break;
+                }
+            } else {
+                auto any = [](int) { return true; };
+                if (!df_wait(a, &a.sync[lo], any, true)) {
+                    stop = true;
+                    break;
+                }
+                if (hi != lo && !df_wait(a, &a.sync[hi], any, true)) {
+                    if (lane == 0) __hip_atomic_store(&a.sync[lo], 0, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                    stop = true;
+                    break;
+                }
+            }
+            df_task(a, A, B, su, acc, e_sum, w_sum, p_cnt, ovf);
+            __builtin_amdgcn_wave_barrier();  // the whole wave is done with the task
+            if (lane == 0) {
+                if constexpr (MODE == 0) {
+                    atomicAdd(&a.sync[A], 1);
+                    if (B != A) atomicAdd(&a.sync[B], 1);
+                } else {
+                    if (hi != lo)
+                        __hip_atomic_store(&a.sync[hi], 0, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&a.sync[lo], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+    }
+    e_sum = wave_sum64(e_sum);
+    w_sum = wave_sum64(w_sum);
+    p_cnt = wave_sum64(p_cnt);
+    if (lane == 0) {
+        long long *dst = &a.part[(blockIdx.x % kPartSlots) * 3];
+        atomicAdd((unsigned long long *)&dst[0], (unsigned long long)e_sum);
+        atomicAdd((unsigned long long *)&dst[1], (unsigned long long)w_sum);
+        atomicAdd((unsigned long long *)&dst[2], (unsigned long long)p_cnt);
+    }
+    if (__ballot(ovf != 0u) && lane == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_OVERFLOW);
+}
+
 // A phase with more groups than the device holds at once runs persistent:
 // as many work-groups as fit (occupancy x compute units), each drawing
 // groups from the phase's ticket counter, which the caller has zeroed.
@@ -1445,6 +1660,8 @@ extern "C" void lc_workspace_destroy(lc_workspace *ws) {
     (void)hipFree(ws->xref);
     (void)hipFree(ws->tmp3);
     (void)hipFree(ws->tmpi);
+    (void)hipFree(ws->df_sync);
+    (void)hipFree(ws->df_ctl);
     (void)hipFree(ws->pbuf);
     (void)hipSetDevice(cur);
     delete ws;
@@ -1572,6 +1789,22 @@ extern "C" int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *off
         lc_schedule_free(s);
         return rc;
     }
+    if (!s->h.order_a.empty()) {  // creation-order kind: the dataflow task list
+        const size_t nt = s->h.order_a.size();
+        std::vector<int32_t> seen((size_t)g->ncell, 0), sa(nt), sb(nt);
+        for (size_t t = 0; t < nt; ++t) {
+            const int32_t a = s->h.order_a[t], b = s->h.order_b[t];
+            sa[t] = seen[(size_t)a];
+            sb[t] = seen[(size_t)b];
+            seen[(size_t)a]++;
+            if (b != a) seen[(size_t)b]++;
+        }
+        if ((rc = up(&s->df_a, s->h.order_a)) || (rc = up(&s->df_b, s->h.order_b)) ||
+            (rc = up(&s->df_seqa, sa)) || (rc = up(&s->df_seqb, sb))) {
+            lc_schedule_free(s);
+            return rc;
+        }
+    }
     *out = s;
     return LC_OK;
 }
@@ -1587,6 +1820,10 @@ extern "C" void lc_schedule_free(lc_schedule *s) {
     (void)hipFree(s->task_ab);
     (void)hipFree(s->foot_rep);
     (void)hipFree(s->cell_rep);
+    (void)hipFree(s->df_a);
+    (void)hipFree(s->df_b);
+    (void)hipFree(s->df_seqa);
+    (void)hipFree(s->df_seqb);
     (void)hipSetDevice(cur);
     delete s;
 }
@@ -1745,6 +1982,87 @@ extern "C" int lc_compute_forces(const lc_grid *g, const lc_schedule *s, const i
     int rc = check_ws(ws, 0, 0);
     if (rc) return rc;
     return forces_impl(g, s, cell_start, coord, n, F, ew, precision, ws, (hipStream_t)stream);
+}
+
+template <int MODE>
+static int launch_dataflow(const DfArgs &a, int ncu, hipStream_t st) {
+    static int per_cu = 0;
+    int res = per_cu;
+    if (res == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, reinterpret_cast<const void *>(&k_dataflow<MODE>), 64, 0) == hipSuccess &&
+            nb >= 1)
+            per_cu = res = nb;
+        else
+            res = 1;
+    }
+    const int64_t grid = std::min<int64_t>(a.nunit, (int64_t)res * ncu);
+    if (grid > 0) {
+        hipLaunchKernelGGL(k_dataflow<MODE>, dim3((unsigned)grid), dim3(64), 0, st, a);
+        LAUNCHCHK("k_dataflow");
+    }
+    return LC_OK;
+}
+
+extern "C" int lc_compute_forces_dataflow(const lc_grid *g, const lc_schedule *s, int mode,
+                                          const int32_t *cell_start, const uint32_t *coord,
+                                          int64_t n, int64_t *F, int64_t *ew, double limit_ms,
+                                          lc_workspace *ws, void *stream) {
+    if (!g || !s || !cell_start || !F || !ew || (n > 0 && !coord))
+        return fail(LC_EINVAL, "lc_compute_forces_dataflow: null argument");
+    if (mode < LC_DF_ORDERED || mode > LC_DF_NESTED)
+        return fail(LC_EINVAL, "lc_compute_forces_dataflow: unknown mode %d", mode);
+    if (s->nc[0] != g->nc[0] || s->nc[1] != g->nc[1] || s->nc[2] != g->nc[2])
+        return fail(LC_EINVAL, "lc_compute_forces_dataflow: schedule built for another grid");
+    if (!s->df_a)
+        return fail(LC_EINVAL, "lc_compute_forces_dataflow: needs a creation-order schedule "
+                               "(LEX, OPT, BEST, BAD, CUSTOM or LOOPEX)");
+    if (mode == LC_DF_NESTED && s->h.chain <= 0)
+        return fail(LC_EINVAL, "lc_compute_forces_dataflow: loop exchange has no per-cell chains");
+    if (!(limit_ms >= 0.0) || limit_ms > 6.0e4)
+        return fail(LC_EINVAL, "lc_compute_forces_dataflow: limit_ms must be in [0, 60000]");
+    int rc = check_ws(ws, n, g->ncell);
+    if (rc) return rc;
+    if (ws->max_per_cell > kDfCell)
+        return fail(LC_ECAPACITY, "lc_compute_forces_dataflow: cells of up to %d particles "
+                                  "(tile hint %d)", kDfCell, ws->max_per_cell);
+    hipStream_t st = (hipStream_t)stream;
+    if (!ws->df_sync) {
+        if ((rc = dalloc(&ws->df_sync, ws->max_cells)) || (rc = dalloc(&ws->df_ctl, 2))) return rc;
+    }
+    if ((rc = fill32(ws->df_sync, g->ncell, st)) || (rc = fill32(ws->df_ctl, 2, st)) ||
+        (rc = fill64((long long *)F, 3 * n, st)))
+        return rc;
+    DfArgs a;
+    a.ta = s->df_a;
+    a.tb = s->df_b;
+    a.seqa = s->df_seqa;
+    a.seqb = s->df_seqb;
+    const int64_t ntask = (int64_t)s->h.order_a.size();
+    a.chain = mode == LC_DF_NESTED ? s->h.chain : 1;
+    a.nunit = mode == LC_DF_NESTED ? ntask / s->h.chain : ntask;
+    a.cell_start = cell_start;
+    a.coord = coord;
+    a.n = n;
+    a.F = (long long *)F;
+    a.part = (long long *)ws->part;
+    a.sync = ws->df_sync;
+    a.ctl = ws->df_ctl;
+    a.flags = ws->flags;
+    a.pp = pair_params(g);
+    a.limit = (unsigned long long)(limit_ms * 1.0e5);  // s_memrealtime: 100 MHz
+    if (mode == LC_DF_ORDERED)
+        rc = launch_dataflow<0>(a, s->ncu, st);
+    else if (mode == LC_DF_MUTEX)
+        rc = launch_dataflow<1>(a, s->ncu, st);
+    else
+        rc = launch_dataflow<2>(a, s->ncu, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (long long *)ws->part, 3,
+                       (long long *)ew, 0);
+    LAUNCHCHK("k_reduce_parts");
+    return LC_OK;
 }
 
 extern "C" int lc_compute_forces_profiled(const lc_grid *g, const lc_schedule *s,

@@ -473,6 +473,11 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
     }
     std::vector<int32_t> level;
     const int64_t cp = task_levels(ncell, A, B, level);
+    hs.cp = cp;
+    // the creation order itself, for the dataflow executors
+    hs.order_a = A;
+    hs.order_b = B;
+    hs.chain = kind == LC_SCHED_LOOPEX ? 0 : (int)order.size();
     // bucket tasks by level, keeping creation order inside a level
     std::vector<int64_t> cnt((size_t)cp + 2, 0);
     for (int32_t l : level) cnt[(size_t)l + 1]++;

@@ -75,6 +75,13 @@ struct HostSchedule {
     std::vector<int32_t> foot_rep;
     std::vector<int32_t> cell_rep;
     int rmax = 0;
+    // creation-order kinds: the tasks in creation order (cell A, cell B),
+    // the critical path, and the per-cell chain length of the basic
+    // traversal (tasks [c * chain, (c + 1) * chain) are cell c's stencil;
+    // 0 for loop exchange, whose order has no per-cell chains)
+    std::vector<int32_t> order_a, order_b;
+    int64_t cp = 0;
+    int chain = 0;
 };
 
 constexpr int kMaxGroupTasks = 512;

@@ -23,7 +23,9 @@ KINDS = {"lex": LEX, "opt": OPT, "best": BEST, "bad": BAD, "loopex": LOOPEX,
          "block8": BLOCK8, "atomic_tile": ATOMIC_TILE, "atomic_pair": ATOMIC_PAIR,
          "custom": CUSTOM, "buffer": BUFFER, "fullshell": FULLSHELL}
 PREC = {"fp32": 0, "fp64": 1}
-FLAG_OVERFLOW, FLAG_DISP, FLAG_FALLBACK = 1, 2, 4
+FLAG_OVERFLOW, FLAG_DISP, FLAG_FALLBACK, FLAG_ABORT = 1, 2, 4, 8
+# dataflow executors (LC_DF_*)
+DATAFLOW = {"ordered": 0, "mutex": 1, "nested": 2}
 SCALE = 2.0 ** 32
 
 
@@ -86,6 +88,7 @@ SYMBOLS = {
     "lc_serialization_degree": ([P, INT, P, INT, P, I64, P], INT),
     "lc_serialization_degree_weighted": ([P, INT, P, INT, P, P], INT),
     "lc_compute_forces": ([P, P, P, P, I64, P, P, INT, P, P], INT),
+    "lc_compute_forces_dataflow": ([P, P, INT, P, P, I64, P, P, ctypes.c_double, P, P], INT),
     "lc_compute_forces_profiled": ([P, P, P, P, I64, P, P, INT, P, P, P, P], INT),
     "lc_verlet_step": ([P, P, P, P, P, I64, P, P, P, P, ctypes.c_double, INT,
                         INT, P, P, P], INT),
@@ -326,6 +329,26 @@ def compute_forces(grid: Grid, sched: Schedule, cell_start, coord, ws: Workspace
     _chk(lib().lc_compute_forces(grid.ptr, sched.ptr, _p(cell_start), _p(coord), n,
                                  _p(F), _p(ew), PREC[precision], ws.ptr,
                                  _stream(stream)))
+    return F, ew
+
+
+def compute_forces_dataflow(grid: Grid, sched: Schedule, cell_start, coord, ws: Workspace,
+                            mode: str = "ordered", F=None, ew=None, limit_ms: float = 2000.0,
+                            stream=None):
+    """One force evaluation by a dataflow executor over a creation-order
+    schedule (mode: "ordered" = the creation order's dependences, "mutex" =
+    per-cell mutual exclusion, "nested" = per-cell chains under mutual
+    exclusion).  Every wait is bounded by limit_ms; an expired wait abandons
+    the evaluation and sets FLAG_ABORT.  Returns (F, ew) as compute_forces."""
+    n = coord.shape[1]
+    dev = coord.device
+    if F is None:
+        F = torch.empty((3, n), dtype=torch.int64, device=dev)
+    if ew is None:
+        ew = torch.empty(3, dtype=torch.int64, device=dev)
+    _chk(lib().lc_compute_forces_dataflow(grid.ptr, sched.ptr, DATAFLOW[mode], _p(cell_start),
+                                          _p(coord), n, _p(F), _p(ew), float(limit_ms),
+                                          ws.ptr, _stream(stream)))
     return F, ew
 
 
