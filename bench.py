@@ -297,6 +297,7 @@ def main():
                 continue
             sdo[k] = {"cp": v["cp"], "S": v["speedup"], "delta": v["delta"], "S_eq2": v["s_eq2"]}
         out["serialization_degree"] = sdo
+        out["paper_strategies"] = paper_strategies(box, pos)
 
     # ---- CPU baseline: the serial oracle on the host (rank 0, N=1 only)
     if not args.no_cpu:
@@ -314,6 +315,55 @@ def main():
             "sample": f"{len(times)} full serial fixed-point link-cell evaluations of the "
                       f"same {box.n}-particle box (median {t:.3f} s each)"}
     print(json.dumps(out), flush=True)
+
+
+def paper_strategies(box, pos):
+    """The paper's comparison on the device, on the even grid (loop exchange
+    needs even cell counts): every creation order (bad, lex = the standard
+    order, opt, loop exchange) with its exact critical path, run (a) as one
+    launch per DAG level and (b) as one dataflow launch that follows the
+    order's dependences; strategy 2 (nested chains) and plain mutual
+    exclusion over the opt order; strategy 3 (buffer + reduce), the
+    colouring and the full shell as the conflict-free references."""
+    import torch
+    from paper_1401_4441_amd import lc
+    g = lc.Grid(box.L, box.rc, 0.0, True)
+    ws = lc.Workspace(box.n, g.ncell)
+    cs, perm, coord = lc.build_cells(g, pos, ws)
+
+    def one(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    rows = {}
+    ws.clear_status()
+    for kind in ("bad", "lex", "opt", "loopex"):
+        s = lc.Schedule(g, kind)
+        sd = lc.serialization_degree(g.nc, kind)
+        reps = 1 if sd["cp"] > 50000 else 3
+        rows[kind] = {
+            "cp": sd["cp"], "S": sd["speedup"],
+            "levels_ms": one(lambda: lc.compute_forces(g, s, cs, coord, ws), reps),
+            "dataflow_ordered_ms": one(lambda: lc.compute_forces_dataflow(
+                g, s, cs, coord, ws, "ordered", limit_ms=20000.0), reps)}
+        if kind == "opt":
+            for mode in ("nested", "mutex"):
+                rows[kind][f"dataflow_{mode}_ms"] = one(lambda: lc.compute_forces_dataflow(
+                    g, s, cs, coord, ws, mode, limit_ms=20000.0), 3)
+        s.close()
+    for kind in ("buffer", "block8", "fullshell"):
+        s = lc.Schedule(g, kind)
+        rows[kind] = {"ms": one(lambda: lc.compute_forces(g, s, cs, coord, ws), 10)}
+        s.close()
+    return {"cells": list(g.nc), "status_flags": ws.status(), "rows": rows}
 
 
 def _time_evals(fn, steps, warmup):

@@ -1273,14 +1273,16 @@ __global__ __launch_bounds__(64) void k_dataflow(DfArgs a) {
     long long e_sum = 0, w_sum = 0, p_cnt = 0;
     uint32_t ovf = 0;
     bool stop = false;
-    // Units come in creation order, kBatch per ticket (fewer atomics on the
-    // one counter, and consecutive tasks, which often share a cell, stay on
-    // one runner); a runner takes its units in increasing order.  Every
-    // unit held belongs to a running runner, and the smallest unfinished
-    // unit is its runner's current one with all its predecessors done, so
-    // the ordered waits always progress; locks are taken lower cell first,
-    // so mutual exclusion cannot deadlock either.
-    constexpr int kBatch = MODE == 2 ? 1 : 8;
+    // Units come from one counter in creation order, a runner taking its
+    // next ticket when its unit is done: ordered, one task per ticket (a
+    // runner blocked on one task then holds back no other); mutex, 8
+    // consecutive tasks per ticket (consecutive tasks often share a cell,
+    // and the counter sees fewer atomics); nested, one chain per ticket.
+    // Every unit held belongs to a running runner, and the smallest
+    // unfinished one is its runner's current unit with all its predecessors
+    // done, so the ordered waits always progress; locks are taken lower cell
+    // first, so mutual exclusion cannot deadlock either.
+    constexpr int kBatch = MODE == 1 ? 8 : 1;
     int64_t unit = 0, uend = 0;
     while (!stop) {
         if (unit == uend) {
