@@ -396,12 +396,16 @@ def bench_md(args):
     dt = 0.005 and a cell rebuild every 10 steps (cells of rc + 0.6 skin)."""
     import torch
     from paper_1401_4441_amd import lc, synth
+    from paper_1401_4441_amd import autotune
     box = synth.workload("fcc4m")
     dev = torch.device("cuda:0")
     g = lc.Grid(box.L, box.rc, 0.6, True)
-    ws = lc.Workspace(box.n, g.ncell)
-    sched = lc.Schedule(g, "buffer")
     pos = torch.from_numpy(box.pos).to(dev)
+    # the skin fixes the grid; the schedule and block shape are tuned on the
+    # starting configuration
+    tune = autotune.tune_shape(g, pos)
+    ws = lc.Workspace(box.n, g.ncell)
+    sched = lc.Schedule(g, tune["kind"], block=tune["block"])
     vel = torch.from_numpy(box.vel).to(dev)
     ids = torch.arange(box.n, dtype=torch.int32, device=dev)
     cs, perm, coord = lc.build_cells(g, pos, ws)  # sets the tile hint
@@ -426,7 +430,7 @@ def bench_md(args):
           pairs / (ms * 1e-3), "pairs/s", ms, args,
           {"workload": "LJ FCC+jitter N=4000000 rho=0.8 rc=2.5, MB T=1, dt=0.005, "
                        "rebuild every 10, skin 0.6, 54^3 cells", "nsteps": nsteps,
-           "schedule": "buffer", "status_flags": st},
+           "schedule": tune["kind"], "block": tune["block"], "status_flags": st},
           dtype="f32 pairs, int64 forces, f64 positions/velocities/energies",
           energy={"E0_per_particle": etot[0] / box.n,
                   "drift_per_particle": (etot[-1] - etot[0]) / box.n,
@@ -438,29 +442,37 @@ def bench_slab(args):
     """2M-particle slab (dense middle third, dilute gas), rc = 3.0."""
     import torch
     from paper_1401_4441_amd import lc, synth
+    from paper_1401_4441_amd import autotune
     box = synth.workload("slab2m")
     dev = torch.device("cuda:0")
-    g = lc.Grid(box.L, box.rc, 0.0, True)
-    ws = lc.Workspace(box.n, g.ncell)
     pos = torch.from_numpy(box.pos).to(dev)
+    tune = autotune.tune_box(pos, box.L, box.rc, reps=5, use_cache=False,
+                             kinds=("block8", "buffer", "atomic_tile", "fullshell"))
+    cf = [t for t in tune["trials"] if t["kind"] in autotune.BOX_KINDS_CONFLICT_FREE]
+    pick = min(cf, key=lambda t: t["ms"])
+    g = lc.Grid(box.L, box.rc, pick["grid"]["extra"], pick["grid"]["even"])
+    ws = lc.Workspace(box.n, g.ncell)
     cs, perm, coord = lc.build_cells(g, pos, ws)
     F = torch.empty((3, box.n), dtype=torch.int64, device=dev)
     ew = torch.empty(3, dtype=torch.int64, device=dev)
     res = {}
-    for kind in ("buffer", "block8", "atomic_tile", "atomic_pair"):
-        s = lc.Schedule(g, kind)
+    for kind in ("buffer", "block8", "atomic_tile", "fullshell", "atomic_pair"):
+        on_grid = [t for t in tune["trials"] if t["kind"] == kind and t["grid"] == pick["grid"]]
+        blk = tuple(min(on_grid, key=lambda t: t["ms"])["block"]) if on_grid else None
+        s = lc.Schedule(g, kind, block=blk)
         ws.clear_status()
         ms = _time_evals(lambda: lc.compute_forces(g, s, cs, coord, ws, "fp32", F, ew),
                          max(args.steps // 5, 3), 2)
-        res[kind] = {"ms": ms, "status_flags": ws.status()}
+        res[kind] = {"ms": ms, "block": list(blk) if blk else None, "status_flags": ws.status()}
         s.close()
     pairs = int(ew[2].item())
     counts = (cs[1:] - cs[:-1]).cpu().numpy()
     best = min(("buffer", "block8"), key=lambda k: res[k]["ms"])
     _line("pair interactions/sec (LJ cell-pair force sweep, inhomogeneous slab)",
           pairs / (res[best]["ms"] * 1e-3), "pairs/s", res[best]["ms"], args,
-          {"workload": "LJ slab N=2000000, rho 0.75 middle third / 0.02 gas, rc=3.0, 64^3 cells",
-           "schedule": best, "pairs_in_cutoff": pairs,
+          {"workload": "LJ slab N=2000000, rho 0.75 middle third / 0.02 gas, rc=3.0",
+           "cells": list(g.nc), "schedule": best, "block": res[best]["block"],
+           "pairs_in_cutoff": pairs,
            "cell_occupancy": {"max": int(counts.max()), "mean": float(counts.mean()),
                               "empty_frac": float((counts == 0).mean())}},
           schedules={k: dict(v, pairs_per_s=pairs / (v["ms"] * 1e-3)) for k, v in res.items()})

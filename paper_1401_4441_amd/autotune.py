@@ -150,6 +150,38 @@ def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
     return out
 
 
+def tune_shape(grid, pos: torch.Tensor, kinds=BOX_KINDS_CONFLICT_FREE, reps: int = 10) -> dict:
+    """Schedule kind and block shape on a fixed grid (e.g. one with a
+    Verlet skin).  Returns {"kind", "block", "ms", "trials"}."""
+    n = pos.shape[1]
+    ws = lc.Workspace(n, grid.ncell)
+    cs, perm, coord = lc.build_cells(grid, pos, ws)
+    s0 = lc.Schedule(grid, kinds[0])
+    t_end = time.perf_counter() + 0.3
+    while time.perf_counter() < t_end:  # clocks up before the trials count
+        time_forces(grid, s0, cs, coord, ws, reps=10, warmup=0, rounds=1)
+    s0.close()
+    trials, best = [], None
+    for kind in kinds:
+        for block in shapes_for(kind):
+            try:
+                sched = lc.Schedule(grid, kind, block=block)
+            except lc.LCError:
+                continue
+            ms = time_forces(grid, sched, cs, coord, ws, reps=reps)
+            rec = {"kind": kind, "block": list(block), "ms": ms}
+            trials.append(rec)
+            if best is None or ms < best["ms"]:
+                best = rec
+            sched.close()
+    ws.close()
+    if best is None:
+        raise lc.LCError(-1, "autotune: no valid configuration")
+    out = dict(best)
+    out["trials"] = trials
+    return out
+
+
 def tune_batch(grids, ns, pos_all: torch.Tensor, reps: int = 5) -> dict:
     """Pick the box split (auto: whole-box work-groups where they fit, or
     blocks everywhere) and persistent vs one-group-per-work-group launch for a
