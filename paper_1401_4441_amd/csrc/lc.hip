@@ -224,6 +224,12 @@ __device__ __forceinline__ bool pair_terms(uint32_t ix, uint32_t iy, uint32_t iz
     return true;
 }
 
+// LDS int64 accumulation (wraps modulo 2^64 like the sums it forms)
+__device__ __forceinline__ void lds_sub64(long long *p, long long v) {
+    __hip_atomic_fetch_sub((unsigned long long *)p, (unsigned long long)v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ long long wave_sum64(long long v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
@@ -449,14 +455,20 @@ struct SweepArgs {
 
 // Exact round-to-nearest-even of v * 2^32 to int64 for |v * 2^32| < 2^51:
 // adding 1.5 * 2^52 in FP64 rounds the (exactly scaled) value to an integer
-// that then sits in the low mantissa bits.  Lanes outside that range (or
-// NaN) set `slow` and are redone with q32f, which also flags overflow.
-__device__ __forceinline__ long long q32_fast(float v, bool &slow) {
+// that then sits in the low mantissa bits.
+__device__ __forceinline__ long long q32_magic(float v) {
     const double d = (double)v * 4294967296.0;
     const double magic = 6755399441055744.0;  // 1.5 * 2^52
-    slow |= !(fabs(d) < 2251799813685248.0);  // 2^51
     return (long long)__double_as_longlong(d + magic) - 0x4338000000000000LL;
 }
+
+// Pairs at least this far apart (r^2 >= 0.3, reduced units) have all five
+// quantised terms below 2^17 in magnitude -- at r^2 = 0.3: |f_x| <= fs r
+// = 1.19e5, w = fs r^2 = 6.5e4, |e| <= 5.4e3, and the LJ terms only shrink
+// with r -- so q32_magic applies to all of them with no per-term range test.
+// Closer pairs (not met in a liquid or a crystal) take q32f, which also
+// flags overflow.
+constexpr float kFastR2 = 0.3f;
 
 // FP32 pair terms with the fast quantisation; same values as pair_terms<false>.
 __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, const PairParams &p,
@@ -480,13 +492,13 @@ __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, 
     e = e * (s6 - 1.0f);
     e = e - p.ecut;
     const float fx = fs * dx, fy = fs * dy, fz = fs * dz, w = fs * r2;
-    bool slow = false;
-    qx = q32_fast(fx, slow);
-    qy = q32_fast(fy, slow);
-    qz = q32_fast(fz, slow);
-    qe = q32_fast(e, slow);
-    qw = q32_fast(w, slow);
-    if (slow) {
+    if (r2 >= kFastR2) {
+        qx = q32_magic(fx);
+        qy = q32_magic(fy);
+        qz = q32_magic(fz);
+        qe = q32_magic(e);
+        qw = q32_magic(w);
+    } else {
         qx = q32f(fx, ovf);
         qy = q32f(fy, ovf);
         qz = q32f(fz, ovf);
@@ -587,9 +599,9 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
         w_sum += qw;
         p_cnt += 1;
         if constexpr (STAGED && WMODE != 2) {
-            atomicSub((unsigned long long *)&sh.acc[0][il], (unsigned long long)qx);
-            atomicSub((unsigned long long *)&sh.acc[1][il], (unsigned long long)qy);
-            atomicSub((unsigned long long *)&sh.acc[2][il], (unsigned long long)qz);
+            lds_sub64(&sh.acc[0][il], qx);  // ds_sub_u64: no negation
+            lds_sub64(&sh.acc[1][il], qy);
+            lds_sub64(&sh.acc[2][il], qz);
             if constexpr (WMODE != 4) {  // full shell: j gets its force from (j, i)
                 atomicAdd((unsigned long long *)&sh.acc[0][jl], (unsigned long long)qx);
                 atomicAdd((unsigned long long *)&sh.acc[1][jl], (unsigned long long)qy);
@@ -1235,9 +1247,9 @@ __device__ __forceinline__ void df_task(const DfArgs &a, int A, int B, uint32_t 
             e_sum += qe;
             w_sum += qw;
             p_cnt += 1;
-            atomicSub((unsigned long long *)&acc[0][i], (unsigned long long)qx);
-            atomicSub((unsigned long long *)&acc[1][i], (unsigned long long)qy);
-            atomicSub((unsigned long long *)&acc[2][i], (unsigned long long)qz);
+            lds_sub64(&acc[0][i], qx);
+            lds_sub64(&acc[1][i], qy);
+            lds_sub64(&acc[2][i], qz);
             fx += qx;
             fy += qy;
             fz += qz;
