@@ -152,18 +152,20 @@ def main():
                 "wide": {"extra": 0.15, "even": True}}[args.grid]
         blk0 = [int(x) for x in args.block.split(",")] if args.block else [1, 2, 2]
         pick = {"kind": args.schedule, "block": blk0, "grid": gopt}
-        tune = {"trials": [dict(pick, nc=[0, 0, 0], ms=0.0)]}
+        tune = {"trials": [dict(pick, nc=[0, 0, 0], ms=0.0, fallback=False)]}
     else:
         tune = autotune.tune_box(pos, box.L, box.rc, reps=10, use_cache=False,
                                  kinds=("block8", "buffer", "atomic_tile", "fullshell"))
-        cf = [t for t in tune["trials"] if t["kind"] in autotune.BOX_KINDS_CONFLICT_FREE]
+        cf = [t for t in tune["trials"]
+              if t["kind"] in autotune.BOX_KINDS_CONFLICT_FREE and not t["fallback"]]
         pick = min(cf, key=lambda t: t["ms"])
     g = lc.Grid(box.L, box.rc, pick["grid"]["extra"], pick["grid"]["even"])
     ws = lc.Workspace(box.n, g.ncell)
     cs, perm, coord = lc.build_cells(g, pos, ws)
 
     def best_block(kind):
-        on_grid = [t for t in tune["trials"] if t["kind"] == kind and t["grid"] == pick["grid"]]
+        on_grid = [t for t in tune["trials"]
+                   if t["kind"] == kind and t["grid"] == pick["grid"] and not t.get("fallback")]
         return tuple(min(on_grid, key=lambda t: t["ms"])["block"]) if on_grid else None
     torch.cuda.synchronize()
     ncand = candidate_pairs(cs.cpu().numpy(), g.nc)
@@ -448,7 +450,8 @@ def bench_slab(args):
     pos = torch.from_numpy(box.pos).to(dev)
     tune = autotune.tune_box(pos, box.L, box.rc, reps=5, use_cache=False,
                              kinds=("block8", "buffer", "atomic_tile", "fullshell"))
-    cf = [t for t in tune["trials"] if t["kind"] in autotune.BOX_KINDS_CONFLICT_FREE]
+    cf = [t for t in tune["trials"]
+          if t["kind"] in autotune.BOX_KINDS_CONFLICT_FREE and not t["fallback"]]
     pick = min(cf, key=lambda t: t["ms"])
     g = lc.Grid(box.L, box.rc, pick["grid"]["extra"], pick["grid"]["even"])
     ws = lc.Workspace(box.n, g.ncell)
@@ -457,7 +460,8 @@ def bench_slab(args):
     ew = torch.empty(3, dtype=torch.int64, device=dev)
     res = {}
     for kind in ("buffer", "block8", "atomic_tile", "fullshell", "atomic_pair"):
-        on_grid = [t for t in tune["trials"] if t["kind"] == kind and t["grid"] == pick["grid"]]
+        on_grid = [t for t in tune["trials"]
+                   if t["kind"] == kind and t["grid"] == pick["grid"] and not t.get("fallback")]
         blk = tuple(min(on_grid, key=lambda t: t["ms"])["block"]) if on_grid else None
         s = lc.Schedule(g, kind, block=blk)
         ws.clear_status()

@@ -116,7 +116,10 @@ void lc_workspace_destroy(lc_workspace *ws);
 /* LDS tile sizing hint: the largest number of particles in one cell (0 =
  * estimate from the mean density).  A work-group stages its footprint cells
  * in LDS when they fit the tile and otherwise runs the (exact but slower)
- * global-memory path, flagged with LC_FLAG_FALLBACK. */
+ * global-memory path, flagged with LC_FLAG_FALLBACK.  The hint also picks the
+ * kernel: the 16-bit candidate filter stages cells of up to 60 particles, so
+ * a larger hint (or, without one, a mean above 30) selects the unfiltered
+ * sweep. */
 int lc_workspace_set_tile_hint(lc_workspace *ws, int32_t max_per_cell);
 
 /* Clear the device status flags (async on stream).  It also re-zeroes the

@@ -104,7 +104,7 @@ def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
     if kinds is None:
         kinds = BOX_KINDS_CONFLICT_FREE + (("atomic_tile",) if allow_atomics else ())
     kinds = tuple(kinds)
-    key = box_key(n, L, rc) + "|" + ",".join(kinds) + "|v3"
+    key = box_key(n, L, rc) + "|" + ",".join(kinds) + "|v4"
     cache = _load_cache() if use_cache else {}
     if key in cache:
         return cache[key]
@@ -131,12 +131,16 @@ def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
                     sched = lc.Schedule(grid, kind, block=block)
                 except lc.LCError:
                     continue
+                ws.clear_status()
                 ms = time_forces(grid, sched, cs, coord, ws, reps=reps)
+                # a footprint beyond the LDS tile runs the (exact) global
+                # fallback: that times the safety net, not the tiled sweep
+                fell_back = bool(ws.status() & lc.FLAG_FALLBACK)
                 ws.clear_status()
                 rec = {"grid": dict(gopt), "kind": kind, "block": list(block), "ms": ms,
-                       "nc": list(grid.nc)}
+                       "nc": list(grid.nc), "fallback": fell_back}
                 trials.append(rec)
-                if best is None or ms < best["ms"]:
+                if not fell_back and (best is None or ms < best["ms"]):
                     best = rec
                 sched.close()
         ws.close()
@@ -168,10 +172,13 @@ def tune_shape(grid, pos: torch.Tensor, kinds=BOX_KINDS_CONFLICT_FREE, reps: int
                 sched = lc.Schedule(grid, kind, block=block)
             except lc.LCError:
                 continue
+            ws.clear_status()
             ms = time_forces(grid, sched, cs, coord, ws, reps=reps)
-            rec = {"kind": kind, "block": list(block), "ms": ms}
+            fell_back = bool(ws.status() & lc.FLAG_FALLBACK)
+            ws.clear_status()
+            rec = {"kind": kind, "block": list(block), "ms": ms, "fallback": fell_back}
             trials.append(rec)
-            if best is None or ms < best["ms"]:
+            if not fell_back and (best is None or ms < best["ms"]):
                 best = rec
             sched.close()
     ws.close()

@@ -1497,7 +1497,10 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     a.pp = pair_params(g);
     // LDS tile: expected particles of the largest footprint with headroom
     const double mean = g->ncell > 0 ? (double)n / (double)g->ncell : 0.0;
-    const bool ff = a.pp.thr16 > 0 && precision == LC_PREC_FP32 && s->h.write_mode != 2;
+    // the filter stages cells of up to kFFCell particles; denser cells take
+    // the unfiltered kernel rather than the global fallback
+    const bool dense = ws->max_per_cell > 0 ? ws->max_per_cell > kFFCell : mean > 0.5 * kFFCell;
+    const bool ff = a.pp.thr16 > 0 && precision == LC_PREC_FP32 && s->h.write_mode != 2 && !dense;
     const double need = ws->max_per_cell > 0 ? (double)ws->max_per_cell * s->h.max_cells * 0.8
                                              : mean * s->h.max_cells * 1.35;
     int cap;
@@ -2408,7 +2411,7 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
         }
         pp.rc2 = g.rc2;
         pp.thr16 = filter16_bound(g.box, g.rc2);
-        if (pp.thr16 == 0) filt = false;
+        if (pp.thr16 == 0 || dens > 0.5 * kFFCell) filt = false;
         pp.ecut = g.ecut;
         pp.rc2d = g.rc * g.rc;
         const double ic = 1.0 / pp.rc2d, s6 = ic * ic * ic;

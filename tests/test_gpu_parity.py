@@ -164,6 +164,24 @@ def test_lds_overflow_falls_back_exactly():
         assert (F == Fo).all() and ew == [Eo, Wo, npo], kind
 
 
+def test_dense_cells_take_the_tiled_path():
+    """A skin grid of 4^3 cells holding 62.5 particles each on average (73
+    at most): beyond what the 16-bit filter stages, so the unfiltered tiled
+    kernel runs (27-cell footprints of at most 1971 particles fit its
+    2048-particle tile) and no work-group falls back to global memory."""
+    box = synth.fcc(4000, 0.8, rc=2.5, seed=1001)
+    S = Setup(box, skin=0.6, even=True)
+    assert S.g.nc == (4, 4, 4)
+    Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
+    for kind in ("block8", "buffer", "atomic_tile", "fullshell"):
+        _say("dense", kind)
+        F, ew, st = S.forces(kind)
+        if kind != "fullshell":  # 48-cell footprints may exceed the tile
+            assert st == 0, (kind, st)
+        assert st & lc.FLAG_OVERFLOW == 0
+        assert (F == Fo).all() and ew == [Eo, Wo, npo], kind
+
+
 @pytest.mark.parametrize("kind", ["buffer", "atomic_tile", "fullshell"])
 def test_block_shapes_bit_exact(kind):
     """Uncoloured kinds over block shapes from single cells to blocks
