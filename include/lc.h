@@ -317,6 +317,16 @@ int lc_compute_forces_profiled(const lc_grid *g, const lc_schedule *s,
                                lc_workspace *ws, void *stream, double *sweep_ms,
                                double *phase_ms);
 
+/* Self-check of the sweep's fast reciprocal (the FP32 pair arithmetic takes
+ * 1/r^2 as the IEEE quotient; pairs with 0.3 <= r^2 < 128 get it from the
+ * hardware estimate plus one Newton-Raphson step).  Compares that device
+ * routine with IEEE division on every float whose bit pattern lies in
+ * [lo_bits, hi_bits) and writes the number of differing results to
+ * *mismatches (host).  Synchronous; allocates 8 bytes of device memory for
+ * the count.  The range the sweep relies on is [0x3e800000, 0x43000000),
+ * i.e. [0.25, 128). */
+int lc_selftest_recip(uint32_t lo_bits, uint32_t hi_bits, uint64_t *mismatches);
+
 /* ---- Sec. VI strategy 2 and the mutual exclusion of Sec. VII: dataflow
  * execution of a creation order on the device -------------------------- */
 #define LC_DF_ORDERED 0 /* the StarSs inout dependences of the creation order:

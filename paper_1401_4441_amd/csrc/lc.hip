@@ -453,24 +453,59 @@ struct SweepArgs {
     int ngroups;
 };
 
-// Exact round-to-nearest-even of v * 2^32 to int64 for |v * 2^32| < 2^51:
-// adding 1.5 * 2^52 in FP64 rounds the (exactly scaled) value to an integer
-// that then sits in the low mantissa bits.
+// Exact round-to-nearest-even of v * 2^32 to int64 for |v| < 2^19: the FP64
+// sum (double)v + 1.5 * 2^20 lies in [2^20, 2^21), where the FP64 spacing is
+// 2^-32, so its one rounding takes v to the nearest multiple of 2^-32 (ties
+// to even), and that multiple's count sits in the low mantissa bits:
+// bits = bits(1.5 * 2^20) + round(v * 2^32).
 __device__ __forceinline__ long long q32_magic(float v) {
-    const double d = (double)v * 4294967296.0;
-    const double magic = 6755399441055744.0;  // 1.5 * 2^52
-    return (long long)__double_as_longlong(d + magic) - 0x4338000000000000LL;
+    const double d = (double)v + 1572864.0;  // 1.5 * 2^20
+    return (long long)__double_as_longlong(d) - 0x4138000000000000LL;
+}
+
+// IEEE (correctly rounded) 1/x for x in [kRcpLo, kRcpHi): the hardware
+// estimate, within one ulp, refined by one Newton-Raphson step in fused
+// multiply-adds (Markstein's reciprocal iteration).  Equality with IEEE
+// division is checked for every float of the range (lc_selftest_recip).
+constexpr float kRcpLo = 0.25f, kRcpHi = 128.0f;
+__device__ __forceinline__ float rcp_nr(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    const float e = __builtin_fmaf(-x, r, 1.0f);
+    return __builtin_fmaf(e, r, r);
 }
 
 // Pairs at least this far apart (r^2 >= 0.3, reduced units) have all five
 // quantised terms below 2^17 in magnitude -- at r^2 = 0.3: |f_x| <= fs r
 // = 1.19e5, w = fs r^2 = 6.5e4, |e| <= 5.4e3, and the LJ terms only shrink
 // with r -- so q32_magic applies to all of them with no per-term range test.
-// Closer pairs (not met in a liquid or a crystal) take q32f, which also
-// flags overflow.
+// Closer pairs (not met in a liquid or a crystal) and pairs beyond the
+// reciprocal's checked range take IEEE division and q32f, which also flags
+// overflow.
 constexpr float kFastR2 = 0.3f;
+static_assert(kFastR2 >= kRcpLo, "fast pairs lie in the checked reciprocal range");
 
-// FP32 pair terms with the fast quantisation; same values as pair_terms<false>.
+// Lennard-Jones terms of one pair from inv = 1/r^2, in the canonical order.
+__device__ __forceinline__ void lj_terms(float inv, float dx, float dy, float dz, float r2,
+                                         float ecut, float &fx, float &fy, float &fz, float &e,
+                                         float &w) {
+    float s6 = inv * inv;
+    s6 = s6 * inv;
+    float t = 24.0f * inv;
+    t = t * s6;
+    float g = 2.0f * s6;
+    g = g - 1.0f;
+    const float fs = t * g;
+    e = 4.0f * s6;
+    e = e * (s6 - 1.0f);
+    e = e - ecut;
+    fx = fs * dx;
+    fy = fs * dy;
+    fz = fs * dz;
+    w = fs * r2;
+}
+
+// FP32 pair terms with the fast reciprocal and quantisation; same values as
+// pair_terms<false>.
 __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, const PairParams &p,
                                                 long long &qx, long long &qy, long long &qz,
                                                 long long &qe, long long &qw, uint32_t &ovf) {
@@ -480,25 +515,16 @@ __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, 
     float r2 = dx * dx + dy * dy;
     r2 = r2 + dz * dz;
     if (!(r2 < p.rc2)) return false;
-    float inv = 1.0f / r2;
-    float s6 = inv * inv;
-    s6 = s6 * inv;
-    float t = 24.0f * inv;
-    t = t * s6;
-    float g = 2.0f * s6;
-    g = g - 1.0f;
-    const float fs = t * g;
-    float e = 4.0f * s6;
-    e = e * (s6 - 1.0f);
-    e = e - p.ecut;
-    const float fx = fs * dx, fy = fs * dy, fz = fs * dz, w = fs * r2;
-    if (r2 >= kFastR2) {
+    float fx, fy, fz, e, w;
+    if (r2 >= kFastR2 && r2 < kRcpHi) {
+        lj_terms(rcp_nr(r2), dx, dy, dz, r2, p.ecut, fx, fy, fz, e, w);
         qx = q32_magic(fx);
         qy = q32_magic(fy);
         qz = q32_magic(fz);
         qe = q32_magic(e);
         qw = q32_magic(w);
     } else {
+        lj_terms(1.0f / r2, dx, dy, dz, r2, p.ecut, fx, fy, fz, e, w);
         qx = q32f(fx, ovf);
         qy = q32f(fy, ovf);
         qz = q32f(fz, ovf);
@@ -514,7 +540,7 @@ template <int CAP, int WMODE, bool FF>
 struct SweepLDS {
     uint4 u[CAP];                                           // box fractions
     // filter coordinates: the top 16 bits of the box fractions, x | y << 16
-    // and z; the filter reads rows aoff .. aoff + kmax + 3 for every lane
+    // and z; the filter reads rows aoff .. aoff + kmax - 1 for every lane
     // (kmax: the wave's largest cell A), so it runs past the footprint by
     // less than kFPad when no cell holds more than kFFCell
     uint2 h[FF ? CAP + kFPad : 1];
@@ -693,27 +719,28 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             // shell, every i but j itself
             const int lim = (intra && WMODE != 4) ? min(jj, na) : na;
             const uint32_t rot = (uint32_t)jj & 31u;
+            // one candidate row: 16-bit differences wrap modulo the box (the
+            // minimum image up to one unit per axis); r2 - bound is negative
+            // (sign bit set) inside, and the sign bit is shifted into m
+            auto row = [&](const uint2 hi, uint32_t m) -> uint32_t {
+                const short2v dxy =
+                    __builtin_bit_cast(short2v, hj.x) - __builtin_bit_cast(short2v, hi.x);
+                const short2v dz0 =
+                    __builtin_bit_cast(short2v, hj.y) - __builtin_bit_cast(short2v, hi.y);
+                int t = __builtin_amdgcn_sdot2(dz0, dz0, -pp.thr16, false);
+                t = __builtin_amdgcn_sdot2(dxy, dxy, t, false);
+                return __builtin_amdgcn_alignbit(m, (uint32_t)t, 31);
+            };
             for (int k0 = 0; k0 < kmax; k0 += 32) {
-                const int kr = min(kmax - k0 + 3, 32) & ~3;  // rows read, uniform
+                const int kr = min(kmax - k0, 32);  // rows read, uniform
                 const uint2 *ha = &sh.h[a0 + k0];
                 uint32_t m = 0u;
-                for (int k = 0; k < kr; k += 4) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const uint2 hi = ha[k + u];
-                        // 16-bit differences wrap modulo the box: the
-                        // minimum image up to one unit per axis
-                        const short2v dxy = __builtin_bit_cast(short2v, hj.x) -
-                                            __builtin_bit_cast(short2v, hi.x);
-                        const short2v dz0 = __builtin_bit_cast(short2v, hj.y) -
-                                            __builtin_bit_cast(short2v, hi.y);
-                        // r2 - bound: negative (sign bit set) inside; the sign
-                        // bit is shifted into m
-                        int t = __builtin_amdgcn_sdot2(dz0, dz0, -pp.thr16, false);
-                        t = __builtin_amdgcn_sdot2(dxy, dxy, t, false);
-                        m = __builtin_amdgcn_alignbit(m, (uint32_t)t, 31);
-                    }
+                int k = 0;
+                for (; k + 2 <= kr; k += 2) {  // two rows per LDS read
+                    m = row(ha[k], m);
+                    m = row(ha[k + 1], m);
                 }
+                if (k < kr) m = row(ha[k], m);
                 // row k sits at bit kr - 1 - k; keep rows k < lim - k0
                 const int nv = lim - k0;
                 m = nv <= 0 ? 0u : nv >= kr ? m : m & ~((1u << (kr - nv)) - 1u);
@@ -729,9 +756,11 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
                     const bool has = m != 0u;
                     const unsigned long long bal = __ballot(has);
                     if (!bal) break;
-                    const uint32_t e =
-                        ebase - (((uint32_t)__builtin_ctz(m | 0x80000000u) + rot) & 31u);
-                    m &= m - 1u;
+                    uint32_t e = 0u;
+                    if (has) {
+                        e = ebase - (((uint32_t)__builtin_ctz(m) + rot) & 31u);
+                        m &= m - 1u;
+                    }
                     push_ent(bal, has, e);
                 }
             }
@@ -1999,6 +2028,36 @@ extern "C" int lc_compute_forces(const lc_grid *g, const lc_schedule *s, const i
     int rc = check_ws(ws, 0, 0);
     if (rc) return rc;
     return forces_impl(g, s, cell_start, coord, n, F, ew, precision, ws, (hipStream_t)stream);
+}
+
+__global__ __launch_bounds__(256) void k_selftest_recip(uint32_t lo, uint32_t n,
+                                                        unsigned long long *bad) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long cnt = 0;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const float x = __uint_as_float(lo + (uint32_t)k);
+        cnt += __float_as_uint(rcp_nr(x)) != __float_as_uint(1.0f / x) ? 1u : 0u;
+    }
+    if (cnt) atomicAdd(bad, cnt);
+}
+
+extern "C" int lc_selftest_recip(uint32_t lo_bits, uint32_t hi_bits, uint64_t *mismatches) {
+    if (!mismatches || hi_bits <= lo_bits) return fail(LC_EINVAL, "lc_selftest_recip: range");
+    unsigned long long *d = nullptr;
+    int rc = dalloc(&d, 1);
+    if (rc) return rc;
+    unsigned long long h = 0;
+    hipError_t e = hipMemcpy(d, &h, sizeof(h), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        const uint32_t n = hi_bits - lo_bits;
+        hipLaunchKernelGGL(k_selftest_recip, dim3(4096), dim3(256), 0, 0, lo_bits, n, d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(&h, d, sizeof(h), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(LC_EHIP, "lc_selftest_recip: %s", hipGetErrorString(e));
+    *mismatches = (uint64_t)h;
+    return LC_OK;
 }
 
 template <int MODE>

@@ -93,6 +93,7 @@ SYMBOLS = {
     "lc_verlet_step": ([P, P, P, P, P, I64, P, P, P, P, ctypes.c_double, INT,
                         INT, P, P, P], INT),
     "lc_kinetic_energy": ([P, I64, P, P, P], INT),
+    "lc_selftest_recip": ([ctypes.c_uint32, ctypes.c_uint32, P], INT),
     "lc_batch_create": ([P, INT, P, P], INT),
     "lc_batch_info_get": ([P, P], INT),
     "lc_batch_offsets": ([P, P, P], INT),
@@ -404,6 +405,18 @@ def kinetic_energy(vel: torch.Tensor, ws: Workspace, out=None, stream=None):
         out = torch.empty(1, dtype=torch.int64, device=vel.device)
     _chk(lib().lc_kinetic_energy(_p(vel), n, _p(out), ws.ptr, _stream(stream)))
     return out
+
+
+RECIP_RANGE = (0x3E800000, 0x43000000)  # bit patterns of 0.25 and 128.0
+
+
+def selftest_recip(lo_bits: int = RECIP_RANGE[0], hi_bits: int = RECIP_RANGE[1]) -> int:
+    """Number of floats with bit patterns in [lo_bits, hi_bits) whose fast
+    device reciprocal differs from IEEE division (0 over RECIP_RANGE, the
+    range the FP32 sweep relies on)."""
+    out = ctypes.c_uint64()
+    _chk(lib().lc_selftest_recip(int(lo_bits), int(hi_bits), ctypes.byref(out)))
+    return int(out.value)
 
 
 def serialization_degree_weighted(dims, kind, cell_counts, offsets=None) -> dict:

@@ -196,6 +196,16 @@ def test_block_shapes_bit_exact(kind):
         assert (F == Fo).all() and ew == [Eo, Wo, npo], (kind, block)
 
 
+def test_fast_reciprocal_is_ieee_on_its_range():
+    """The FP32 sweep takes 1/r^2 for 0.3 <= r^2 < 128 from the hardware
+    estimate plus one Newton-Raphson step; it must equal IEEE division for
+    every float of [0.25, 128) (75.5M values, checked exhaustively)."""
+    lo, hi = lc.RECIP_RANGE
+    assert np.float32(np.uint32(lo).view(np.float32)) == 0.25
+    assert np.float32(np.uint32(hi).view(np.float32)) == 128.0
+    assert lc.selftest_recip(lo, hi) == 0
+
+
 def test_overflow_flag():
     """Two particles 0.05 apart: the force exceeds the fixed-point range;
     the oracle refuses too."""
