@@ -112,6 +112,7 @@ constexpr int kWB0 = lcs::kMaxGroupCells;  // first thread of the write-back wav
 constexpr int kFPad = 64;           // filter rows past the footprint (see SweepLDS)
 constexpr int kFFCell = kFPad - 4;  // largest cell the filter path stages
 constexpr int kMaxT = lcs::kMaxGroupTasks;
+constexpr int kMaxChunks = 64;      // chunk tables cover groups of up to 4096 slots
 constexpr int kMaxF = lcs::kMaxGroupCells;
 
 static_assert(kMaxT <= kWG && kMaxF <= kWG, "tables scanned one item per thread");
@@ -240,21 +241,21 @@ __device__ __forceinline__ int wave_max32(int v) {
     return v;
 }
 
-// Exclusive scan of one int per thread over a work-group of NT threads.
-template <int NT>
-__device__ int block_scan_excl(int v, int *s_w, int &total) {
+// Exclusive scan of one value per thread over a work-group of NT threads.
+template <int NT, typename T>
+__device__ T block_scan_excl(T v, T *s_w, T &total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int x = v;
+    T x = v;
     for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o);
+        T y = __shfl_up(x, o);
         if (lane >= o) x += y;
     }
     if (lane == 63) s_w[w] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
-        int acc = 0;
+        T acc = 0;
         for (int k = 0; k < NT / 64; ++k) {
-            int t = s_w[k];
+            T t = s_w[k];
             s_w[k] = acc;
             acc += t;
         }
@@ -262,7 +263,7 @@ __device__ int block_scan_excl(int v, int *s_w, int &total) {
     }
     __syncthreads();
     total = s_w[NT / 64];
-    int r = x - v + s_w[w];
+    T r = x - v + s_w[w];
     __syncthreads();
     return r;
 }
@@ -552,6 +553,13 @@ struct SweepLDS {
     int ta[kMaxT];          // task: local first slot of A | (count of A << 16)
     int tb[kMaxT];          // task: local first slot of B, bit 31 = intra
     int tslot[kMaxT + 1];   // prefix of |B| over the tasks
+    // per 64-slot chunk (nslot <= 64 * kMaxChunks): the task of its first
+    // slot, a mask of the slots where a later task starts, and the largest
+    // cell A among its tasks
+    int ct0[kMaxChunks];
+    unsigned long long cmask[kMaxChunks];
+    int ckmax[kMaxChunks];
+    long long w64[kNW + 1];
     uint32_t q[kNW][kQ];    // per-wave queue of in-cutoff pairs (i | j << 16)
     long long red[kNW][3];
     int w[kNW + 1];
@@ -681,19 +689,32 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
         push_ent(__ballot(in), in, (uint32_t)il | jbits);
     };
 
-    for (int base = wave * 64; base < nslot; base += kNW * 64) {
+    const bool tables = nslot <= 64 * kMaxChunks;
+    for (int c = wave; c * 64 < nslot; c += kNW) {
+        const int base = c * 64;
         const int s = base + lane;
         const bool valid = s < nslot;
-        // task of the chunk's first slot (one wave-uniform search), then each
-        // lane steps forward to its own task (a chunk spans a few tasks)
-        int lo = 0, hi = nt;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (sh.tslot[mid] <= base) lo = mid; else hi = mid;
+        int t, kmax_c = 0;
+        if (tables) {
+            // the chunk's first task plus the task starts at or below this
+            // lane's slot (no task starts past nslot)
+            const unsigned long long m = sh.cmask[c] >> 1;
+            t = __builtin_amdgcn_readfirstlane(sh.ct0[c]) +
+                (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            kmax_c = __builtin_amdgcn_readfirstlane(sh.ckmax[c]);
+        } else {
+            // task of the chunk's first slot (one wave-uniform search), then
+            // each lane steps forward to its own task
+            int lo = 0, hi = nt;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (sh.tslot[mid] <= base) lo = mid; else hi = mid;
+            }
+            t = __builtin_amdgcn_readfirstlane(lo);
+            const int slast = min(s, nslot - 1);
+            while (sh.tslot[t + 1] <= slast) ++t;
         }
-        int t = __builtin_amdgcn_readfirstlane(lo);
-        const int slast = min(s, nslot - 1);
-        while (sh.tslot[t + 1] <= slast) ++t;
         const int jj = s - sh.tslot[t];
         const int bo = sh.tb[t];
         const bool intra = bo < 0;
@@ -713,7 +734,7 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             // a batch's i-side adds spread over addresses.
             const int na = valid ? (ta >> 16) : 0;
             const int a0 = valid ? aoff : 0;
-            const int kmax = __builtin_amdgcn_readfirstlane(wave_max32(na));
+            const int kmax = tables ? kmax_c : __builtin_amdgcn_readfirstlane(wave_max32(na));
             const uint2 hj = valid ? sh.h[jl] : make_uint2(0u, 0u);
             // intra: i before j (each unordered pair once), or, in the full
             // shell, every i but j itself
@@ -770,7 +791,7 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             // atomics); an intra task keeps a pair when i < j
             const uint4 uj = valid ? load_u(jl) : make_uint4(0u, 0u, 0u, 0u);
             const int na = valid ? (ta >> 16) : 0;
-            const int kdiag = wave_max32(na);
+            const int kdiag = tables ? kmax_c : wave_max32(na);
             int ik = na > 0 ? jj % na : 0;
             for (int k = 0; k < kdiag; ++k) {
                 const bool act = k < na && (!intra || (WMODE == 4 ? ik != jj : ik < jj));
@@ -935,18 +956,39 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
             __syncthreads();
         }
     }
-    // task table
-    int nb = 0;
+    // task table: a task with an empty cell has no pairs and is dropped; the
+    // others are numbered densely in the order given, so that consecutive
+    // tasks own consecutive j slots
+    int na_t = 0, nb_t = 0, ta_v = 0, tb_v = 0;
     if (tid < nt) {
         const int la = (int)(my_ab & 0xffffu), lb = (int)(my_ab >> 16);
-        sh.ta[tid] = sh.fl[la] | ((sh.fl[la + 1] - sh.fl[la]) << 16);
-        sh.tb[tid] = sh.fl[lb] | (la == lb ? (int)0x80000000 : 0);
-        nb = sh.fl[lb + 1] - sh.fl[lb];
+        na_t = sh.fl[la + 1] - sh.fl[la];
+        nb_t = sh.fl[lb + 1] - sh.fl[lb];
+        ta_v = sh.fl[la] | (na_t << 16);
+        tb_v = sh.fl[lb] | (la == lb ? (int)0x80000000 : 0);
     }
-    int nslot;
-    const int so = block_scan_excl<kWG>(nb, sh.w, nslot);
-    if (tid < nt) sh.tslot[tid] = so;
-    if (tid == 0) sh.tslot[nt] = nslot;
+    const bool live = na_t > 0 && nb_t > 0;
+    if (tid < kMaxChunks) {  // ordered before the atomics by the scan's barriers
+        sh.cmask[tid] = 0ull;
+        sh.ckmax[tid] = 0;
+    }
+    long long tot64;
+    const long long pre = block_scan_excl<kWG>(live ? (1LL << 32) | nb_t : 0LL, sh.w64, tot64);
+    const int ntl = (int)(tot64 >> 32), nslot = (int)(uint32_t)tot64;
+    if (live) {
+        const int ct = (int)(pre >> 32), so = (int)(uint32_t)pre;
+        sh.ta[ct] = ta_v;
+        sh.tb[ct] = tb_v;
+        sh.tslot[ct] = so;
+        if (nslot <= 64 * kMaxChunks) {
+            if (so & 63) atomicOr(&sh.cmask[so >> 6], 1ull << (so & 63));
+            for (int c = so >> 6; c <= (so + nb_t - 1) >> 6; ++c) {
+                if (c << 6 >= so) sh.ct0[c] = ct;  // the task holding the chunk's first slot
+                atomicMax(&sh.ckmax[c], na_t);
+            }
+        }
+    }
+    if (tid == 0) sh.tslot[ntl] = nslot;
     if (staged) {
 #pragma unroll
         for (int r = 0; r < NK; ++r) {
@@ -974,10 +1016,10 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
     long long e_sum = 0, w_sum = 0, p_cnt = 0;
     uint32_t ovf = 0;
     if (staged)
-        sweep_pairs<CAP, WMODE, F64, true, FF>(sh, a, pp, f0, nf, nt, nslot, e_sum, w_sum, p_cnt,
+        sweep_pairs<CAP, WMODE, F64, true, FF>(sh, a, pp, f0, nf, ntl, nslot, e_sum, w_sum, p_cnt,
                                                ovf);
     else
-        sweep_pairs<CAP, WMODE, F64, false, FF>(sh, a, pp, f0, nf, nt, nslot, e_sum, w_sum, p_cnt,
+        sweep_pairs<CAP, WMODE, F64, false, FF>(sh, a, pp, f0, nf, ntl, nslot, e_sum, w_sum, p_cnt,
                                                 ovf);
     if constexpr (PF) {  // next group: particle ranges of its footprint cells
         pre_cells(a, nx);
