@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -231,25 +232,67 @@ __device__ __forceinline__ void lds_sub64(long long *p, long long v) {
                            __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Cross-lane steps of a wave-wide inclusive scan, all in DPP (no LDS round
+// trips): row_shr 1, 2, 4, 8 scan each row of 16 lanes, then row_bcast 15
+// (into rows 1 and 3) and row_bcast 31 (into rows 2 and 3) carry the row
+// totals across.  A lane with no source reads `id`.  Every lane of the wave
+// must be active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_from(int id, int x) {
+    return __builtin_amdgcn_update_dpp(id, x, CTRL, ROWS, 0xf, false);
+}
+
+__device__ __forceinline__ int wave_scan_incl(int x) {
+    x += dpp_from<0x111, 0xf>(0, x);
+    x += dpp_from<0x112, 0xf>(0, x);
+    x += dpp_from<0x114, 0xf>(0, x);
+    x += dpp_from<0x118, 0xf>(0, x);
+    x += dpp_from<0x142, 0xa>(0, x);
+    x += dpp_from<0x143, 0xc>(0, x);
+    return x;
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ long long dpp_from64(long long x) {
+    const uint32_t lo = (uint32_t)dpp_from<CTRL, ROWS>(0, (int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)dpp_from<CTRL, ROWS>(0, (int)(uint32_t)((uint64_t)x >> 32));
+    return (long long)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ long long wave_scan_incl(long long x) {
+    x += dpp_from64<0x111, 0xf>(x);
+    x += dpp_from64<0x112, 0xf>(x);
+    x += dpp_from64<0x114, 0xf>(x);
+    x += dpp_from64<0x118, 0xf>(x);
+    x += dpp_from64<0x142, 0xa>(x);
+    x += dpp_from64<0x143, 0xc>(x);
+    return x;
+}
+
+// Wave-wide sum (wraps modulo 2^64), the same value in every lane.
 __device__ __forceinline__ long long wave_sum64(long long v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    const long long x = wave_scan_incl(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), 63);
+    return (long long)(((uint64_t)hi << 32) | lo);
 }
 
 __device__ __forceinline__ int wave_max32(int v) {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
+    const int lo = INT_MIN;
+    v = max(v, dpp_from<0x111, 0xf>(lo, v));
+    v = max(v, dpp_from<0x112, 0xf>(lo, v));
+    v = max(v, dpp_from<0x114, 0xf>(lo, v));
+    v = max(v, dpp_from<0x118, 0xf>(lo, v));
+    v = max(v, dpp_from<0x142, 0xa>(lo, v));
+    v = max(v, dpp_from<0x143, 0xc>(lo, v));
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Exclusive scan of one value per thread over a work-group of NT threads.
 template <int NT, typename T>
 __device__ T block_scan_excl(T v, T *s_w, T &total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    T x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        T y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
+    const T x = wave_scan_incl(v);
     if (lane == 63) s_w[w] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
