@@ -483,8 +483,11 @@ struct SweepArgs {
     const uint32_t *coord;
     int64_t n;
     long long *F;
-    const int *foot_rep;  // replica slot per footprint entry (WMODE 3)
+    // WMODE 3: replica slot of each footprint entry | (the cell's replica
+    // count << 16); WMODE 4: home flag
+    const int *foot_rep;
     long long *pbuf;      // replica partial sums (WMODE 3), 3 x n per slot
+    int *rcnt;            // replica count per particle, written by replica 0 (WMODE 3)
     long long *part;  // kPartSlots x 3 partial {energy, virial, pairs}
     uint32_t *flags;
     PairParams pp;
@@ -690,8 +693,8 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             int64_t gi = foot_gidx(sh, nf, il), gj = foot_gidx(sh, nf, jl);
             unsigned long long *Fi = (unsigned long long *)a.F, *Fj = Fi;
             if constexpr (WMODE == 3) {
-                const int ri = sh.frep[foot_cell(sh, nf, il)];
-                const int rj = sh.frep[foot_cell(sh, nf, jl)];
+                const int ri = sh.frep[foot_cell(sh, nf, il)] & 0xffff;
+                const int rj = sh.frep[foot_cell(sh, nf, jl)] & 0xffff;
                 Fi = (unsigned long long *)a.pbuf + (int64_t)ri * 3 * n;
                 Fj = (unsigned long long *)a.pbuf + (int64_t)rj * 3 * n;
             }
@@ -977,10 +980,12 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
             for (int k = tid; k < total; k += kWG) {
                 const int f = foot_cell(sh, nf, k);
                 const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
-                long long *P = a.pbuf + (int64_t)sh.frep[f] * 3 * n;
+                const int fr = sh.frep[f];
+                long long *P = a.pbuf + (int64_t)(fr & 0xffff) * 3 * n;
                 P[gi] = 0;
                 P[n + gi] = 0;
                 P[2 * n + gi] = 0;
+                if ((fr & 0xffff) == 0) a.rcnt[gi] = fr >> 16;
             }
             __syncthreads();
         }
@@ -1102,10 +1107,13 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
         for (int k = wt < 0 ? total : wt; k < total; k += kWG - wb0) {
             const int f = sh.pc[k];
             const int64_t gi = (int64_t)sh.fg[f] + (k - sh.fl[f]);
-            long long *P = a.pbuf + (int64_t)sh.frep[f] * 3 * n;
+            const int fr = sh.frep[f];
+            long long *P = a.pbuf + (int64_t)(fr & 0xffff) * 3 * n;
             P[gi] = sh.acc[0][k];
             P[n + gi] = sh.acc[1][k];
             P[2 * n + gi] = sh.acc[2][k];
+            // the cell's first replica also records how many there are
+            if ((fr & 0xffff) == 0) a.rcnt[gi] = fr >> 16;
         }
     } else if constexpr (WMODE == 4) {
         if (!staged) return;
@@ -1232,21 +1240,15 @@ __global__ __launch_bounds__(256) void k_reduce_parts(long long *__restrict__ pa
 // With part != NULL one extra work-group (the last) sums the energy slots
 // instead, which saves a launch.
 __global__ __launch_bounds__(256) void k_gather_partials(
-    const long long *__restrict__ pbuf, const int *__restrict__ cell_rep,
-    const int *__restrict__ cell_start, int ncell, int64_t n, long long *__restrict__ F,
-    long long *__restrict__ part, long long *__restrict__ ew) {
+    const long long *__restrict__ pbuf, const int *__restrict__ rcnt, int64_t n,
+    long long *__restrict__ F, long long *__restrict__ part, long long *__restrict__ ew) {
     if (part && blockIdx.x == gridDim.x - 1) {
         reduce_parts_wg(part, 3, ew);
         return;
     }
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    int lo = 0, hi = ncell;  // cell_start[lo] <= p < cell_start[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (cell_start[mid] <= p) lo = mid; else hi = mid;
-    }
-    const int R = cell_rep[lo];
+    const int R = rcnt[p];  // replicas of p's cell, recorded by the sweep
     long long fx = 0, fy = 0, fz = 0;
     for (int r = 0; r < R; ++r) {
         const long long *P = pbuf + (int64_t)r * 3 * n;
@@ -1570,6 +1572,23 @@ static PairParams pair_params(const lc_grid *g) {
     return p;
 }
 
+// Footprint entries as the sweep reads them: with buffer + reduce, the
+// replica slot | (the cell's replica count << 16); otherwise as built.
+static std::vector<int32_t> device_foot_rep(const lcs::HostSchedule &h) {
+    std::vector<int32_t> out(h.foot_rep);
+    if (h.write_mode == 3)
+        for (size_t f = 0; f < out.size(); ++f)
+            out[f] |= h.cell_rep[(size_t)h.foot_cells[f]] << 16;
+    return out;
+}
+
+// Buffer + reduce scratch: rmax replica slots of 3 x n int64, then n int32
+// replica counts.
+static int64_t pbuf_elems(int rmax, int64_t n) { return (int64_t)rmax * 3 * n + (n + 1) / 2; }
+static int *rcnt_of(lc_workspace *ws, int rmax, int64_t n) {
+    return (int *)(ws->pbuf + (int64_t)rmax * 3 * n);
+}
+
 static int ensure_pbuf(lc_workspace *ws, int64_t need) {
     if (need <= ws->pbuf_elems) return LC_OK;
     (void)hipFree(ws->pbuf);
@@ -1588,7 +1607,7 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     const bool fullshell = s->h.write_mode == 4;  // writes every particle itself
     int rc = (buffered || fullshell) ? LC_OK : fill64((long long *)F, 3 * n, st);
     if (rc) return rc;
-    if (buffered && (rc = ensure_pbuf(ws, (int64_t)s->h.rmax * 3 * n))) return rc;
+    if (buffered && (rc = ensure_pbuf(ws, pbuf_elems(s->h.rmax, n)))) return rc;
     const int nphase = (int)s->h.phase_grp.size() - 1;
     SweepArgs a;
     a.grp_task = s->grp_task;
@@ -1601,6 +1620,7 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     a.F = (long long *)F;
     a.foot_rep = s->foot_rep;
     a.pbuf = ws->pbuf;
+    a.rcnt = buffered ? rcnt_of(ws, s->h.rmax, n) : nullptr;
     a.part = (long long *)ws->part;
     a.grp_box = nullptr;
     a.ppar = nullptr;
@@ -1636,8 +1656,8 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     }
     if (buffered && n > 0) {  // gather + the energy sums in one launch
         hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((n + 255) / 256 + 1)), dim3(256), 0,
-                           st, (const long long *)ws->pbuf, (const int *)s->cell_rep, cell_start,
-                           g->ncell, n, (long long *)F, (long long *)ws->part, (long long *)ew);
+                           st, (const long long *)ws->pbuf, (const int *)a.rcnt, n,
+                           (long long *)F, (long long *)ws->part, (long long *)ew);
         LAUNCHCHK("k_gather_partials");
         return LC_OK;
     }
@@ -1916,7 +1936,7 @@ extern "C" int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *off
     };
     if ((rc = up(&s->grp_task, s->h.grp_task)) || (rc = up(&s->grp_foot, s->h.grp_foot)) ||
         (rc = up(&s->foot_cells, s->h.foot_cells)) || (rc = up(&s->task_ab, s->h.task_ab)) ||
-        (rc = up(&s->foot_rep, s->h.foot_rep)) || (rc = up(&s->cell_rep, s->h.cell_rep))) {
+        (rc = up(&s->foot_rep, device_foot_rep(s->h))) || (rc = up(&s->cell_rep, s->h.cell_rep))) {
         lc_schedule_free(s);
         return rc;
     }
@@ -2606,7 +2626,8 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
         b->ncu = ncu;
     std::vector<int64_t> ps(b->pstart);
     if ((rc = upload(&b->d_grp_task, h.grp_task)) || (rc = upload(&b->d_grp_foot, h.grp_foot)) ||
-        (rc = upload(&b->d_foot_cells, h.foot_cells)) || (rc = upload(&b->d_foot_rep, h.foot_rep)) ||
+        (rc = upload(&b->d_foot_cells, h.foot_cells)) ||
+        (rc = upload(&b->d_foot_rep, device_foot_rep(h))) ||
         (rc = upload(&b->d_cell_rep, h.cell_rep)) || (rc = upload(&b->d_grp_box, b->grp_box)) ||
         (rc = upload(&b->d_task_ab, h.task_ab)) || (rc = upload(&b->d_ppar, b->ppar)) ||
         (rc = upload(&b->d_geo, b->geo)) || (rc = upload(&b->d_pstart, ps)) ||
@@ -2694,6 +2715,7 @@ static int batch_forces_impl(const lc_batch *b, const int32_t *cell_start, const
     a.F = (long long *)F;
     a.foot_rep = b->d_foot_rep;
     a.pbuf = ws->pbuf;
+    a.rcnt = rcnt_of(ws, b->h.rmax, b->ntot);
     a.part = (long long *)ws->part;
     a.flags = ws->flags;
     a.pp = b->ppar[0];
@@ -2709,9 +2731,8 @@ static int batch_forces_impl(const lc_batch *b, const int32_t *cell_start, const
     if (ng > 0 && (rc = launch_sweep(b->cap, 3, false, b->ff, a, ng, b->ncu, tk, st))) return rc;
     if (b->ntot > 0) {
         hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((b->ntot + 255) / 256)), dim3(256), 0,
-                           st, (const long long *)ws->pbuf, (const int *)b->d_cell_rep, cell_start,
-                           (int)b->ncell, b->ntot, (long long *)F, (long long *)nullptr,
-                           (long long *)nullptr);
+                           st, (const long long *)ws->pbuf, (const int *)a.rcnt, b->ntot,
+                           (long long *)F, (long long *)nullptr, (long long *)nullptr);
         LAUNCHCHK("k_gather_partials");
     }
     return LC_OK;
@@ -2724,7 +2745,7 @@ extern "C" int lc_batch_forces(const lc_batch *b, const int32_t *cell_start, con
         return fail(LC_EINVAL, "lc_batch_forces: null argument");
     int rc = check_ws(ws, b->ntot, b->ncell);
     if (rc) return rc;
-    if ((rc = ensure_pbuf(ws, (int64_t)b->h.rmax * 3 * b->ntot))) return rc;
+    if ((rc = ensure_pbuf(ws, pbuf_elems(b->h.rmax, b->ntot)))) return rc;
     return batch_forces_impl(b, cell_start, coord, F, ew, persistent, ws, (hipStream_t)stream);
 }
 
@@ -2735,7 +2756,7 @@ extern "C" int lc_batch_graph_create(const lc_batch *b, const int32_t *cell_star
     if (!b || !out || !stream) return fail(LC_EINVAL, "lc_batch_graph_create: bad arguments");
     int rc = check_ws(ws, b->ntot, b->ncell);
     if (rc) return rc;
-    if ((rc = ensure_pbuf(ws, (int64_t)b->h.rmax * 3 * b->ntot))) return rc;  // outside capture
+    if ((rc = ensure_pbuf(ws, pbuf_elems(b->h.rmax, b->ntot)))) return rc;  // outside capture
     hipStream_t st = (hipStream_t)stream;
     lc_graph *gr = new lc_graph();
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
