@@ -108,7 +108,7 @@ struct lc_schedule {
 constexpr int kPartSlots = 1024;    // spread slots for global int64 sums
 constexpr int kWG = 512;            // threads per sweep work-group
 constexpr int kNW = kWG / 64;       // waves per sweep work-group
-constexpr int kQ = 128;             // per-wave pair queue (>= 64 + 63)
+constexpr int kQ = 192;             // per-wave pair queue (>= 128 + 63)
 constexpr int kWB0 = lcs::kMaxGroupCells;  // first thread of the write-back waves
 constexpr int kFPad = 64;           // filter rows past the footprint (see SweepLDS)
 constexpr int kFFCell = kFPad - 4;  // largest cell the filter path stages
@@ -665,9 +665,23 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
         }
     };
 
-    auto eval = [&](uint32_t ent) {
-        const int il = (int)(ent & 0xffffu), jl = (int)(ent >> 16);
-        const uint4 ui = load_u(il), uj = load_u(jl);
+    // one queued pair: its coordinates are loaded first (load), so that the
+    // loads of two batches are in flight together, then evaluated (eval)
+    struct PairIn {
+        uint4 ui, uj;
+        int il, jl;
+    };
+    auto load = [&](uint32_t ent) -> PairIn {
+        PairIn r;
+        r.il = (int)(ent & 0xffffu);
+        r.jl = (int)(ent >> 16);
+        r.ui = load_u(r.il);
+        r.uj = load_u(r.jl);
+        return r;
+    };
+    auto eval = [&](const PairIn &pin) {
+        const int il = pin.il, jl = pin.jl;
+        const uint4 ui = pin.ui, uj = pin.uj;
         long long qx, qy, qz, qe, qw;
         bool in;
         if constexpr (F64)
@@ -718,15 +732,17 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             q[qn + below] = ent;
         }
         qn += (int)__popcll(m);
-        if (qn >= 64) {
+        if (qn >= 128) {  // two batches, their loads in flight together
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            eval(q[lane]);
-            const uint32_t rest = lane + 64 < qn ? q[lane + 64] : 0u;
+            const PairIn p0 = load(q[lane]), p1 = load(q[lane + 64]);
+            const uint32_t rest = lane + 128 < qn ? q[lane + 128] : 0u;
+            eval(p0);
+            eval(p1);
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            if (lane + 64 < qn) q[lane] = rest;
-            qn -= 64;
+            if (lane + 128 < qn) q[lane] = rest;
+            qn -= 128;
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         }
@@ -853,7 +869,8 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    if (lane < qn) eval(q[lane]);
+    if (lane < qn) eval(load(q[lane]));
+    if (lane + 64 < qn) eval(load(q[lane + 64]));
 }
 
 // What a group's setup reads from global memory before its LDS work: the
