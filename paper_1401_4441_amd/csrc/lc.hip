@@ -96,6 +96,10 @@ struct lc_schedule {
     int32_t *grp_task = nullptr, *grp_foot = nullptr, *foot_cells = nullptr;
     uint32_t *task_ab = nullptr;
     int32_t *foot_rep = nullptr, *cell_rep = nullptr;  // buffer + reduce
+    // the same groups at a fixed stride (see SweepArgs), or none
+    uint32_t *fx_task = nullptr;
+    int32_t *fx_foot = nullptr, *fx_rep = nullptr, *fx_cnt = nullptr;
+    int fx_tmax = 0, fx_fmax = 0;
     // creation-order kinds: tasks in creation order and, per task, how many
     // earlier tasks touch its cells A and B (dataflow executors)
     int32_t *df_a = nullptr, *df_b = nullptr, *df_seqa = nullptr, *df_seqb = nullptr;
@@ -498,6 +502,13 @@ struct SweepArgs {
     // persistent launch: work-groups draw groups from this ticket counter
     int *ticket;
     int ngroups;
+    // Optional copy of the group tables at a fixed stride: group g's task
+    // entries at fx_task[g * fx_tmax ..], footprint cells (-1 past the end)
+    // and replica entries at fx_foot / fx_rep[g * fx_fmax ..], {nt, nf} at
+    // fx_cnt[2 g].  A group's setup then reads them all in one round trip.
+    const uint32_t *fx_task;
+    const int *fx_foot, *fx_rep, *fx_cnt;
+    int fx_tmax, fx_fmax;
 };
 
 // Exact round-to-nearest-even of v * 2^32 to int64 for |v| < 2^19: the FP64
@@ -918,6 +929,24 @@ __device__ __forceinline__ void pre_foot(const SweepArgs &a, GroupPre &p) {
     p.rep = (WMODE >= 3 && tid < p.nf) ? a.foot_rep[p.f0 + tid] : 0;
 }
 
+// Both steps of pre_head / pre_foot in one round trip, from the fixed-stride
+// tables.
+template <int WMODE>
+__device__ __forceinline__ void pre_fixed(const SweepArgs &a, int g, GroupPre &p) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    p.g = g;
+    p.box = 0;
+    const int hv = a.fx_cnt[2 * g + (lane & 1)];
+    const int64_t tb = (int64_t)g * a.fx_tmax, fb = (int64_t)g * a.fx_fmax;
+    p.ab = tid < a.fx_tmax ? a.fx_task[tb + tid] : 0u;
+    p.c = tid < a.fx_fmax ? a.fx_foot[fb + tid] : -1;
+    p.rep = (WMODE >= 3 && tid < a.fx_fmax) ? a.fx_rep[fb + tid] : 0;
+    p.t0 = 0;
+    p.f0 = 0;
+    p.nt = __builtin_amdgcn_readlane(hv, 0);
+    p.nf = __builtin_amdgcn_readlane(hv, 1);
+}
+
 __device__ __forceinline__ void pre_cells(const SweepArgs &a, GroupPre &p) {
     p.gs = p.c >= 0 ? a.cell_start[p.c] : 0;
     p.ge = p.c >= 0 ? a.cell_start[p.c + 1] : 0;
@@ -1181,9 +1210,13 @@ void k_sweep(SweepArgs a) {
     GroupPre p, nx;
     int stage = 0;
     if (!a.ticket) {
-        pre_head(a, a.grp_base + blockIdx.x, p);
-        pre_head_done(a, p);
-        pre_foot<WMODE>(a, p);
+        if (a.fx_task) {
+            pre_fixed<WMODE>(a, a.grp_base + blockIdx.x, p);
+        } else {
+            pre_head(a, a.grp_base + blockIdx.x, p);
+            pre_head_done(a, p);
+            pre_foot<WMODE>(a, p);
+        }
         pre_cells(a, p);
         sweep_group<CAP, WMODE, F64, FF, false>(sh, a, p, nx, stage);
         return;
@@ -1638,6 +1671,12 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     a.foot_rep = s->foot_rep;
     a.pbuf = ws->pbuf;
     a.rcnt = buffered ? rcnt_of(ws, s->h.rmax, n) : nullptr;
+    a.fx_task = s->fx_task;
+    a.fx_foot = s->fx_foot;
+    a.fx_rep = s->fx_rep;
+    a.fx_cnt = s->fx_cnt;
+    a.fx_tmax = s->fx_tmax;
+    a.fx_fmax = s->fx_fmax;
     a.part = (long long *)ws->part;
     a.grp_box = nullptr;
     a.ppar = nullptr;
@@ -1957,6 +1996,42 @@ extern "C" int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *off
         lc_schedule_free(s);
         return rc;
     }
+    {
+        // fixed-stride copy of the group tables when the padding costs at
+        // most half again the tables themselves (near-uniform groups)
+        const lcs::HostSchedule &h = s->h;
+        const size_t ng = h.grp_task.size() - 1;
+        int tmax = 0, fmax = 0;
+        for (size_t q = 0; q < ng; ++q) {
+            tmax = std::max(tmax, h.grp_task[q + 1] - h.grp_task[q]);
+            fmax = std::max(fmax, h.grp_foot[q + 1] - h.grp_foot[q]);
+        }
+        const size_t padded = ng * (size_t)(tmax + 2 * fmax);
+        const size_t actual = h.task_ab.size() + 2 * h.foot_cells.size();
+        if (ng > 0 && tmax > 0 && 2 * padded <= 3 * actual) {
+            const std::vector<int32_t> drep = device_foot_rep(h);
+            std::vector<uint32_t> ft(ng * (size_t)tmax, 0u);
+            std::vector<int32_t> ff(ng * (size_t)fmax, -1), fr(ng * (size_t)fmax, 0), fc(2 * ng);
+            for (size_t q = 0; q < ng; ++q) {
+                const int t0 = h.grp_task[q], nt = h.grp_task[q + 1] - t0;
+                const int f0 = h.grp_foot[q], nf = h.grp_foot[q + 1] - f0;
+                for (int t = 0; t < nt; ++t) ft[q * tmax + t] = h.task_ab[(size_t)(t0 + t)];
+                for (int f = 0; f < nf; ++f) {
+                    ff[q * fmax + f] = h.foot_cells[(size_t)(f0 + f)];
+                    if (!drep.empty()) fr[q * fmax + f] = drep[(size_t)(f0 + f)];
+                }
+                fc[2 * q] = nt;
+                fc[2 * q + 1] = nf;
+            }
+            if ((rc = up(&s->fx_task, ft)) || (rc = up(&s->fx_foot, ff)) ||
+                (rc = up(&s->fx_rep, fr)) || (rc = up(&s->fx_cnt, fc))) {
+                lc_schedule_free(s);
+                return rc;
+            }
+            s->fx_tmax = tmax;
+            s->fx_fmax = fmax;
+        }
+    }
     if (!s->h.order_a.empty()) {  // creation-order kind: the dataflow task list
         const size_t nt = s->h.order_a.size();
         std::vector<int32_t> seen((size_t)g->ncell, 0), sa(nt), sb(nt);
@@ -1988,6 +2063,10 @@ extern "C" void lc_schedule_free(lc_schedule *s) {
     (void)hipFree(s->task_ab);
     (void)hipFree(s->foot_rep);
     (void)hipFree(s->cell_rep);
+    (void)hipFree(s->fx_task);
+    (void)hipFree(s->fx_foot);
+    (void)hipFree(s->fx_rep);
+    (void)hipFree(s->fx_cnt);
     (void)hipFree(s->df_a);
     (void)hipFree(s->df_b);
     (void)hipFree(s->df_seqa);
@@ -2733,6 +2812,9 @@ static int batch_forces_impl(const lc_batch *b, const int32_t *cell_start, const
     a.foot_rep = b->d_foot_rep;
     a.pbuf = ws->pbuf;
     a.rcnt = rcnt_of(ws, b->h.rmax, b->ntot);
+    a.fx_task = nullptr;
+    a.fx_foot = a.fx_rep = a.fx_cnt = nullptr;
+    a.fx_tmax = a.fx_fmax = 0;
     a.part = (long long *)ws->part;
     a.flags = ws->flags;
     a.pp = b->ppar[0];
