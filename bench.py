@@ -84,12 +84,23 @@ def measured_traffic(kernel_prefix: str, workload: str, config: dict):
     return None
 
 
-def candidate_pairs(cell_start: np.ndarray, nc) -> int:
+def half_shell(reach: int):
+    """Half shell of a stencil reaching `reach` cells: the offsets with
+    dx > 0, or dx = 0 and dz > 0, or dx = dz = 0 and dy < 0 (13 at reach 1,
+    62 at reach 2)."""
+    if reach == 1:
+        return H3
+    r = range(-reach, reach + 1)
+    return [(x, y, z) for z in r for y in r for x in r
+            if x > 0 or (x == 0 and z > 0) or (x == 0 and z == 0 and y < 0)]
+
+
+def candidate_pairs(cell_start: np.ndarray, nc, reach: int = 1) -> int:
     """Candidate pairs the half-stencil sweep visits: n_c(n_c-1)/2 per cell
     plus n_c * n_{c+d} per cell and half-stencil offset d."""
     cnt = np.diff(cell_start.astype(np.int64)).reshape(nc[2], nc[1], nc[0])
     total = int(np.sum(cnt * (cnt - 1) // 2))
-    for dx, dy, dz in H3:
+    for dx, dy, dz in half_shell(reach):
         nb = np.roll(cnt, shift=(-dz, -dy, -dx), axis=(0, 1, 2))
         total += int(np.sum(cnt * nb))
     return total
@@ -109,7 +120,7 @@ def main():
                     help="fix the headline schedule instead of autotuning (with --block and "
                          "--grid; used to profile one configuration)")
     ap.add_argument("--block", default=None, help="block shape X,Y,Z for --schedule")
-    ap.add_argument("--grid", default="natural", choices=("even", "natural", "wide"),
+    ap.add_argument("--grid", default="natural", choices=("even", "natural", "wide", "half"),
                     help="cell grid for --schedule: even counts, natural (side >= rc), "
                          "or widened 15%% with even counts")
     ap.add_argument("--copy-probe", action="store_true",
@@ -149,7 +160,8 @@ def main():
     # the baseline table); the fastest conflict-free one is the headline
     if args.schedule:
         gopt = {"even": {"extra": 0.0, "even": True}, "natural": {"extra": 0.0, "even": False},
-                "wide": {"extra": 0.15, "even": True}}[args.grid]
+                "wide": {"extra": 0.15, "even": True},
+                "half": {"extra": 0.0, "even": False, "half": True}}[args.grid]
         blk0 = [int(x) for x in args.block.split(",")] if args.block else [1, 2, 2]
         pick = {"kind": args.schedule, "block": blk0, "grid": gopt}
         tune = {"trials": [dict(pick, nc=[0, 0, 0], ms=0.0, fallback=False)]}
@@ -159,7 +171,7 @@ def main():
         cf = [t for t in tune["trials"]
               if t["kind"] in autotune.BOX_KINDS_CONFLICT_FREE and not t["fallback"]]
         pick = min(cf, key=lambda t: t["ms"])
-    g = lc.Grid(box.L, box.rc, pick["grid"]["extra"], pick["grid"]["even"])
+    g = autotune.make_grid(box.L, box.rc, pick["grid"])
     ws = lc.Workspace(box.n, g.ncell)
     cs, perm, coord = lc.build_cells(g, pos, ws)
 
@@ -168,7 +180,7 @@ def main():
                    if t["kind"] == kind and t["grid"] == pick["grid"] and not t.get("fallback")]
         return tuple(min(on_grid, key=lambda t: t["ms"])["block"]) if on_grid else None
     torch.cuda.synchronize()
-    ncand = candidate_pairs(cs.cpu().numpy(), g.nc)
+    ncand = candidate_pairs(cs.cpu().numpy(), g.nc, g.reach)
     F = torch.empty((3, box.n), dtype=torch.int64, device=dev)
     ew = torch.empty(3, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
@@ -272,6 +284,10 @@ def main():
                              ("fullshell", 20, 3), ("atomic_pair", 20, 3), ("loopex", 10, 2),
                              ("opt", 2, 1), ("lex", 1, 1)):
             kb = best_block(kind)
+            if g.reach == 2 and kind in ("loopex", "opt", "lex"):
+                extra[kind] = {"skipped": "creation orders are timed on the rc-cell grid "
+                                          "(paper_strategies)"}
+                continue
             try:
                 s, kms, _ = time_sched(kind, st, wu, kb)
             except lc.LCError as e:  # loop exchange needs even cell counts
@@ -309,7 +325,7 @@ def main():
         t_begin = time.perf_counter()
         while len(times) < 5 and (time.perf_counter() - t_begin) < 20.0:
             t0 = time.perf_counter()
-            _, _, _, npo = O.forces_lc_fx(u, box.L, box.rc, g.nc)
+            _, _, _, npo = O.forces_lc_fx(u, box.L, box.rc, O.grid_dims(box.L, box.rc))
             times.append(time.perf_counter() - t0)
         t = statistics.median(times)
         out["cpu_baseline"] = {
@@ -453,7 +469,7 @@ def bench_slab(args):
     cf = [t for t in tune["trials"]
           if t["kind"] in autotune.BOX_KINDS_CONFLICT_FREE and not t["fallback"]]
     pick = min(cf, key=lambda t: t["ms"])
-    g = lc.Grid(box.L, box.rc, pick["grid"]["extra"], pick["grid"]["even"])
+    g = autotune.make_grid(box.L, box.rc, pick["grid"])
     ws = lc.Workspace(box.n, g.ncell)
     cs, perm, coord = lc.build_cells(g, pos, ws)
     F = torch.empty((3, box.n), dtype=torch.int64, device=dev)
@@ -463,7 +479,11 @@ def bench_slab(args):
         on_grid = [t for t in tune["trials"]
                    if t["kind"] == kind and t["grid"] == pick["grid"] and not t.get("fallback")]
         blk = tuple(min(on_grid, key=lambda t: t["ms"])["block"]) if on_grid else None
-        s = lc.Schedule(g, kind, block=blk)
+        try:
+            s = lc.Schedule(g, kind, block=blk)
+        except lc.LCError as e:  # e.g. no block colouring on cells of side rc/2
+            res[kind] = {"skipped": str(e)}
+            continue
         ws.clear_status()
         ms = _time_evals(lambda: lc.compute_forces(g, s, cs, coord, ws, "fp32", F, ew),
                          max(args.steps // 5, 3), 2)
@@ -471,15 +491,34 @@ def bench_slab(args):
         s.close()
     pairs = int(ew[2].item())
     counts = (cs[1:] - cs[:-1]).cpu().numpy()
-    best = min(("buffer", "block8"), key=lambda k: res[k]["ms"])
+    best = min((k for k in ("buffer", "block8") if "ms" in res[k]), key=lambda k: res[k]["ms"])
+    # cell side rc against rc/2 (the reach-2 stencil: fewer candidate pairs,
+    # smaller and more numerous tasks), fastest trial of each kind per grid
+    variants = {}
+    for name, gopt in (("rc", {"extra": 0.0, "even": False}),
+                       ("rc/2", {"extra": 0.0, "even": False, "half": True})):
+        gv = autotune.make_grid(box.L, box.rc, gopt)
+        wsv = lc.Workspace(box.n, gv.ncell)
+        csv_, _, _ = lc.build_cells(gv, pos, wsv)
+        entry = {"cells": list(gv.nc), "candidate_pairs": candidate_pairs(csv_.cpu().numpy(), gv.nc,
+                                                                           gv.reach)}
+        for kind in ("buffer", "atomic_tile"):
+            tr = [t for t in tune["trials"] if t["kind"] == kind and t["grid"] == gopt
+                  and not t["fallback"]]
+            if tr:
+                t = min(tr, key=lambda t: t["ms"])
+                entry[kind] = {"ms": t["ms"], "block": t["block"]}
+        variants[name] = entry
+        wsv.close()
     _line("pair interactions/sec (LJ cell-pair force sweep, inhomogeneous slab)",
           pairs / (res[best]["ms"] * 1e-3), "pairs/s", res[best]["ms"], args,
           {"workload": "LJ slab N=2000000, rho 0.75 middle third / 0.02 gas, rc=3.0",
            "cells": list(g.nc), "schedule": best, "block": res[best]["block"],
-           "pairs_in_cutoff": pairs,
+           "pairs_in_cutoff": pairs, "grid_choice": pick["grid"], "cell_size_variants": variants,
            "cell_occupancy": {"max": int(counts.max()), "mean": float(counts.mean()),
                               "empty_frac": float((counts == 0).mean())}},
-          schedules={k: dict(v, pairs_per_s=pairs / (v["ms"] * 1e-3)) for k, v in res.items()})
+          schedules={k: (dict(v, pairs_per_s=pairs / (v["ms"] * 1e-3)) if "ms" in v else v)
+                     for k, v in res.items()})
 
 
 def bench_boxes(args):

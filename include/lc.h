@@ -79,6 +79,9 @@ const char *lc_last_error(void);
 /* ---- grid --------------------------------------------------------------- */
 
 #define LC_GRID_EVEN 1 /* round the cell count per axis down to even       */
+#define LC_GRID_HALF 2 /* cells of side >= (rc + skin) / 2: the stencil
+                          reaches 2 cells (Sec. IV takes side >= rc; the
+                          half-size cells visit fewer candidate pairs)       */
 
 /* Periodic cell grid (Sec. IV: cells of side >= rc).  Filled by
  * lc_make_grid; plain data, may be copied. */
@@ -92,13 +95,19 @@ typedef struct lc_grid {
     float scale[3];    /* (float)(L_d * 2^-32)                              */
     float rc2;         /* (float)(rc * rc)                                  */
     float ecut;        /* canonical pair energy at r2 = rc2                 */
-    int32_t pad;
+    int32_t reach;     /* stencil reach in cells: 1, or 2 with LC_GRID_HALF  */
 } lc_grid;
 
 /* [host] nc_d = floor(L_d / (rc * (1 + 2^-12) + skin)), the largest count
  * whose cell side covers rc plus the skin with a margin that FP32 rounding of
- * r2 cannot cross.  flags: LC_GRID_EVEN.  Returns LC_EINVAL when an axis gets
- * fewer than 3 cells (pairs would be visited twice) or ncell >= 2^31. */
+ * r2 cannot cross; with LC_GRID_HALF, floor(2 L_d / (...)) (two cells cover
+ * it, reach 2).  flags: LC_GRID_EVEN | LC_GRID_HALF.  Returns LC_EINVAL when
+ * an axis gets fewer than 2 reach + 1 cells (pairs would be visited twice) or
+ * ncell >= 2^31.  Schedules and sweeps follow the grid's reach; at reach 2
+ * there is no LC_SCHED_BLOCK8 (LC_SCHED_LOOPEX colours with stride 3 and
+ * needs cell counts divisible by 3), the presets OPT/BEST/BAD are not defined
+ * (pass the order as LC_SCHED_CUSTOM offsets in [-2, 2]), and batches take
+ * reach-1 grids only. */
 int lc_make_grid(const double box[3], double rc, double skin, int flags,
                  lc_grid *out);
 

@@ -31,13 +31,33 @@ BOX_KINDS_CONFLICT_FREE = ("block8", "buffer")
 # (one work-group per compute unit), so they need no pruning here.
 BLOCKS = {"block8": ((1, 2, 2), (2, 2, 2), (1, 3, 3), (2, 3, 3)),
           "uncoloured": ((1, 2, 2), (1, 2, 3), (1, 3, 3), (2, 2, 2), (2, 2, 3), (1, 3, 4),
-                         (1, 4, 4), (2, 3, 3))}
+                         (1, 4, 4), (2, 3, 3)),
+          # cells of side rc/2: the reach-2 footprint of a block (bx + 2) x
+          # (by + 4) x (bz + 4) must stay within 128 cells
+          "uncoloured_half": ((1, 1, 1), (1, 1, 2), (2, 1, 1), (1, 2, 2), (1, 2, 3))}
 
 
-def shapes_for(kind: str):
-    return BLOCKS["block8"] if kind == "block8" else BLOCKS["uncoloured"]
+def shapes_for(kind: str, half: bool = False):
+    if kind == "block8":
+        return BLOCKS["block8"]
+    return BLOCKS["uncoloured_half"] if half else BLOCKS["uncoloured"]
 GRIDS = ({"extra": 0.0, "even": True}, {"extra": 0.0, "even": False},
-         {"extra": 0.15, "even": True})
+         {"extra": 0.15, "even": True}, {"extra": 0.0, "even": False, "half": True})
+
+
+def _first_schedule(grid, kinds):
+    """A schedule of the first kind the grid supports (for clock warm-up)."""
+    for kind in kinds:
+        try:
+            return lc.Schedule(grid, kind)
+        except lc.LCError:
+            continue
+    raise lc.LCError(-1, "autotune: no schedule kind fits this grid")
+
+
+def make_grid(L, rc: float, gopt: dict):
+    """The grid a GRIDS entry (or a trial's "grid" record) describes."""
+    return lc.Grid(L, rc, gopt["extra"], gopt["even"], half=gopt.get("half", False))
 
 
 def _cache_path() -> str:
@@ -113,20 +133,20 @@ def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
     warmed = False
     for gopt in GRIDS:
         try:
-            grid = lc.Grid(L, rc, gopt["extra"], gopt["even"])
+            grid = make_grid(L, rc, gopt)
         except lc.LCError:
             continue
         ws = lc.Workspace(n, grid.ncell)
         cs, perm, coord = lc.build_cells(grid, pos, ws)
         if not warmed:  # bring the clocks up before the first trial counts
-            s0 = lc.Schedule(grid, kinds[0])
+            s0 = _first_schedule(grid, kinds)
             t_end = time.perf_counter() + 0.3
             while time.perf_counter() < t_end:
                 time_forces(grid, s0, cs, coord, ws, reps=10, warmup=0, rounds=1)
             s0.close()
             warmed = True
         for kind in kinds:
-            for block in shapes_for(kind):
+            for block in shapes_for(kind, grid.reach == 2):
                 try:
                     sched = lc.Schedule(grid, kind, block=block)
                 except lc.LCError:
@@ -160,14 +180,14 @@ def tune_shape(grid, pos: torch.Tensor, kinds=BOX_KINDS_CONFLICT_FREE, reps: int
     n = pos.shape[1]
     ws = lc.Workspace(n, grid.ncell)
     cs, perm, coord = lc.build_cells(grid, pos, ws)
-    s0 = lc.Schedule(grid, kinds[0])
+    s0 = _first_schedule(grid, kinds)
     t_end = time.perf_counter() + 0.3
     while time.perf_counter() < t_end:  # clocks up before the trials count
         time_forces(grid, s0, cs, coord, ws, reps=10, warmup=0, rounds=1)
     s0.close()
     trials, best = [], None
     for kind in kinds:
-        for block in shapes_for(kind):
+        for block in shapes_for(kind, grid.reach == 2):
             try:
                 sched = lc.Schedule(grid, kind, block=block)
             except lc.LCError:

@@ -1812,6 +1812,9 @@ static int gather_impl(const int32_t *perm, int64_t n, const double *in3, double
 // C-ABI
 // ---------------------------------------------------------------------------
 
+// Stencil reach of a grid (grids filled before the field existed read 0).
+static int grid_reach(const lc_grid *g) { return g->reach > 1 ? 2 : 1; }
+
 extern "C" int lc_make_grid(const double box[3], double rc, double skin, int flags,
                             lc_grid *out) {
     if (!box || !out) return fail(LC_EINVAL, "lc_make_grid: null argument");
@@ -1823,13 +1826,15 @@ extern "C" int lc_make_grid(const double box[3], double rc, double skin, int fla
         if (!(box[d] > 0.0)) return fail(LC_EINVAL, "lc_make_grid: box length");
         g.box[d] = box[d];
         g.inv_box[d] = 1.0 / box[d];
-        const double side = rc * (1.0 + 1.0 / 4096.0) + skin;
+        const int reach = (flags & LC_GRID_HALF) ? 2 : 1;
+        const double side = (rc * (1.0 + 1.0 / 4096.0) + skin) / reach;
         const double q = box[d] / side;
         if (!(q < 2147483647.0)) return fail(LC_EINVAL, "lc_make_grid: too many cells");
         int64_t k = (int64_t)q;
         if ((flags & LC_GRID_EVEN) && (k & 1)) k -= 1;
-        if (k < 3)
-            return fail(LC_EINVAL, "lc_make_grid: axis %d gets %lld cells (< 3)", d, (long long)k);
+        if (k < 2 * reach + 1)
+            return fail(LC_EINVAL, "lc_make_grid: axis %d gets %lld cells (< %d)", d, (long long)k,
+                        2 * reach + 1);
         g.nc[d] = (int32_t)k;
         ncell *= k;
         g.scale[d] = (float)(box[d] / 4294967296.0);
@@ -1838,6 +1843,7 @@ extern "C" int lc_make_grid(const double box[3], double rc, double skin, int fla
     g.ncell = (int32_t)ncell;
     g.rc = rc;
     g.skin = skin;
+    g.reach = (flags & LC_GRID_HALF) ? 2 : 1;
     g.rc2 = (float)(rc * rc);
     {
         float inv = 1.0f / g.rc2;
@@ -1962,7 +1968,7 @@ extern "C" int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *off
     lc_schedule *s = new lc_schedule();
     for (int d = 0; d < 3; ++d) s->nc[d] = g->nc[d];
     std::string err;
-    int rc = lcs::build_schedule(g->nc, kind, offsets, n, s->h, err, block_min);
+    int rc = lcs::build_schedule(g->nc, kind, offsets, n, s->h, err, block_min, grid_reach(g));
     if (rc) {
         delete s;
         return fail(rc, "lc_make_schedule: %s", err.c_str());
@@ -2100,7 +2106,7 @@ extern "C" int lc_schedule_plan_ex(const lc_grid *g, int kind, const int8_t *off
     if (kind < 0 || kind >= LC_SCHED_COUNT) return fail(LC_EINVAL, "unknown schedule kind %d", kind);
     lcs::HostSchedule h;
     std::string err;
-    int rc = lcs::build_schedule(g->nc, kind, offsets, n, h, err, block_min);
+    int rc = lcs::build_schedule(g->nc, kind, offsets, n, h, err, block_min, grid_reach(g));
     if (rc) return fail(rc, "lc_schedule_plan: %s", err.c_str());
     if (!lcs::validate(h, g->ncell, err)) return fail(LC_ESCHED, "lc_schedule_plan: %s", err.c_str());
     memset(out, 0, sizeof *out);
@@ -2147,7 +2153,8 @@ extern "C" int lc_serialization_degree(const int32_t dims[3], int kind, const in
     if (kind != LC_SCHED_LEX && kind != LC_SCHED_OPT && kind != LC_SCHED_BEST &&
         kind != LC_SCHED_BAD && kind != LC_SCHED_LOOPEX && kind != LC_SCHED_CUSTOM)
         return fail(LC_EINVAL, "kind %d has no creation order", kind);
-    if (!lcs::stencil_order(kind, two_d, offsets, n, order, err))
+    if (!lcs::stencil_order(kind, two_d, offsets, n, order, err,
+                            kind == LC_SCHED_CUSTOM ? lcs::order_reach(offsets, n) : 1))
         return fail(LC_EINVAL, "serialization_degree: %s", err.c_str());
     std::vector<int32_t> A, B, level;
     if (kind == LC_SCHED_LOOPEX) {
@@ -2191,7 +2198,8 @@ extern "C" int lc_serialization_degree_weighted(const int32_t dims[3], int kind,
     const bool two_d = dims[2] == 1;
     std::vector<lcs::Offset> order;
     std::string err;
-    if (!lcs::stencil_order(kind, two_d, offsets, n, order, err))
+    if (!lcs::stencil_order(kind, two_d, offsets, n, order, err,
+                            kind == LC_SCHED_CUSTOM ? lcs::order_reach(offsets, n) : 1))
         return fail(LC_EINVAL, "serialization_degree_weighted: %s", err.c_str());
     std::vector<int32_t> A, B;
     if (kind == LC_SCHED_LOOPEX) {
@@ -2580,6 +2588,10 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
         if (boxes[k].n < 0 || boxes[k].grid.ncell < 27) {
             delete b;
             return fail(LC_EINVAL, "lc_batch_create: box %d", k);
+        }
+        if (grid_reach(&boxes[k].grid) != 1) {
+            delete b;
+            return fail(LC_EINVAL, "lc_batch_create: box %d has a reach-2 grid", k);
         }
         b->pstart.push_back(b->pstart.back() + boxes[k].n);
         b->cstart.push_back(b->cstart.back() + boxes[k].grid.ncell);

@@ -2,6 +2,7 @@
 #include "lc_sched.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <unordered_map>
 
@@ -52,10 +53,33 @@ std::vector<Offset> half_stencil(bool two_d) {
     return h;
 }
 
+std::vector<Offset> half_shell(int reach) {
+    if (reach <= 1) return half_stencil(false);
+    std::vector<Offset> h;
+    const int r = reach;
+    for (int dx = 1; dx <= r; ++dx)
+        for (int dz = -r; dz <= r; ++dz)
+            for (int dy = -r; dy <= r; ++dy) h.push_back(mk(dx, dy, dz));
+    for (int dz = 1; dz <= r; ++dz)
+        for (int dy = -r; dy <= r; ++dy) h.push_back(mk(0, dy, dz));
+    for (int dy = -1; dy >= -r; --dy) h.push_back(mk(0, dy, 0));
+    return h;
+}
+
+int order_reach(const int8_t *offsets, int n) {
+    int r = 1;
+    for (int k = 0; offsets && k < 3 * n; ++k) r = std::max(r, std::abs((int)offsets[k]));
+    return r;
+}
+
 bool stencil_order(int kind, bool two_d, const int8_t *offsets, int n,
-                   std::vector<Offset> &order, std::string &err) {
+                   std::vector<Offset> &order, std::string &err, int reach) {
     order.clear();
     const Offset intra = mk(0, 0, 0), ex = mk(1, 0, 0);
+    if (reach < 1 || reach > 2 || (two_d && reach != 1)) {
+        err = "stencil reach must be 1 or 2 (3D)";
+        return false;
+    }
     if (kind == LC_SCHED_CUSTOM) {
         if (!offsets || n <= 0) {
             err = "custom order needs offsets";
@@ -64,20 +88,23 @@ bool stencil_order(int kind, bool two_d, const int8_t *offsets, int n,
         for (int k = 0; k < n; ++k)
             order.push_back(mk(offsets[3 * k], offsets[3 * k + 1], offsets[3 * k + 2]));
         // validate: intra once, and one of d / -d for every neighbour
-        int nz = 0, want = two_d ? 9 : 27;
-        std::vector<int> seen(27, 0);
+        const int r = reach, w = 2 * r + 1;
+        int nz = 0;
+        const int want = two_d ? w * w : w * w * w;
+        std::vector<int> seen((size_t)(w * w * w), 0);
         for (auto &o : order) {
             for (int d = 0; d < 3; ++d)
-                if (o.d[d] < -1 || o.d[d] > 1) {
-                    err = "offset component outside [-1, 1]";
+                if (o.d[d] < -r || o.d[d] > r) {
+                    err = r == 1 ? "offset component outside [-1, 1]"
+                                 : "offset component outside [-2, 2]";
                     return false;
                 }
             if (two_d && o.d[2]) {
                 err = "2D order with nonzero dz";
                 return false;
             }
-            int k1 = (o.d[0] + 1) + 3 * (o.d[1] + 1) + 9 * (o.d[2] + 1);
-            int k2 = (-o.d[0] + 1) + 3 * (-o.d[1] + 1) + 9 * (-o.d[2] + 1);
+            int k1 = (o.d[0] + r) + w * (o.d[1] + r) + w * w * (o.d[2] + r);
+            int k2 = (-o.d[0] + r) + w * (-o.d[1] + r) + w * w * (-o.d[2] + r);
             if (seen[k1] || (k1 != k2 && seen[k2])) {
                 err = "offset or its mirror repeated";
                 return false;
@@ -90,6 +117,25 @@ bool stencil_order(int kind, bool two_d, const int8_t *offsets, int n,
             return false;
         }
         return true;
+    }
+    if (reach == 2) {
+        switch (kind) {
+            case LC_SCHED_LEX:
+            case LC_SCHED_LOOPEX:
+            case LC_SCHED_BLOCK8:
+            case LC_SCHED_ATOMIC_TILE:
+            case LC_SCHED_ATOMIC_PAIR:
+            case LC_SCHED_BUFFER: {
+                std::vector<Offset> h2 = half_shell(2);
+                std::sort(h2.begin(), h2.end(), lin_less);
+                order.push_back(intra);
+                for (auto &o : h2) order.push_back(o);
+                return true;
+            }
+            default:
+                err = "this kind has no reach-2 preset order (pass the offsets)";
+                return false;
+        }
     }
     std::vector<Offset> h = half_stencil(two_d);
     std::sort(h.begin(), h.end(), lin_less);
@@ -162,19 +208,20 @@ void basic_tasks(const int32_t dims[3], const std::vector<Offset> &order,
 }
 
 bool loopex_tasks(const int32_t dims[3], const std::vector<Offset> &order,
-                  std::vector<int32_t> &A, std::vector<int32_t> &B) {
+                  std::vector<int32_t> &A, std::vector<int32_t> &B, int stride) {
     const int64_t nx = dims[0], ny = dims[1], nz = dims[2];
     const bool flat = nz == 1;
-    if ((nx & 1) || (ny & 1) || (!flat && (nz & 1))) return false;
+    const int s = stride;
+    if ((nx % s) || (ny % s) || (!flat && (nz % s))) return false;
     A.clear();
     B.clear();
-    const int zc = flat ? 1 : 2, zs = flat ? 1 : 2;
+    const int zc = flat ? 1 : s, zs = flat ? 1 : s;
     for (const Offset &o : order)
-        for (int c = 0; c < 4 * zc; ++c) {
-            const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+        for (int c = 0; c < s * s * zc; ++c) {
+            const int cx = c % s, cy = (c / s) % s, cz = c / (s * s);
             for (int64_t z = cz; z < nz; z += zs)
-                for (int64_t y = cy; y < ny; y += 2)
-                    for (int64_t x = cx; x < nx; x += 2) {
+                for (int64_t y = cy; y < ny; y += s)
+                    for (int64_t x = cx; x < nx; x += s) {
                         A.push_back((int32_t)(x + nx * (y + ny * z)));
                         B.push_back((int32_t)(wrap(x + o.d[0], nx) +
                                               nx * (wrap(y + o.d[1], ny) +
@@ -297,7 +344,20 @@ std::vector<int> axis_blocks(int n, int minsize) {
 }  // namespace
 
 int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
-                   int n, HostSchedule &hs, std::string &err, const int32_t *block_min) {
+                   int n, HostSchedule &hs, std::string &err, const int32_t *block_min,
+                   int reach) {
+    if (reach != 1 && reach != 2) {
+        err = "stencil reach must be 1 or 2";
+        return LC_EINVAL;
+    }
+    if (reach == 2 && kind == LC_SCHED_BLOCK8) {
+        err = "no 2x2x2 block colouring at reach 2 (use buffer, atomic_tile or loopex)";
+        return LC_EINVAL;
+    }
+    if (kind == LC_SCHED_CUSTOM && order_reach(offsets, n) != reach) {
+        err = "custom offsets must reach as far as the grid's stencil";
+        return LC_EINVAL;
+    }
     // BLOCK8 colours its blocks, so their sizes are lower bounds (the
     // stencil reach) with an even block count per axis; the uncoloured kinds
     // take explicit sizes as upper bounds.
@@ -325,14 +385,15 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
         // each home cell with its intra task and its 26 full-shell
         // neighbours; foot_rep marks the home cells (1), which alone are
         // written.
-        static const int32_t dflt[3] = {1, 2, 2};
-        const int32_t *sz = block_min ? bmin : dflt;
+        // (default 1 x 1 x 1 at reach 2: a 125-cell footprint)
+        static const int32_t dflt[3] = {1, 2, 2}, dflt2[3] = {1, 1, 1};
+        const int32_t *sz = block_min ? bmin : (reach == 2 ? dflt2 : dflt);
         std::vector<int> bs[3];
         for (int d = 0; d < 3; ++d) bs[d] = axis_blocks_max(nc[d], sz[d]);
         std::vector<Offset> shell(1, Offset{{0, 0, 0}});
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx)
+        for (int dz = -reach; dz <= reach; ++dz)
+            for (int dy = -reach; dy <= reach; ++dy)
+                for (int dx = -reach; dx <= reach; ++dx)
                     if (dx || dy || dz) shell.push_back(Offset{{(int8_t)dx, (int8_t)dy, (int8_t)dz}});
         hs.write_mode = 4;
         struct G {
@@ -371,25 +432,27 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
     }
 
     std::vector<Offset> order;
-    if (!stencil_order(kind, false, offsets, n, order, err)) return LC_EINVAL;
+    if (!stencil_order(kind, false, offsets, n, order, err, reach)) return LC_EINVAL;
 
     if (kind == LC_SCHED_BLOCK8 || kind == LC_SCHED_ATOMIC_TILE || kind == LC_SCHED_BUFFER) {
         hs.write_mode = kind == LC_SCHED_BLOCK8 ? 0 : (kind == LC_SCHED_ATOMIC_TILE ? 1 : 3);
         std::vector<int> bs[3];
         for (int d = 0; d < 3; ++d)
-            bs[d] = (block_min && !coloured) ? axis_blocks_max(nc[d], bmin[d])
-                                             : axis_blocks(nc[d], bmin[d]);
+            // (uncoloured kinds at reach 2 default to blocks of at most
+            // 1 x 2 x 2: their footprints stay inside the work-group limits)
+            bs[d] = (!coloured && (block_min || reach == 2)) ? axis_blocks_max(nc[d], bmin[d])
+                                                             : axis_blocks(nc[d], bmin[d]);
         const int nb[3] = {(int)bs[0].size() - 1, (int)bs[1].size() - 1,
                            (int)bs[2].size() - 1};
         const int ncol[3] = {nb[0] > 1 ? 2 : 1, nb[1] > 1 ? 2 : 1, nb[2] > 1 ? 2 : 1};
         {
             // footprint extent per axis: the largest block plus the stencil
-            // reach (1 cell along +x, 1 on each side along y and z)
+            // reach (reach cells along +x, reach on each side along y and z)
             hs.compact = true;
             for (int d = 0; d < 3; ++d) {
                 int big = 0;
                 for (int b = 0; b < nb[d]; ++b) big = std::max(big, bs[d][b + 1] - bs[d][b]);
-                const int extent = big + (d == 0 ? 1 : 2);
+                const int extent = big + (d == 0 ? reach : 2 * reach);
                 if (2 * extent >= nc[d]) hs.compact = false;
             }
         }
@@ -447,8 +510,10 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
 
     if (kind == LC_SCHED_ATOMIC_PAIR) {
         hs.write_mode = 2;
-        // footprint of a home cell: 2 cells along x, 3 along y and z
-        hs.compact = 2 * 2 < nc[0] && 2 * 3 < nc[1] && 2 * 3 < nc[2];
+        // footprint of a home cell: 1 + reach cells along x, 1 + 2 reach
+        // along y and z
+        hs.compact = 2 * (1 + reach) < nc[0] && 2 * (1 + 2 * reach) < nc[1] &&
+                     2 * (1 + 2 * reach) < nc[2];
         std::vector<int32_t> A, B;
         basic_tasks(nc, order, A, B);
         const size_t per = order.size();
@@ -464,8 +529,9 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
     // Creation-order kinds: execute the DAG level by level.
     std::vector<int32_t> A, B;
     if (kind == LC_SCHED_LOOPEX) {
-        if (!loopex_tasks(nc, order, A, B)) {
-            err = "loop-exchange colouring needs even cell counts";
+        if (!loopex_tasks(nc, order, A, B, reach + 1)) {
+            err = reach == 1 ? "loop-exchange colouring needs even cell counts"
+                             : "loop-exchange colouring at reach 2 needs cell counts divisible by 3";
             return LC_EINVAL;
         }
     } else {

@@ -19,11 +19,24 @@ struct Offset {
 // column.
 std::vector<Offset> half_stencil(bool two_d);
 
+// The 3D half shell of a stencil reaching `reach` cells (1 or 2; cells of side
+// >= rc / reach): the same construction as the reach-1 one above -- every
+// offset with dx > 0, those with dx = 0 and dz > 0, and those with dx = dz = 0
+// and dy < 0 -- so 13 offsets at reach 1 (the Fig. 3 set) and 62 at reach 2.
+std::vector<Offset> half_shell(int reach);
+
 // Stencil evaluation order (intra = (0,0,0) included) of a preset kind
 // (LC_SCHED_LEX/OPT/BEST/BAD/LOOPEX), or the caller's order for CUSTOM.
-// Returns false with `err` set when the order is not a valid half shell.
+// reach: the stencil's reach in cells (1, or 2 for cells of side >= rc/2;
+// at reach 2 the presets are the linear-index order of half_shell(2), and
+// OPT/BEST/BAD have none).  A CUSTOM order must be a complete half shell of
+// the same reach.  Returns false with `err` set when the order is not a valid
+// half shell.
 bool stencil_order(int kind, bool two_d, const int8_t *offsets, int n,
-                   std::vector<Offset> &order, std::string &err);
+                   std::vector<Offset> &order, std::string &err, int reach = 1);
+
+// The reach of a CUSTOM order: the largest offset component (1 or 2).
+int order_reach(const int8_t *offsets, int n);
 
 // Tasks (cellA, cellB) in creation order.
 //   basic:  for z, for y, for x: for each entry of `order`
@@ -31,8 +44,11 @@ bool stencil_order(int kind, bool two_d, const int8_t *offsets, int n,
 //           fastest): for each cell of that colour (x fastest)
 void basic_tasks(const int32_t dims[3], const std::vector<Offset> &order,
                  std::vector<int32_t> &A, std::vector<int32_t> &B);
+// Loop exchange colours cells with stride `stride` along each axis
+// (stride^D colours; stride = reach + 1 keeps a colour's tasks of one offset
+// disjoint); every cell count must be a multiple of the stride.
 bool loopex_tasks(const int32_t dims[3], const std::vector<Offset> &order,
-                  std::vector<int32_t> &A, std::vector<int32_t> &B);
+                  std::vector<int32_t> &A, std::vector<int32_t> &B, int stride = 2);
 
 // DAG level of every task under the inout rule, by the last-writer
 // recurrence: level[t] = 1 + max(last[A_t], last[B_t]), then both cells'
@@ -92,10 +108,11 @@ constexpr int kLevelGroupTasks = 16;
 // negative LC_E* code with `err` set.
 // block_min (may be NULL): smallest block per axis for the block kinds
 // (default {1, 2, 2}; at least 1 along x and 2 along y and z, the stencil's
-// reach on each side).
+// reach on each side).  reach: 1, or 2 on grids of cells of side >= rc/2
+// (no BLOCK8 there: its blocks would exceed the work-group limits).
 int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
                    int n, HostSchedule &hs, std::string &err,
-                   const int32_t *block_min = nullptr);
+                   const int32_t *block_min = nullptr, int reach = 1);
 
 // Every phase's work-groups write pairwise disjoint cells (required for
 // plain read-modify-write).  Returns true when valid.

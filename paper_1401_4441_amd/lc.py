@@ -40,7 +40,7 @@ class _Grid(ctypes.Structure):
                 ("rc", ctypes.c_double), ("skin", ctypes.c_double),
                 ("nc", ctypes.c_int32 * 3), ("ncell", ctypes.c_int32),
                 ("scale", ctypes.c_float * 3), ("rc2", ctypes.c_float),
-                ("ecut", ctypes.c_float), ("pad", ctypes.c_int32)]
+                ("ecut", ctypes.c_float), ("reach", ctypes.c_int32)]
 
 
 class _SchedInfo(ctypes.Structure):
@@ -146,12 +146,24 @@ def _p(t: torch.Tensor | None):
 
 # ---------------------------------------------------------------------------
 
+GRID_EVEN, GRID_HALF = 1, 2
+
+
 class Grid:
-    def __init__(self, box, rc: float, skin: float = 0.0, even: bool = False):
+    """Periodic cell grid.  half: cells of side >= (rc + skin) / 2, so the
+    stencil reaches two cells (fewer candidate pairs; schedules follow)."""
+
+    def __init__(self, box, rc: float, skin: float = 0.0, even: bool = False,
+                 half: bool = False):
         self._g = _Grid()
         b = (ctypes.c_double * 3)(*[float(x) for x in box])
+        flags = (GRID_EVEN if even else 0) | (GRID_HALF if half else 0)
         _chk(lib().lc_make_grid(ctypes.cast(b, P), float(rc), float(skin),
-                                1 if even else 0, ctypes.byref(self._g)))
+                                flags, ctypes.byref(self._g)))
+
+    @property
+    def reach(self) -> int:
+        return int(self._g.reach)
 
     @property
     def ptr(self):

@@ -42,10 +42,14 @@ def test_tune_box_pick_is_valid_and_exact(tmp_path, monkeypatch):
     assert t["trials"] and not t["fallback"]
     assert t["ms"] == min(x["ms"] for x in t["trials"] if not x["fallback"])
     assert {x["kind"] for x in t["trials"]} == {"block8", "buffer", "atomic_tile", "fullshell"}
+    # the cells of side rc/2 are among the grids tried (no block colouring there)
+    half = [x for x in t["trials"] if x["grid"].get("half")]
+    assert half and {x["kind"] for x in half} == {"buffer", "atomic_tile", "fullshell"}
     u = O.canonical(box.pos, box.L)
-    for rec in [t] + sorted(t["trials"], key=lambda x: x["ms"])[:3]:  # fallbacks are exact too
-        g = lc.Grid(box.L, box.rc, rec["grid"]["extra"], rec["grid"]["even"])
-        Fo, Eo, Wo, npo = O.forces_lc_fx(u, box.L, box.rc, g.nc)
+    Fo, Eo, Wo, npo = O.forces_lc_fx(u, box.L, box.rc, O.grid_dims(box.L, box.rc))
+    best_half = min(half, key=lambda x: x["ms"])
+    for rec in [t, best_half] + sorted(t["trials"], key=lambda x: x["ms"])[:3]:
+        g = autotune.make_grid(box.L, box.rc, rec["grid"])  # fallbacks are exact too
         F, ew, st = _forces(g, rec["kind"], tuple(rec["block"]), pos, box.n)
         assert st & lc.FLAG_OVERFLOW == 0 and (F == Fo).all() and ew == [Eo, Wo, npo], rec
         assert bool(st & lc.FLAG_FALLBACK) == rec["fallback"], rec
@@ -67,5 +71,19 @@ def test_tune_shape_on_a_skin_grid():
     assert t["ms"] == min(x["ms"] for x in t["trials"] if not x["fallback"])
     u = O.canonical(box.pos, box.L)
     Fo, Eo, Wo, npo = O.forces_lc_fx(u, box.L, box.rc, g.nc)
+    F, ew, st = _forces(g, t["kind"], tuple(t["block"]), pos, box.n)
+    assert st == 0 and (F == Fo).all() and ew == [Eo, Wo, npo]
+
+
+def test_tune_shape_on_half_cells():
+    box = synth.fcc(4000, 0.8, rc=2.5, seed=1002)
+    pos = torch.from_numpy(box.pos).to(DEV)
+    g = lc.Grid(box.L, box.rc, half=True)
+    _say("tune_shape half cells", g.nc)
+    t = autotune.tune_shape(g, pos, kinds=("buffer", "atomic_tile"), reps=2)
+    assert t["kind"] in ("buffer", "atomic_tile") and not t["fallback"]
+    assert {tuple(x["block"]) for x in t["trials"]} <= set(autotune.BLOCKS["uncoloured_half"])
+    u = O.canonical(box.pos, box.L)
+    Fo, Eo, Wo, npo = O.forces_lc_fx(u, box.L, box.rc, O.grid_dims(box.L, box.rc))
     F, ew, st = _forces(g, t["kind"], tuple(t["block"]), pos, box.n)
     assert st == 0 and (F == Fo).all() and ew == [Eo, Wo, npo]

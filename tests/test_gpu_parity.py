@@ -30,9 +30,9 @@ def _say(*a):
 
 
 class Setup:
-    def __init__(self, box, skin=0.0, even=False):
+    def __init__(self, box, skin=0.0, even=False, half=False):
         self.box = box
-        self.g = lc.Grid(box.L, box.rc, skin, even)
+        self.g = lc.Grid(box.L, box.rc, skin, even, half=half)
         self.ws = lc.Workspace(box.n, self.g.ncell)
         self.pos = torch.from_numpy(box.pos).to(DEV)
         self.cs, self.perm, self.coord = lc.build_cells(self.g, self.pos, self.ws)
@@ -45,8 +45,8 @@ class Setup:
         out[:, self.perm_h] = Fh
         return out
 
-    def forces(self, kind, precision="fp32", block=None):
-        s = lc.Schedule(self.g, kind, block=block)
+    def forces(self, kind, precision="fp32", block=None, offsets=None):
+        s = lc.Schedule(self.g, kind, offsets=offsets, block=block)
         self.ws.clear_status()
         F, ew = lc.compute_forces(self.g, s, self.cs, self.coord, self.ws, precision)
         torch.cuda.synchronize()
@@ -263,3 +263,48 @@ def test_displacement_flag():
     vel = synth.maxwell_boltzmann(box.n, 1.0, seed=15)
     _, _, _, st = _verlet_gpu(box, vel, 0.005, 120, 1000, 0.1)
     assert st & lc.FLAG_DISP
+
+
+def _half_shell2():
+    r = range(-2, 3)
+    return [(x, y, z) for z in r for y in r for x in r
+            if x > 0 or (x == 0 and z > 0) or (x == 0 and z == 0 and y < 0)]
+
+
+def test_half_cells_bit_exact():
+    """Cells of side rc/2 (13^3, reach-2 stencil of 62 offsets + intra): every
+    schedule kind defined there gives the bits of the oracle's rc-cell sweep
+    (the pair set does not depend on the cell size)."""
+    box = synth.fcc(4000, 0.8, rc=2.5, seed=41)
+    S = Setup(box, half=True)
+    assert S.g.nc == (13, 13, 13) and S.g.reach == 2
+    Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, O.grid_dims(box.L, box.rc))
+    order = [O.INTRA] + [tuple(-c for c in d) for d in _half_shell2()][::-1]
+    cases = [("buffer", None, None), ("buffer", (1, 1, 1), None), ("buffer", (2, 1, 1), None),
+             ("atomic_tile", None, None), ("atomic_pair", None, None),
+             ("fullshell", None, None), ("lex", None, None), ("custom", None, order)]
+    for kind, block, offs in cases:
+        _say("half", kind, block)
+        F, ew, st = S.forces(kind, block=block, offsets=offs)
+        assert st & lc.FLAG_OVERFLOW == 0
+        assert (F == Fo).all() and ew == [Eo, Wo, npo], (kind, block)
+    for mode in ("ordered", "nested"):
+        _say("half dataflow", mode)
+        s = lc.Schedule(S.g, "lex")
+        S.ws.clear_status()
+        F, ew = lc.compute_forces_dataflow(S.g, s, S.cs, S.coord, S.ws, mode)
+        torch.cuda.synchronize()
+        assert S.ws.status() == 0
+        assert (S.unsort(F) == Fo).all() and [int(x) for x in ew.cpu()] == [Eo, Wo, npo], mode
+
+
+def test_half_cells_loopex_27_colours():
+    """Loop exchange at reach 2 colours cells with stride 3 (27 colours): a
+    12^3 half-cell grid, level by level, bit-exact."""
+    box = synth.fcc(3000, 0.8, rc=2.5, seed=42)
+    S = Setup(box, half=True)
+    assert S.g.nc == (12, 12, 12)
+    Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, O.grid_dims(box.L, box.rc))
+    F, ew, st = S.forces("loopex")
+    assert st & lc.FLAG_OVERFLOW == 0
+    assert (F == Fo).all() and ew == [Eo, Wo, npo]

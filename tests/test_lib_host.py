@@ -196,3 +196,72 @@ def test_weighted_cp_matches_oracle():
         _, cp = O.dag_lc_weighted(A, B, w)
         assert r["cp"] == pytest.approx(cp)
         assert r["work"] == pytest.approx(w.sum())
+
+
+# ---- cells of side rc/2: the stencil reaches two cells ----------------------
+
+def _half_shell2():
+    """The reach-2 half shell, built here from its definition (every offset
+    in [-2, 2]^3 with dx > 0, or dx = 0 and dz > 0, or dx = dz = 0 and
+    dy < 0), independently of the library's construction."""
+    r = range(-2, 3)
+    return [(x, y, z) for z in r for y in r for x in r
+            if x > 0 or (x == 0 and z > 0) or (x == 0 and z == 0 and y < 0)]
+
+
+def test_half_shell2_is_a_half_shell():
+    h = _half_shell2()
+    assert len(h) == 62 and len(set(h)) == 62
+    full = {d for d in itertools.product(range(-2, 3), repeat=3) if d != (0, 0, 0)}
+    assert {d for d in h} | {tuple(-c for c in d) for d in h} == full
+
+
+def test_half_grid_dims():
+    g = lc.Grid((17.0998,) * 3, 2.5, half=True)
+    assert g.reach == 2 and lc.Grid((17.0998,) * 3, 2.5).reach == 1
+    # two cells cover rc with the FP32 margin: floor(2 L / (rc (1 + 2^-12)))
+    assert g.nc == (13, 13, 13)
+    assert lc.Grid((17.0998,) * 3, 2.5, 0.6, half=True).nc == (11, 11, 11)
+    with pytest.raises(lc.LCError):
+        lc.Grid((6.0, 20, 20), 2.5, half=True)  # 4 cells: a +-2 stencil wraps
+
+
+def test_half_grid_plans():
+    g = lc.Grid((17.0998,) * 3, 2.5, half=True)
+    n = g.ncell
+    for kind, per_cell in (("buffer", 63), ("atomic_tile", 63), ("atomic_pair", 63),
+                           ("fullshell", 125), ("lex", 63)):
+        info = lc.schedule_plan(g, kind)
+        assert info["ntask"] == per_cell * n, kind
+        assert info["max_group_tasks"] <= 512 and info["max_group_cells"] <= 128, kind
+    assert lc.schedule_plan(g, "lex")["nphase"] == lc.serialization_degree(
+        g.nc, "custom", offsets=[O.INTRA] + sorted(_half_shell2(), key=lambda d: (d[2], d[1], d[0])))["cp"]
+    for kind in ("block8", "opt", "best", "bad"):
+        with pytest.raises(lc.LCError):
+            lc.schedule_plan(g, kind)
+    with pytest.raises(lc.LCError):  # 13 cells: no stride-3 colouring
+        lc.schedule_plan(g, "loopex")
+    g12 = lc.Grid((15.6,) * 3, 2.5, half=True)
+    assert g12.nc == (12, 12, 12)
+    info = lc.schedule_plan(g12, "loopex")  # 27 colours x 63 offsets, levels validated
+    assert info["ntask"] == 63 * g12.ncell and info["nphase"] <= 27 * 63
+    # a reach-1 order on a reach-2 grid (or the reverse) is refused
+    with pytest.raises(lc.LCError):
+        lc.schedule_plan(g, "custom", offsets=O.ORDER3_LEX)
+    with pytest.raises(lc.LCError):
+        lc.schedule_plan(lc.Grid((17.0998,) * 3, 2.5), "custom",
+                         offsets=[O.INTRA] + _half_shell2())
+
+
+def test_reach2_cp_matches_oracle():
+    """The critical path of a reach-2 creation order (library recurrence vs
+    the oracle's task list and DAG)."""
+    order = [O.INTRA] + sorted(_half_shell2(), key=lambda d: (d[2], d[1], d[0]))
+    rev = [O.INTRA] + [tuple(-c for c in d) for d in order[1:]][::-1]
+    for dims in ((5, 5, 5), (6, 5, 7)):
+        for o in (order, rev):
+            r = lc.serialization_degree(dims, "custom", offsets=o)
+            want = O.serialization_degree(dims, o)
+            assert (r["tasks"], r["cp"]) == (want["T"], want["cp"])
+    with pytest.raises(lc.LCError):  # not a complete reach-2 half shell
+        lc.serialization_degree((5, 5, 5), "custom", offsets=order[:-1])
