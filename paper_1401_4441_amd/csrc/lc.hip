@@ -6,14 +6,19 @@
 //   k_bin                   cell of each particle + atomic rank in its cell
 //   k_scan_*                exclusive scan of per-cell counts -> cell_start
 //   k_scatter               counting-sort scatter: perm + sorted box fractions
-//   k_sweep<CAP,WMODE,F64>  one phase of cell-cell tasks (Sec. IV): per
+//   k_sweep<CAP,WMODE,F64,FF>  one phase of cell-cell tasks (Sec. IV): per
 //                           work-group a group of tasks whose footprint cells
 //                           are staged in LDS; lanes own j particles, loop over
 //                           i; in-cutoff pairs are compacted into a per-wave
-//                           queue and evaluated 64 at a time; int64 forces
+//                           queue and evaluated in full waves; int64 forces
 //                           accumulate in LDS and are written back with plain
-//                           read-modify-write (conflict-free phase) or global
-//                           atomics
+//                           read-modify-write (conflict-free phase), into
+//                           replica slots (buffer + reduce), home particles
+//                           only (full shell) or with global atomics
+//   k_gather_partials       buffer + reduce: sum each particle's replicas
+//   k_dataflow<MODE>        creation-order executors (ordered / mutex /
+//                           nested), one wave per task runner
+//   k_selftest_recip        the fast reciprocal against IEEE division
 //   k_kick_drift / k_kick_ke  velocity Verlet halves (FP64)
 //   k_gather                reorder SoA rows by a permutation
 #include <hip/hip_runtime.h>
@@ -649,13 +654,15 @@ __device__ __forceinline__ int foot_cell(const L &sh, int nf, int l) {
 //   STAGED: the footprint's box fractions and accumulators live in LDS;
 //           otherwise box fractions come from global memory and every pair
 //           adds into F with global atomics.
-//   FF:     the candidate test uses the float tile (group-relative
-//           coordinates) against a slightly enlarged cutoff; the exact
-//           canonical test is repeated when the pair is evaluated.
+//   FF:     candidates first pass a 16-bit integer filter (the top halves of
+//           the box fractions against an enlarged cutoff, see
+//           filter16_bound); the exact canonical test is repeated when the
+//           pair is evaluated.
 // Lanes own j slots (64 consecutive slots of the concatenated B cells of the
 // group's tasks) and loop over the i particles of their task's cell A;
 // pairs inside the cutoff are compacted into a per-wave queue and evaluated
-// 64 at a time, so the Lennard-Jones arithmetic runs on full waves.
+// 128 at a time (two full-wave batches), so the Lennard-Jones arithmetic
+// runs on full waves.
 template <int CAP, int WMODE, bool F64, bool STAGED, bool FF>
 __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const SweepArgs &a,
                                             const PairParams &pp, int f0, int nf, int nt,
