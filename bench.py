@@ -47,7 +47,7 @@ WORKLOADS = {
     "fcc4m": dict(n=4_000_000, rho=0.8, rc=2.5, seed=1003,
                   desc="LJ FCC+jitter N=4000000 rho=0.8 rc=2.5 periodic cube"),
 }
-EXTRA_WORKLOADS = ("fcc4m_md", "slab2m", "boxes512")
+EXTRA_WORKLOADS = ("fcc4m_md", "slab2m", "boxes512", "lj2d_1m")
 
 H3 = ([(1, a, b) for b in (-1, 0, 1) for a in (-1, 0, 1)]
       + [(0, a, 1) for a in (-1, 0, 1)] + [(0, -1, 0)])
@@ -150,6 +150,8 @@ def main():
         return bench_slab(args)
     if args.workload == "boxes512":
         return bench_boxes(args)
+    if args.workload == "lj2d_1m":
+        return bench_2d(args)
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     box = synth.fcc(w["n"], w["rho"], rc=w["rc"], seed=w["seed"])
@@ -519,6 +521,63 @@ def bench_slab(args):
                               "empty_frac": float((counts == 0).mean())}},
           schedules={k: (dict(v, pairs_per_s=pairs / (v["ms"] * 1e-3)) if "ms" in v else v)
                      for k, v in res.items()})
+
+
+def bench_2d(args):
+    """A flat (2D) LJ system, 1M particles at areal density 0.7, rc = 2.5, on
+    the 2D stencil (Fig. 3a): the autotuned conflict-free sweep against the
+    atomics and full-shell baselines, and the paper's 2D creation orders
+    (Fig. 5: naive, bad, optimal; loop exchange) run level by level on a
+    64k-particle flat box, beside their exact critical paths."""
+    import torch
+    from paper_1401_4441_amd import autotune, lc, synth
+    box = synth.workload("lj2d_1m")
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(box.pos).to(dev)
+    g = lc.Grid(box.L, box.rc, flat=True)
+    tune = autotune.tune_shape(g, pos, kinds=("block8", "buffer", "atomic_tile", "fullshell"),
+                               reps=5)
+    ws = lc.Workspace(box.n, g.ncell)
+    cs, perm, coord = lc.build_cells(g, pos, ws)
+    F = torch.empty((3, box.n), dtype=torch.int64, device=dev)
+    ew = torch.empty(3, dtype=torch.int64, device=dev)
+    res = {}
+    for kind in ("buffer", "block8", "atomic_tile", "fullshell", "atomic_pair"):
+        tr = [t for t in tune["trials"] if t["kind"] == kind and not t["fallback"]]
+        blk = tuple(min(tr, key=lambda t: t["ms"])["block"]) if tr else None
+        s = lc.Schedule(g, kind, block=blk)
+        ws.clear_status()
+        ms = _time_evals(lambda: lc.compute_forces(g, s, cs, coord, ws, "fp32", F, ew),
+                         max(args.steps // 5, 3), 2)
+        res[kind] = {"ms": ms, "block": list(blk) if blk else None, "phases": s.info()["nphase"],
+                     "status_flags": ws.status()}
+        s.close()
+    pairs = int(ew[2].item())
+    best = min(("buffer", "block8"), key=lambda k: res[k]["ms"])
+    # the paper's 2D orders on a smaller flat box (one launch per DAG level)
+    small = synth.square2d(65536, 0.7, rc=2.5, seed=1007)
+    gs = lc.Grid(small.L, small.rc, even=True, flat=True)
+    wss = lc.Workspace(small.n, gs.ncell)
+    ps = torch.from_numpy(small.pos).to(dev)
+    css, _, cos = lc.build_cells(gs, ps, wss)
+    orders = {}
+    for kind in ("lex", "bad", "opt", "loopex"):
+        s = lc.Schedule(gs, kind)
+        ms = _time_evals(lambda: lc.compute_forces(gs, s, css, cos, wss), 2, 1)
+        sd = lc.serialization_degree(gs.nc, kind)
+        orders[kind] = {"levels": s.info()["nphase"], "cp": sd["cp"], "S": sd["speedup"],
+                        "delta": sd["delta"], "ms": ms}
+        s.close()
+    _line("pair interactions/sec (LJ cell-pair force sweep, flat 2D system)",
+          pairs / (res[best]["ms"] * 1e-3), "pairs/s", res[best]["ms"], args,
+          {"workload": "flat LJ N=1000000, square lattice + jitter, areal density 0.7, rc=2.5",
+           "cells": list(g.nc), "schedule": best, "block": res[best]["block"],
+           "pairs_in_cutoff": pairs},
+          schedules={k: dict(v, pairs_per_s=pairs / (v["ms"] * 1e-3)) for k, v in res.items()},
+          conflict_free_vs_atomics={
+              "speedup_over_atomic_pair": res["atomic_pair"]["ms"] / res[best]["ms"],
+              "speedup_over_full_shell": res["fullshell"]["ms"] / res[best]["ms"]},
+          paper_orders_2d={"n": small.n, "cells": list(gs.nc), "orders": orders})
 
 
 def bench_boxes(args):

@@ -82,6 +82,9 @@ const char *lc_last_error(void);
 #define LC_GRID_HALF 2 /* cells of side >= (rc + skin) / 2: the stencil
                           reaches 2 cells (Sec. IV takes side >= rc; the
                           half-size cells visit fewer candidate pairs)       */
+#define LC_GRID_2D 4   /* a flat system: one cell along z (every particle
+                          at the same z); schedules use the 2D stencil of
+                          Fig. 3a and the 2D orders of Fig. 5               */
 
 /* Periodic cell grid (Sec. IV: cells of side >= rc).  Filled by
  * lc_make_grid; plain data, may be copied. */
@@ -103,7 +106,9 @@ typedef struct lc_grid {
  * r2 cannot cross; with LC_GRID_HALF, floor(2 L_d / (...)) (two cells cover
  * it, reach 2).  flags: LC_GRID_EVEN | LC_GRID_HALF.  Returns LC_EINVAL when
  * an axis gets fewer than 2 reach + 1 cells (pairs would be visited twice) or
- * ncell >= 2^31.  Schedules and sweeps follow the grid's reach; at reach 2
+ * ncell >= 2^31.  With LC_GRID_2D the z axis keeps one cell (box[2] only has
+ * to be positive; the particles must share one z) and the x, y rules apply;
+ * it cannot be combined with LC_GRID_HALF.  Schedules and sweeps follow the grid's reach; at reach 2
  * there is no LC_SCHED_BLOCK8 (LC_SCHED_LOOPEX colours with stride 3 and
  * needs cell counts divisible by 3), the presets OPT/BEST/BAD are not defined
  * (pass the order as LC_SCHED_CUSTOM offsets in [-2, 2]), and batches take

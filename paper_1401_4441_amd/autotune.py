@@ -34,10 +34,15 @@ BLOCKS = {"block8": ((1, 2, 2), (2, 2, 2), (1, 3, 3), (2, 3, 3)),
                          (1, 4, 4), (2, 3, 3)),
           # cells of side rc/2: the reach-2 footprint of a block (bx + 2) x
           # (by + 4) x (bz + 4) must stay within 128 cells
-          "uncoloured_half": ((1, 1, 1), (1, 1, 2), (2, 1, 1), (1, 2, 2), (1, 2, 3))}
+          "uncoloured_half": ((1, 1, 1), (1, 1, 2), (2, 1, 1), (1, 2, 2), (1, 2, 3)),
+          # flat (2D) grids: one cell along z; a block's footprint is about
+          # (bx + 1) x (by + 2) cells
+          "flat": ((2, 4, 1), (4, 4, 1), (4, 8, 1), (8, 8, 1), (6, 12, 1), (8, 12, 1))}
 
 
-def shapes_for(kind: str, half: bool = False):
+def shapes_for(kind: str, half: bool = False, flat: bool = False):
+    if flat:
+        return BLOCKS["flat"]
     if kind == "block8":
         return BLOCKS["block8"]
     return BLOCKS["uncoloured_half"] if half else BLOCKS["uncoloured"]
@@ -146,7 +151,7 @@ def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
             s0.close()
             warmed = True
         for kind in kinds:
-            for block in shapes_for(kind, grid.reach == 2):
+            for block in shapes_for(kind, grid.reach == 2, grid.nc[2] == 1):
                 try:
                     sched = lc.Schedule(grid, kind, block=block)
                 except lc.LCError:
@@ -187,7 +192,7 @@ def tune_shape(grid, pos: torch.Tensor, kinds=BOX_KINDS_CONFLICT_FREE, reps: int
     s0.close()
     trials, best = [], None
     for kind in kinds:
-        for block in shapes_for(kind, grid.reach == 2):
+        for block in shapes_for(kind, grid.reach == 2, grid.nc[2] == 1):
             try:
                 sched = lc.Schedule(grid, kind, block=block)
             except lc.LCError:

@@ -1604,9 +1604,11 @@ static int launch_sweep(int cap, int wmode, bool f64, bool ff, const SweepArgs &
 // bound uses rc slightly enlarged (the canonical FP32 r2 may round below the
 // exact one) and +2 units.  0: the filter is not used (axes whose units
 // differ by more than 25% would make the superset needlessly wide).
-static int filter16_bound(const double box[3], float rc2) {
-    const double umin = std::min(box[0], std::min(box[1], box[2])) / 65536.0;
-    const double umax = std::max(box[0], std::max(box[1], box[2])) / 65536.0;
+static int filter16_bound(const double box[3], float rc2, bool flat = false) {
+    // a flat system's z differences are all zero: only x and y set the units
+    const double bz = flat ? box[0] : box[2];
+    const double umin = std::min(box[0], std::min(box[1], bz)) / 65536.0;
+    const double umax = std::max(box[0], std::max(box[1], bz)) / 65536.0;
     if (!(umin > 0.0) || umax > 1.25 * umin) return 0;
     const double ru = std::sqrt((double)rc2) * (1.0 + 1e-5) / umin + 2.0;
     const double t = std::ceil(ru * ru) + 1.0;
@@ -1620,7 +1622,7 @@ static PairParams pair_params(const lc_grid *g) {
         p.sd[d] = g->box[d] / 4294967296.0;
     }
     p.rc2 = g->rc2;
-    p.thr16 = filter16_bound(g->box, g->rc2);
+    p.thr16 = filter16_bound(g->box, g->rc2, g->nc[2] == 1);
     p.ecut = g->ecut;
     p.rc2d = g->rc * g->rc;
     const double ic = 1.0 / p.rc2d;
@@ -1826,6 +1828,9 @@ extern "C" int lc_make_grid(const double box[3], double rc, double skin, int fla
                             lc_grid *out) {
     if (!box || !out) return fail(LC_EINVAL, "lc_make_grid: null argument");
     if (!(rc > 0.0) || !(skin >= 0.0)) return fail(LC_EINVAL, "lc_make_grid: rc/skin");
+    const bool flat = (flags & LC_GRID_2D) != 0;
+    if (flat && (flags & LC_GRID_HALF))
+        return fail(LC_EINVAL, "lc_make_grid: LC_GRID_2D with LC_GRID_HALF");
     lc_grid g;
     memset(&g, 0, sizeof g);
     int64_t ncell = 1;
@@ -1839,7 +1844,8 @@ extern "C" int lc_make_grid(const double box[3], double rc, double skin, int fla
         if (!(q < 2147483647.0)) return fail(LC_EINVAL, "lc_make_grid: too many cells");
         int64_t k = (int64_t)q;
         if ((flags & LC_GRID_EVEN) && (k & 1)) k -= 1;
-        if (k < 2 * reach + 1)
+        if (flat && d == 2) k = 1;  // the flat axis: one cell
+        else if (k < 2 * reach + 1)
             return fail(LC_EINVAL, "lc_make_grid: axis %d gets %lld cells (< %d)", d, (long long)k,
                         2 * reach + 1);
         g.nc[d] = (int32_t)k;

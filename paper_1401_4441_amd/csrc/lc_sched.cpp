@@ -143,7 +143,11 @@ bool stencil_order(int kind, bool two_d, const int8_t *offsets, int n,
         const Offset bl = mk(0, -1, 0), lr = mk(1, -1, 0), ur = mk(1, 1, 0);
         switch (kind) {
             case LC_SCHED_LEX:  // Fig. 5(a)
-            case LC_SCHED_LOOPEX: order = {intra, bl, lr, ex, ur}; return true;
+            case LC_SCHED_LOOPEX:
+            case LC_SCHED_BLOCK8:
+            case LC_SCHED_ATOMIC_TILE:
+            case LC_SCHED_ATOMIC_PAIR:
+            case LC_SCHED_BUFFER: order = {intra, bl, lr, ex, ur}; return true;
             case LC_SCHED_BAD: order = {intra, bl, lr, ur, ex}; return true;   // 5(b)
             case LC_SCHED_OPT: order = {ex, lr, ur, bl, intra}; return true;   // 5(c)
             case LC_SCHED_BEST: order = {intra, ex, lr, ur, bl}; return true;
@@ -350,6 +354,12 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
         err = "stencil reach must be 1 or 2";
         return LC_EINVAL;
     }
+    // a flat grid (one cell along z): the 2D stencil and orders
+    const bool flat = nc[2] == 1;
+    if (flat && reach != 1) {
+        err = "flat grids take the reach-1 2D stencil";
+        return LC_EINVAL;
+    }
     if (reach == 2 && kind == LC_SCHED_BLOCK8) {
         err = "no 2x2x2 block colouring at reach 2 (use buffer, atomic_tile or loopex)";
         return LC_EINVAL;
@@ -366,7 +376,8 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
     if (block_min) {
         for (int d = 0; d < 3; ++d) bmin[d] = block_min[d];
         const int lo_yz = coloured ? 2 : 1;
-        if (bmin[0] < 1 || bmin[1] < lo_yz || bmin[2] < lo_yz || bmin[0] > 64 ||
+        const int lo_z = flat ? 1 : lo_yz;  // a flat grid's z axis is one cell
+        if (bmin[0] < 1 || bmin[1] < lo_yz || bmin[2] < lo_z || bmin[0] > 64 ||
             bmin[1] > 64 || bmin[2] > 64) {
             err = coloured ? "block sizes must be >= {1, 2, 2} (the stencil reach) and <= 64"
                            : "block sizes must be >= 1 and <= 64";
@@ -391,7 +402,8 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
         std::vector<int> bs[3];
         for (int d = 0; d < 3; ++d) bs[d] = axis_blocks_max(nc[d], sz[d]);
         std::vector<Offset> shell(1, Offset{{0, 0, 0}});
-        for (int dz = -reach; dz <= reach; ++dz)
+        const int rz = flat ? 0 : reach;
+        for (int dz = -rz; dz <= rz; ++dz)
             for (int dy = -reach; dy <= reach; ++dy)
                 for (int dx = -reach; dx <= reach; ++dx)
                     if (dx || dy || dz) shell.push_back(Offset{{(int8_t)dx, (int8_t)dy, (int8_t)dz}});
@@ -432,7 +444,7 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
     }
 
     std::vector<Offset> order;
-    if (!stencil_order(kind, false, offsets, n, order, err, reach)) return LC_EINVAL;
+    if (!stencil_order(kind, flat, offsets, n, order, err, reach)) return LC_EINVAL;
 
     if (kind == LC_SCHED_BLOCK8 || kind == LC_SCHED_ATOMIC_TILE || kind == LC_SCHED_BUFFER) {
         hs.write_mode = kind == LC_SCHED_BLOCK8 ? 0 : (kind == LC_SCHED_ATOMIC_TILE ? 1 : 3);

@@ -146,18 +146,21 @@ def _p(t: torch.Tensor | None):
 
 # ---------------------------------------------------------------------------
 
-GRID_EVEN, GRID_HALF = 1, 2
+GRID_EVEN, GRID_HALF, GRID_2D = 1, 2, 4
 
 
 class Grid:
     """Periodic cell grid.  half: cells of side >= (rc + skin) / 2, so the
-    stencil reaches two cells (fewer candidate pairs; schedules follow)."""
+    stencil reaches two cells (fewer candidate pairs; schedules follow).
+    flat: a 2D system (all particles at one z), one cell along z, the 2D
+    stencil and orders."""
 
     def __init__(self, box, rc: float, skin: float = 0.0, even: bool = False,
-                 half: bool = False):
+                 half: bool = False, flat: bool = False):
         self._g = _Grid()
         b = (ctypes.c_double * 3)(*[float(x) for x in box])
-        flags = (GRID_EVEN if even else 0) | (GRID_HALF if half else 0)
+        flags = (GRID_EVEN if even else 0) | (GRID_HALF if half else 0) | \
+            (GRID_2D if flat else 0)
         _chk(lib().lc_make_grid(ctypes.cast(b, P), float(rc), float(skin),
                                 flags, ctypes.byref(self._g)))
 

@@ -12,6 +12,7 @@ Lennard-Jones systems in reduced units (epsilon = sigma = mass = k_B = 1):
 * ``fcc``      -- face-centred cubic crystal with uniform jitter, periodic cube;
 * ``slab``     -- dense FCC slab (middle third along z) in a dilute FCC gas;
 * ``boxes``    -- many independent periodic boxes of uneven size and density;
+* ``square2d`` -- a flat (2D) square lattice with jitter, all particles at z = 0;
 * ``maxwell_boltzmann`` -- seeded thermal velocities at a target temperature.
 
 All positions are returned as float64 arrays of shape ``(3, N)`` (SoA, one
@@ -86,6 +87,37 @@ def fcc(n: int, density: float, rc: float = 2.5, jitter: float = 0.05,
     pos = _wrap(np.ascontiguousarray(sites.T), Lv)
     return Box(pos=np.ascontiguousarray(pos), L=Lv, rc=rc, seed=seed,
                meta={"kind": "fcc", "density": density, "a": a, "m": m,
+                     "jitter": jitter})
+
+
+def square2d(n: int, density: float, rc: float = 2.5, jitter: float = 0.05,
+             seed: int = 1234) -> Box:
+    """A flat (2D) system: ``n`` particles on a square lattice at areal
+    ``density`` with uniform jitter in x and y, all at z = 0.
+
+    When ``n`` is not m^2 a seeded random subset of the m = ceil(sqrt(n))
+    lattice is kept.  The box is L x L in the plane; its z edge (4 rc) only
+    has to be positive, since every z difference is zero.
+    """
+    rng = np.random.default_rng(seed)
+    L = math.sqrt(n / density)
+    m = math.isqrt(n)
+    if m * m != n:
+        m = math.ceil(math.sqrt(n))
+    a = L / m
+    g = np.arange(m, dtype=np.float64)
+    cy, cx = np.meshgrid(g, g, indexing="ij")
+    sites = np.stack([cx.ravel(), cy.ravel()], axis=1) * a
+    if sites.shape[0] != n:
+        keep = np.sort(rng.choice(sites.shape[0], size=n, replace=False))
+        sites = sites[keep]
+    sites = sites + rng.uniform(-jitter, jitter, size=sites.shape)
+    Lv = np.array([L, L, 4.0 * rc])
+    pos = np.zeros((3, n))
+    pos[:2] = sites.T
+    pos = _wrap(pos, Lv)
+    return Box(pos=np.ascontiguousarray(pos), L=Lv, rc=rc, seed=seed,
+               meta={"kind": "square2d", "density": density, "a": a, "m": m,
                      "jitter": jitter})
 
 
@@ -166,4 +198,6 @@ def workload(name: str) -> Box:
         return b
     if name == "slab2m":
         return slab(2_000_000, seed=1005)
+    if name == "lj2d_1m":
+        return square2d(1_000_000, 0.7, rc=2.5, seed=1006)
     raise KeyError(name)

@@ -30,9 +30,9 @@ def _say(*a):
 
 
 class Setup:
-    def __init__(self, box, skin=0.0, even=False, half=False):
+    def __init__(self, box, skin=0.0, even=False, half=False, flat=False):
         self.box = box
-        self.g = lc.Grid(box.L, box.rc, skin, even, half=half)
+        self.g = lc.Grid(box.L, box.rc, skin, even, half=half, flat=flat)
         self.ws = lc.Workspace(box.n, self.g.ncell)
         self.pos = torch.from_numpy(box.pos).to(DEV)
         self.cs, self.perm, self.coord = lc.build_cells(self.g, self.pos, self.ws)
@@ -308,3 +308,22 @@ def test_half_cells_loopex_27_colours():
     F, ew, st = S.forces("loopex")
     assert st & lc.FLAG_OVERFLOW == 0
     assert (F == Fo).all() and ew == [Eo, Wo, npo]
+
+
+def test_flat_2d_bit_exact():
+    """A flat LJ system (square lattice with jitter, all particles at z = 0)
+    on a 26 x 26 x 1 grid: the 2D stencil, every schedule kind and the
+    paper's 2D orders, bit-exact against the oracle's brute force."""
+    box = synth.square2d(3000, 0.7, rc=2.5, seed=43)
+    S = Setup(box, flat=True)
+    assert S.g.nc == (26, 26, 1)
+    Fo, Eo, Wo, npo = O.forces_brute_fx(S.u, box.L, box.rc)
+    assert npo > 15000
+    cases = [("block8", (4, 4, 1)), ("block8", None), ("buffer", (8, 8, 1)), ("buffer", None),
+             ("atomic_tile", (4, 8, 1)), ("atomic_pair", None), ("fullshell", (4, 4, 1)),
+             ("lex", None), ("opt", None), ("bad", None), ("loopex", None)]
+    for kind, block in cases:
+        _say("flat", kind, block)
+        F, ew, st = S.forces(kind, block=block)
+        assert st & lc.FLAG_OVERFLOW == 0
+        assert (F == Fo).all() and ew == [Eo, Wo, npo], (kind, block)

@@ -265,3 +265,31 @@ def test_reach2_cp_matches_oracle():
             assert (r["tasks"], r["cp"]) == (want["T"], want["cp"])
     with pytest.raises(lc.LCError):  # not a complete reach-2 half shell
         lc.serialization_degree((5, 5, 5), "custom", offsets=order[:-1])
+
+
+# ---- flat (2D) systems: one cell along z, the Fig. 3a stencil ---------------
+
+def test_flat_grid_plans_follow_the_2d_closed_forms():
+    """On a flat grid the creation orders are the 2D ones of Fig. 5: their
+    level counts are the periodic closed forms (naive (4Nx+1)Ny, bad
+    (5Nx-1)Ny+1, opt (Nx+2)Ny+2), loop exchange has 2n - 1 = 9 levels, and
+    the tile kinds cover each of the 5 stencil entries per cell once."""
+    g = lc.Grid((65.465, 65.465, 10.0), 2.5, flat=True)
+    nx, ny, nz = g.nc
+    assert (nx, ny, nz) == (26, 26, 1)
+    assert lc.schedule_plan(g, "lex")["nphase"] == (4 * nx + 1) * ny
+    assert lc.schedule_plan(g, "bad")["nphase"] == (5 * nx - 1) * ny + 1
+    assert lc.schedule_plan(g, "opt")["nphase"] == (nx + 2) * ny + 2
+    assert lc.schedule_plan(g, "loopex")["nphase"] == 9
+    info = lc.schedule_plan(g, "block8", block=(4, 4, 1))
+    assert info["nphase"] == 4 and info["ntask"] == 5 * g.ncell
+    for kind in ("buffer", "atomic_tile", "atomic_pair"):
+        assert lc.schedule_plan(g, kind)["ntask"] == 5 * g.ncell, kind
+    assert lc.schedule_plan(g, "fullshell")["ntask"] == 9 * g.ncell
+    # blocks of at most 8 x 12: 26 = 7+7+6+6 along x, 9+9+8 along y; the
+    # largest, 7 x 9, reaches (7 + 1) x (9 + 2) cells but one corner (no
+    # (0, +1) offset in the half stencil)
+    info = lc.schedule_plan(g, "buffer", block=(8, 12, 1))
+    assert info["max_group_cells"] == 8 * 11 - 1 and info["max_group_tasks"] == 5 * 7 * 9
+    with pytest.raises(lc.LCError):
+        lc.Grid((65.465, 65.465, 10.0), 2.5, half=True, flat=True)
