@@ -493,7 +493,21 @@ def bench_slab(args):
         s.close()
     pairs = int(ew[2].item())
     counts = (cs[1:] - cs[:-1]).cpu().numpy()
-    best = min((k for k in ("buffer", "block8") if "ms" in res[k]), key=lambda k: res[k]["ms"])
+    # load-aware launch order (groups heaviest first by n_A n_B) for the
+    # conflict-free kinds: the dense slab's groups start first
+    cc = lc.cell_counts_of(cs)
+    for kind in ("buffer", "block8"):
+        if "ms" not in res[kind]:
+            continue
+        blk = tuple(res[kind]["block"]) if res[kind]["block"] else None
+        s = lc.Schedule(g, kind, block=blk, cell_counts=cc)
+        ms = _time_evals(lambda: lc.compute_forces(g, s, cs, coord, ws, "fp32", F, ew),
+                         max(args.steps // 5, 3), 2)
+        res[kind + "_load_aware"] = {"ms": ms, "block": res[kind]["block"],
+                                     "status_flags": ws.status()}
+        s.close()
+    best = min((k for k in ("buffer", "block8", "buffer_load_aware", "block8_load_aware")
+                if k in res and "ms" in res[k]), key=lambda k: res[k]["ms"])
     # cell side rc against rc/2 (the reach-2 stencil: fewer candidate pairs,
     # smaller and more numerous tasks), fastest trial of each kind per grid
     variants = {}

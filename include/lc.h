@@ -241,6 +241,24 @@ int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *offsets,
 int lc_schedule_info_get(const lc_schedule *s, lc_schedule_info *out);
 void lc_schedule_free(lc_schedule *s);
 
+/* Load-aware variant of lc_make_schedule_ex (the weighted tasks of the
+ * paper's equal-duration assumption, Sec. V, relaxed): the work-groups of
+ * every phase are launched in decreasing order of estimated work -- the sum
+ * over a group's tasks of n_A n_B (n_A (n_A - 1) / 2 for an intra task) --
+ * so heavy groups start first and a launch ends on light ones.  cell_counts
+ * [host] int32 per cell (e.g. the differences of cell_start); LC_EINVAL if
+ * NULL or negative.  The schedule stays valid for any later particle
+ * distribution; only its launch order was chosen for this one. */
+int lc_make_schedule_weighted(const lc_grid *g, int kind, const int8_t *offsets,
+                              int n, const int32_t *block_min,
+                              const int32_t *cell_counts, lc_schedule **out);
+
+/* [host] The estimated work of every work-group of s in launch order, as
+ * lc_make_schedule_weighted orders it: work [host] double, one per group
+ * (lc_schedule_info.ngroup). */
+int lc_schedule_group_work(const lc_schedule *s, const int32_t *cell_counts,
+                           double *work);
+
 /* [host only] Build and validate the schedule of `kind` like
  * lc_make_schedule, without touching a device; fills *out. */
 int lc_schedule_plan(const lc_grid *g, int kind, const int8_t *offsets, int n,

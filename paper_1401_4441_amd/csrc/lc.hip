@@ -1974,8 +1974,9 @@ extern "C" int lc_make_schedule(const lc_grid *g, int kind, const int8_t *offset
     return lc_make_schedule_ex(g, kind, offsets, n, nullptr, out);
 }
 
-extern "C" int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *offsets, int n,
-                                   const int32_t *block_min, lc_schedule **out) {
+static int make_schedule_impl(const lc_grid *g, int kind, const int8_t *offsets, int n,
+                              const int32_t *block_min, const int32_t *cell_counts,
+                              lc_schedule **out) {
     if (!g || !out) return fail(LC_EINVAL, "lc_make_schedule: null argument");
     if (kind < 0 || kind >= LC_SCHED_COUNT) return fail(LC_EINVAL, "unknown schedule kind %d", kind);
     lc_schedule *s = new lc_schedule();
@@ -1985,6 +1986,15 @@ extern "C" int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *off
     if (rc) {
         delete s;
         return fail(rc, "lc_make_schedule: %s", err.c_str());
+    }
+    if (cell_counts) {
+        for (int64_t c = 0; c < g->ncell; ++c)
+            if (cell_counts[c] < 0) {
+                delete s;
+                return fail(LC_EINVAL, "lc_make_schedule_weighted: negative count in cell %lld",
+                            (long long)c);
+            }
+        lcs::order_groups_by_work(s->h, cell_counts);
     }
     if (!lcs::validate(s->h, g->ncell, err)) {
         delete s;
@@ -2068,6 +2078,26 @@ extern "C" int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *off
         }
     }
     *out = s;
+    return LC_OK;
+}
+
+extern "C" int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *offsets, int n,
+                                   const int32_t *block_min, lc_schedule **out) {
+    return make_schedule_impl(g, kind, offsets, n, block_min, nullptr, out);
+}
+
+extern "C" int lc_make_schedule_weighted(const lc_grid *g, int kind, const int8_t *offsets, int n,
+                                         const int32_t *block_min, const int32_t *cell_counts,
+                                         lc_schedule **out) {
+    if (!cell_counts) return fail(LC_EINVAL, "lc_make_schedule_weighted: null cell_counts");
+    return make_schedule_impl(g, kind, offsets, n, block_min, cell_counts, out);
+}
+
+extern "C" int lc_schedule_group_work(const lc_schedule *s, const int32_t *cell_counts,
+                                      double *work) {
+    if (!s || !cell_counts || !work) return fail(LC_EINVAL, "lc_schedule_group_work: null argument");
+    const std::vector<double> w = lcs::group_work(s->h, cell_counts);
+    std::copy(w.begin(), w.end(), work);
     return LC_OK;
 }
 

@@ -581,6 +581,58 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
     return LC_OK;
 }
 
+std::vector<double> group_work(const HostSchedule &hs, const int32_t *cell_counts) {
+    const size_t ng = hs.grp_task.empty() ? 0 : hs.grp_task.size() - 1;
+    std::vector<double> w(ng, 0.0);
+    for (size_t g = 0; g < ng; ++g) {
+        const int32_t *fc = hs.foot_cells.data() + hs.grp_foot[g];
+        for (int t = hs.grp_task[g]; t < hs.grp_task[g + 1]; ++t) {
+            const uint32_t ab = hs.task_ab[(size_t)t];
+            const int la = (int)(ab & 0xffffu), lb = (int)(ab >> 16);
+            const double na = cell_counts[fc[la]], nb = cell_counts[fc[lb]];
+            w[g] += la == lb ? na * (na - 1.0) * 0.5 : na * nb;
+        }
+    }
+    return w;
+}
+
+void order_groups_by_work(HostSchedule &hs, const int32_t *cell_counts) {
+    const std::vector<double> w = group_work(hs, cell_counts);
+    const size_t ng = w.size();
+    std::vector<int32_t> perm(ng);
+    for (size_t g = 0; g < ng; ++g) perm[g] = (int32_t)g;
+    const int nphase = (int)hs.phase_grp.size() - 1;
+    for (int p = 0; p < nphase; ++p)
+        std::stable_sort(perm.begin() + hs.phase_grp[p], perm.begin() + hs.phase_grp[p + 1],
+                         [&](int32_t a, int32_t b) { return w[(size_t)a] > w[(size_t)b]; });
+    HostSchedule out = hs;
+    out.grp_task.assign(1, 0);
+    out.grp_foot.assign(1, 0);
+    out.task_ab.clear();
+    out.foot_cells.clear();
+    out.foot_rep.clear();
+    for (int32_t g : perm) {
+        out.task_ab.insert(out.task_ab.end(), hs.task_ab.begin() + hs.grp_task[g],
+                           hs.task_ab.begin() + hs.grp_task[g + 1]);
+        out.foot_cells.insert(out.foot_cells.end(), hs.foot_cells.begin() + hs.grp_foot[g],
+                              hs.foot_cells.begin() + hs.grp_foot[g + 1]);
+        if (!hs.foot_rep.empty())
+            out.foot_rep.insert(out.foot_rep.end(), hs.foot_rep.begin() + hs.grp_foot[g],
+                                hs.foot_rep.begin() + hs.grp_foot[g + 1]);
+        out.grp_task.push_back((int32_t)out.task_ab.size());
+        out.grp_foot.push_back((int32_t)out.foot_cells.size());
+    }
+    if (out.write_mode == 3) {  // replica slot r: the r-th group, in launch order
+        std::fill(out.cell_rep.begin(), out.cell_rep.end(), 0);
+        out.rmax = 0;
+        for (size_t k = 0; k < out.foot_cells.size(); ++k) {
+            out.foot_rep[k] = out.cell_rep[(size_t)out.foot_cells[k]]++;
+            out.rmax = std::max(out.rmax, out.cell_rep[(size_t)out.foot_cells[k]]);
+        }
+    }
+    hs = std::move(out);
+}
+
 bool validate(const HostSchedule &hs, int64_t ncell, std::string &err) {
     if (hs.write_mode == 4) {
         // full shell: every cell is the home (written) cell of exactly one

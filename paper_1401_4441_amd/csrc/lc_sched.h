@@ -118,4 +118,15 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
 // plain read-modify-write).  Returns true when valid.
 bool validate(const HostSchedule &hs, int64_t ncell, std::string &err);
 
+// Estimated work of every work-group, in launch order: the sum over its
+// tasks of n_A n_B (n_A (n_A - 1) / 2 for an intra task) from per-cell
+// particle counts -- the task weights of the weighted critical path.
+std::vector<double> group_work(const HostSchedule &hs, const int32_t *cell_counts);
+
+// Reorder the work-groups of every phase by group_work, largest first
+// (longest-processing-time order: the heavy groups start early and the
+// launch ends on light ones).  Replica slots (buffer + reduce) are
+// reassigned in the new order.  Tasks inside a group keep their order.
+void order_groups_by_work(HostSchedule &hs, const int32_t *cell_counts);
+
 }  // namespace lcs

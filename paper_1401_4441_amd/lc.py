@@ -80,6 +80,8 @@ SYMBOLS = {
     "lc_gather": ([P, I64, P, P, P, P, P], INT),
     "lc_make_schedule": ([P, INT, P, INT, P], INT),
     "lc_make_schedule_ex": ([P, INT, P, INT, P, P], INT),
+    "lc_make_schedule_weighted": ([P, INT, P, INT, P, P, P], INT),
+    "lc_schedule_group_work": ([P, P, P], INT),
     "lc_schedule_info_get": ([P, P], INT),
     "lc_schedule_free": ([P], None),
     "lc_schedule_plan": ([P, INT, P, INT, P], INT),
@@ -226,8 +228,30 @@ class Workspace:
             pass
 
 
+def _counts_array(cell_counts, ncell: int):
+    import numpy as np
+    if isinstance(cell_counts, torch.Tensor):
+        cell_counts = cell_counts.detach().cpu().numpy()
+    arr = np.ascontiguousarray(np.asarray(cell_counts, dtype=np.int32).reshape(-1))
+    if arr.shape[0] != ncell:
+        raise LCError(-1, f"cell_counts has {arr.shape[0]} entries, the grid {ncell} cells")
+    return arr
+
+
+def cell_counts_of(cell_start) -> "object":
+    """Per-cell particle counts (host int32) from a cell_start array."""
+    import numpy as np
+    if isinstance(cell_start, torch.Tensor):
+        cell_start = cell_start.detach().cpu().numpy()
+    return np.diff(np.asarray(cell_start, dtype=np.int64)).astype(np.int32)
+
+
 class Schedule:
-    def __init__(self, grid: Grid, kind, offsets=None, block=None):
+    """A schedule of `kind` on `grid`.  cell_counts (per-cell particle
+    counts, e.g. cell_counts_of(cell_start)): launch each phase's work-groups
+    heaviest first (load-aware order)."""
+
+    def __init__(self, grid: Grid, kind, offsets=None, block=None, cell_counts=None):
         if isinstance(kind, str):
             kind = KINDS[kind]
         self._h = ctypes.c_void_p()
@@ -246,8 +270,23 @@ class Schedule:
             bp = None
         self.kind = int(kind)
         self.block = tuple(block) if block is not None else None
-        _chk(lib().lc_make_schedule_ex(grid.ptr, int(kind), op, int(n), bp,
-                                       ctypes.byref(self._h)))
+        if cell_counts is None:
+            _chk(lib().lc_make_schedule_ex(grid.ptr, int(kind), op, int(n), bp,
+                                           ctypes.byref(self._h)))
+        else:
+            cc = _counts_array(cell_counts, grid.ncell)
+            _chk(lib().lc_make_schedule_weighted(grid.ptr, int(kind), op, int(n), bp,
+                                                 ctypes.c_void_p(cc.ctypes.data),
+                                                 ctypes.byref(self._h)))
+
+    def group_work(self, cell_counts):
+        """Estimated work of every work-group, in launch order (numpy)."""
+        import numpy as np
+        cc = _counts_array(cell_counts, self.grid.ncell)
+        out = np.zeros(self.info()["ngroup"], dtype=np.float64)
+        _chk(lib().lc_schedule_group_work(self._h, ctypes.c_void_p(cc.ctypes.data),
+                                          ctypes.c_void_p(out.ctypes.data)))
+        return out
 
     @property
     def ptr(self):
