@@ -112,7 +112,7 @@ typedef struct lc_grid {
  * there is no LC_SCHED_BLOCK8 (LC_SCHED_LOOPEX colours with stride 3 and
  * needs cell counts divisible by 3), the presets OPT/BEST/BAD are not defined
  * (pass the order as LC_SCHED_CUSTOM offsets in [-2, 2]), and batches take
- * reach-1 grids only. */
+ * reach-1 3D grids only (no LC_GRID_HALF, no LC_GRID_2D). */
 int lc_make_grid(const double box[3], double rc, double skin, int flags,
                  lc_grid *out);
 

@@ -2632,9 +2632,10 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
             delete b;
             return fail(LC_EINVAL, "lc_batch_create: box %d", k);
         }
-        if (grid_reach(&boxes[k].grid) != 1) {
+        if (grid_reach(&boxes[k].grid) != 1 || boxes[k].grid.nc[2] < 3) {
             delete b;
-            return fail(LC_EINVAL, "lc_batch_create: box %d has a reach-2 grid", k);
+            return fail(LC_EINVAL, "lc_batch_create: box %d: batches take 3D grids of cells of "
+                                   "side >= rc", k);
         }
         b->pstart.push_back(b->pstart.back() + boxes[k].n);
         b->cstart.push_back(b->cstart.back() + boxes[k].grid.ncell);

@@ -293,3 +293,13 @@ def test_flat_grid_plans_follow_the_2d_closed_forms():
     assert info["max_group_cells"] == 8 * 11 - 1 and info["max_group_tasks"] == 5 * 7 * 9
     with pytest.raises(lc.LCError):
         lc.Grid((65.465, 65.465, 10.0), 2.5, half=True, flat=True)
+
+
+def test_batch_refuses_half_and_flat_grids():
+    """Batched boxes use the 3D rc-cell stencil (their whole-box groups
+    too): a box on a half-cell or flat grid is refused before any device
+    work."""
+    for g in (lc.Grid((17.0998,) * 3, 2.5, half=True),
+              lc.Grid((65.465, 65.465, 10.0), 2.5, flat=True)):
+        with pytest.raises(lc.LCError, match="3D grids"):
+            lc.Batch([lc.Grid((17.0998,) * 3, 2.5), g], [4000, 4000])
