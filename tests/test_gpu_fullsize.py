@@ -3,7 +3,8 @@ particles the oracle computes one by one (brute force over all partners),
 plus properties that hold at any size (exact momentum conservation, no
 flags).  Sizes: the 4,000,000-particle crystal on its rebuild grid (cells
 of rc + skin, 54^3) and on plain rc cells (68^3); the 2,000,000-particle
-inhomogeneous slab (rc = 3.0, 64^3 cells)."""
+inhomogeneous slab (rc = 3.0, 64^3 cells, plain and load-aware launch
+order; 131^3 cells of side rc/2)."""
 import numpy as np
 import pytest
 import torch
@@ -25,8 +26,8 @@ def _box(name):
     return _cache[name]
 
 
-def _check(box, skin, even, kinds, idx):
-    g = lc.Grid(box.L, box.rc, skin, even)
+def _check(box, skin, even, kinds, idx, half=False, weighted=False):
+    g = lc.Grid(box.L, box.rc, skin, even, half=half)
     print("grid", g.nc, "n", box.n, flush=True)
     ws = lc.Workspace(box.n, g.ncell)
     pos = torch.from_numpy(box.pos).to(DEV)
@@ -37,9 +38,10 @@ def _check(box, skin, even, kinds, idx):
     u = O.canonical(box.pos, box.L)
     Fo, nn = O.forces_subset_fx(u, box.L, box.rc, idx)
     results = []
+    counts = lc.cell_counts_of(cs) if weighted else None
     for kind in kinds:
         print("  kind", kind, flush=True)
-        s = lc.Schedule(g, kind)
+        s = lc.Schedule(g, kind, cell_counts=counts)
         ws.clear_status()
         F, ew = lc.compute_forces(g, s, cs, coord, ws)
         torch.cuda.synchronize()
@@ -48,7 +50,10 @@ def _check(box, skin, even, kinds, idx):
         assert (Fs == Fo).all(), kind
         assert (F.sum(dim=1) == 0).all(), kind
         assert st & lc.FLAG_OVERFLOW == 0, (kind, st)
-        results.append((F.clone(), ew.clone(), st))
+        # in input order: separate builds may order particles inside a cell
+        # differently (atomic ranks)
+        results.append((F[:, torch.from_numpy(inv.astype(np.int64)).to(DEV)].clone(), ew.clone(),
+                        st))
     for F, ew, _ in results[1:]:
         assert torch.equal(F, results[0][0]) and torch.equal(ew, results[0][1])
     return results
@@ -78,3 +83,7 @@ def test_slab2m():
                           rng.choice(gas, 16, replace=False)])
     res = _check(box, 0.0, True, ["buffer", "block8"], idx)
     assert all(st & lc.FLAG_FALLBACK == 0 for _, _, st in res)
+    # the load-aware launch order, and cells of side rc/2 (131^3)
+    res2 = _check(box, 0.0, True, ["buffer", "block8"], idx, weighted=True)
+    assert torch.equal(res2[0][0], res[0][0]) and torch.equal(res2[0][1], res[0][1])
+    _check(box, 0.0, False, ["atomic_tile"], idx, half=True)

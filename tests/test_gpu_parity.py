@@ -125,6 +125,28 @@ def test_c2_full_size_all_schedules():
         assert st == 0, (kind, st)
 
 
+def test_c2_headline_configurations():
+    """256k particles on the natural 27^3 grid with the block shapes the
+    autotuner picks there (BUFFER and ATOMIC_TILE up to 1x4x4 and 2x2x3,
+    FULLSHELL, BLOCK8 on odd counts), and on the rc/2 grid: bit-exact."""
+    box = synth.fcc(256000, 0.8, rc=2.5, seed=1002)
+    S = Setup(box)
+    assert S.g.nc == (27, 27, 27)
+    Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
+    for kind, block in (("buffer", (1, 3, 3)), ("buffer", (1, 3, 4)), ("buffer", (1, 4, 4)),
+                        ("buffer", (2, 2, 3)), ("atomic_tile", (1, 3, 4)),
+                        ("fullshell", (1, 2, 2)), ("block8", (1, 2, 2))):
+        _say("  fcc256k 27^3", kind, block)
+        F, ew, st = S.forces(kind, block=block)
+        assert st == 0 and (F == Fo).all() and ew == [Eo, Wo, npo], (kind, block)
+    H = Setup(box, half=True)
+    assert H.g.nc == (54, 54, 54)
+    for kind, block in (("buffer", (1, 2, 3)), ("atomic_tile", (1, 2, 2))):
+        _say("  fcc256k 54^3", kind, block)
+        F, ew, st = H.forces(kind, block=block)
+        assert st == 0 and (F == Fo).all() and ew == [Eo, Wo, npo], (kind, block)
+
+
 def test_ragged_and_vacancies():
     """N not a multiple of the lattice or of 64; odd cell counts."""
     for n, rho, seed in ((1234, 0.8, 3), (777, 0.6, 4), (5003, 0.85, 5)):
