@@ -100,7 +100,7 @@ struct lc_schedule {
     lcs::HostSchedule h;
     int32_t *grp_task = nullptr, *grp_foot = nullptr, *foot_cells = nullptr;
     uint32_t *task_ab = nullptr;
-    int32_t *foot_rep = nullptr, *cell_rep = nullptr;  // buffer + reduce
+    int32_t *foot_rep = nullptr;  // replica slot | count << 16 (buffer + reduce), home flag
     // the same groups at a fixed stride (see SweepArgs), or none
     uint32_t *fx_task = nullptr;
     int32_t *fx_foot = nullptr, *fx_rep = nullptr, *fx_cnt = nullptr;
@@ -2021,7 +2021,7 @@ static int make_schedule_impl(const lc_grid *g, int kind, const int8_t *offsets,
     };
     if ((rc = up(&s->grp_task, s->h.grp_task)) || (rc = up(&s->grp_foot, s->h.grp_foot)) ||
         (rc = up(&s->foot_cells, s->h.foot_cells)) || (rc = up(&s->task_ab, s->h.task_ab)) ||
-        (rc = up(&s->foot_rep, device_foot_rep(s->h))) || (rc = up(&s->cell_rep, s->h.cell_rep))) {
+        (rc = up(&s->foot_rep, device_foot_rep(s->h)))) {
         lc_schedule_free(s);
         return rc;
     }
@@ -2111,7 +2111,6 @@ extern "C" void lc_schedule_free(lc_schedule *s) {
     (void)hipFree(s->foot_cells);
     (void)hipFree(s->task_ab);
     (void)hipFree(s->foot_rep);
-    (void)hipFree(s->cell_rep);
     (void)hipFree(s->fx_task);
     (void)hipFree(s->fx_foot);
     (void)hipFree(s->fx_rep);
@@ -2577,7 +2576,7 @@ struct lc_batch {
     std::vector<PairParams> ppar;
     std::vector<BoxGeo> geo;
     int32_t *d_grp_task = nullptr, *d_grp_foot = nullptr, *d_foot_cells = nullptr;
-    int32_t *d_foot_rep = nullptr, *d_cell_rep = nullptr, *d_grp_box = nullptr;
+    int32_t *d_foot_rep = nullptr, *d_grp_box = nullptr;
     uint32_t *d_task_ab = nullptr;
     PairParams *d_ppar = nullptr;
     BoxGeo *d_geo = nullptr;
@@ -2599,7 +2598,6 @@ extern "C" void lc_batch_free(lc_batch *b) {
     (void)hipFree(b->d_grp_foot);
     (void)hipFree(b->d_foot_cells);
     (void)hipFree(b->d_foot_rep);
-    (void)hipFree(b->d_cell_rep);
     (void)hipFree(b->d_grp_box);
     (void)hipFree(b->d_task_ab);
     (void)hipFree(b->d_ppar);
@@ -2780,7 +2778,7 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
     if ((rc = upload(&b->d_grp_task, h.grp_task)) || (rc = upload(&b->d_grp_foot, h.grp_foot)) ||
         (rc = upload(&b->d_foot_cells, h.foot_cells)) ||
         (rc = upload(&b->d_foot_rep, device_foot_rep(h))) ||
-        (rc = upload(&b->d_cell_rep, h.cell_rep)) || (rc = upload(&b->d_grp_box, b->grp_box)) ||
+        (rc = upload(&b->d_grp_box, b->grp_box)) ||
         (rc = upload(&b->d_task_ab, h.task_ab)) || (rc = upload(&b->d_ppar, b->ppar)) ||
         (rc = upload(&b->d_geo, b->geo)) || (rc = upload(&b->d_pstart, ps)) ||
         (rc = dalloc(&b->d_ticket, 1))) {
