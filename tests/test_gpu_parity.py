@@ -376,3 +376,11 @@ def test_load_aware_group_order():
         torch.cuda.synchronize()
         assert S.ws.status() & lc.FLAG_OVERFLOW == 0
         assert (S.unsort(F) == Fo).all() and [int(x) for x in ew.cpu()] == [Eo, Wo, npo], kind
+
+
+def test_weighted_schedule_rejects_negative_counts():
+    g = lc.Grid((17.0998,) * 3, 2.5)
+    counts = np.ones(g.ncell, dtype=np.int32)
+    counts[5] = -1
+    with pytest.raises(lc.LCError, match="negative"):
+        lc.Schedule(g, "buffer", cell_counts=counts)

@@ -303,3 +303,12 @@ def test_batch_refuses_half_and_flat_grids():
               lc.Grid((65.465, 65.465, 10.0), 2.5, flat=True)):
         with pytest.raises(lc.LCError, match="3D grids"):
             lc.Batch([lc.Grid((17.0998,) * 3, 2.5), g], [4000, 4000])
+
+
+def test_new_entry_points_reject_bad_arguments():
+    """Argument checks that run before any device work."""
+    with pytest.raises(lc.LCError):
+        lc.selftest_recip(0x43000000, 0x3E800000)  # empty range
+    g = lc.Grid((17.0998,) * 3, 2.5)
+    with pytest.raises(lc.LCError):  # wrong number of cell counts
+        lc.Schedule(g, "buffer", cell_counts=np.zeros(g.ncell - 1, dtype=np.int32))
