@@ -137,7 +137,7 @@ def main():
         print(json.dumps({"copy_probe_bytes": x.numel() * 4, "copies": 3}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
+        print(json.dumps({"error": "this implementation runs on one GPU only; "
                           "--gpus must be 1 (multi-GPU sharding is design-only)"}))
         sys.exit(2)
 

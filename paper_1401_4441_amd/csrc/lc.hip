@@ -1345,7 +1345,7 @@ struct DfArgs {
 // Bounded wait of lane 0 for `ok(v)` on *p, or (cas) for the lock at *p to
 // be free and taken (only lane 0 polls, inside a divergent branch, so the
 // accesses are vector memory operations).  Gives up when another runner has
-// aborted or after a.limit ticks, then aborts everyone.  Returns the verdict
+// aborted or after a.limit ticks, then aborts everyone.  Returns the outcome
 // to all lanes.  No fence: the force adds are device atomics, so the waits
 // carry no data, only the strategy's scheduling constraint.
 template <class OK>
