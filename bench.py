@@ -120,6 +120,9 @@ def main():
                     help="fix the headline schedule instead of autotuning (with --block and "
                          "--grid; used to profile one configuration)")
     ap.add_argument("--block", default=None, help="block shape X,Y,Z for --schedule")
+    ap.add_argument("--load-aware", action="store_true",
+                    help="with --schedule: launch the groups heaviest first by the input's "
+                         "cell counts")
     ap.add_argument("--grid", default="natural", choices=("even", "natural", "wide", "half"),
                     help="cell grid for --schedule: even counts, natural (side >= rc), "
                          "or widened 15%% with even counts")
@@ -167,15 +170,18 @@ def main():
         blk0 = [int(x) for x in args.block.split(",")] if args.block else [1, 2, 2]
         pick = {"kind": args.schedule, "block": blk0, "grid": gopt}
         tune = {"trials": [dict(pick, nc=[0, 0, 0], ms=0.0, fallback=False)]}
+        load_aware = args.load_aware
     else:
         tune = autotune.tune_box(pos, box.L, box.rc, reps=10, use_cache=False,
                                  kinds=("block8", "buffer", "atomic_tile", "fullshell"))
         cf = [t for t in tune["trials"]
               if t["kind"] in autotune.BOX_KINDS_CONFLICT_FREE and not t["fallback"]]
         pick = min(cf, key=lambda t: t["ms"])
+        load_aware = None  # decided below by timing both launch orders
     g = autotune.make_grid(box.L, box.rc, pick["grid"])
     ws = lc.Workspace(box.n, g.ncell)
     cs, perm, coord = lc.build_cells(g, pos, ws)
+    counts = lc.cell_counts_of(cs)
 
     def best_block(kind):
         on_grid = [t for t in tune["trials"]
@@ -187,8 +193,8 @@ def main():
     ew = torch.empty(3, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
 
-    def time_sched(kind, steps, warmup, block=None):
-        s = lc.Schedule(g, kind, block=block)
+    def time_sched(kind, steps, warmup, block=None, weighted=False):
+        s = lc.Schedule(g, kind, block=block, cell_counts=counts if weighted else None)
         for _ in range(warmup):
             lc.compute_forces(g, s, cs, coord, ws, "fp32", F, ew)
         torch.cuda.synchronize()
@@ -205,10 +211,24 @@ def main():
         return s, ms, wall
 
     best, blk = pick["kind"], tuple(pick["block"])
+    order_trials = None
+    if load_aware is None:
+        # the autotuned kind and shape, its groups launched in the fixed
+        # order or heaviest first by this input's cell counts (the schedule
+        # is built before the timed region, like the autotuner's pick)
+        order_trials = {}
+        for w_ in (False, True):
+            ms_ = []
+            for _ in range(3):
+                s_, m_, _ = time_sched(best, 20, 3, blk, weighted=w_)
+                s_.close()
+                ms_.append(m_)
+            order_trials["load_aware" if w_ else "fixed"] = statistics.median(ms_)
+        load_aware = order_trials["load_aware"] < order_trials["fixed"]
 
     # ---- the timed region: K evaluations under that schedule
     ws.clear_status()
-    sched, ms, wall = time_sched(best, args.steps, args.warmup, blk)
+    sched, ms, wall = time_sched(best, args.steps, args.warmup, blk, weighted=load_aware)
     pairs = int(ew[2].item())
     status = ws.status()
     value = pairs / (ms * 1e-3)
@@ -250,6 +270,7 @@ def main():
         "data": "synthetic (seeded FCC lattice + uniform jitter)",
         "config": {"workload": w["desc"], "n": box.n, "cells": list(g.nc),
                    "schedule": best, "block": list(blk), "grid_choice": pick["grid"],
+                   "load_aware": load_aware, "launch_order_trials_ms": order_trials,
                    "autotune_trials": [[t["kind"], t["nc"][0], t["block"], round(t["ms"], 4)]
                                        for t in tune["trials"]],
                    "pairs_in_cutoff": pairs,
@@ -264,7 +285,8 @@ def main():
             "unit": "Tops/s (VALU lane-ops)",
             "frac": achieved_tops / VALU_PEAK_TOPS,
             "traffic": measured_traffic(f"k_sweep_wmode{sched.info()['write_mode']}", args.workload,
-                                        {"kind": best, "nc": list(g.nc), "block": list(blk)}),
+                                        {"kind": best, "nc": list(g.nc), "block": list(blk),
+                                         "load_aware": load_aware}),
             "traffic_source": f"profiles/k_sweep_{args.workload}_traffic.json (rocprofv3 --pmc "
                               "FETCH_SIZE / WRITE_SIZE, scaled by a 64 MiB copy); null if the "
                               "kernel changed since",

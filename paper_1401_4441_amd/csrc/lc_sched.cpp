@@ -345,6 +345,26 @@ std::vector<int> axis_blocks(int n, int minsize) {
     return s;
 }
 
+// The tasks of one block of cells (block bx, by, bz of the partition bs),
+// offset-major: for each stencil offset, every cell of the block in x-fastest
+// order.  Consecutive tasks then have distinct cells A and distinct cells B,
+// so the 64 lanes of a wave, which cover about five consecutive tasks, spread
+// their force additions over several cells' particles instead of piling them
+// onto one cell A.
+void block_tasks(const int32_t nc[3], const std::vector<int> bs[3], int bx, int by, int bz,
+                 const std::vector<Offset> &offs, std::vector<int32_t> &A,
+                 std::vector<int32_t> &B) {
+    for (const Offset &o : offs)
+        for (int z = bs[2][bz]; z < bs[2][bz + 1]; ++z)
+            for (int y = bs[1][by]; y < bs[1][by + 1]; ++y)
+                for (int x = bs[0][bx]; x < bs[0][bx + 1]; ++x) {
+                    A.push_back(x + nc[0] * (y + nc[1] * z));
+                    B.push_back((int32_t)(wrap(x + o.d[0], nc[0]) +
+                                          nc[0] * (wrap(y + o.d[1], nc[1]) +
+                                                   nc[1] * wrap(z + o.d[2], nc[2]))));
+                }
+}
+
 }  // namespace
 
 int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
@@ -416,18 +436,7 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
             for (size_t by = 0; by + 1 < bs[1].size(); ++by)
                 for (size_t bx = 0; bx + 1 < bs[0].size(); ++bx) {
                     G gr;
-                    for (int z = bs[2][bz]; z < bs[2][bz + 1]; ++z)
-                        for (int y = bs[1][by]; y < bs[1][by + 1]; ++y)
-                            for (int x = bs[0][bx]; x < bs[0][bx + 1]; ++x) {
-                                const int32_t a = x + nc[0] * (y + nc[1] * z);
-                                for (const Offset &o : shell) {
-                                    gr.A.push_back(a);
-                                    gr.B.push_back((int32_t)(
-                                        wrap(x + o.d[0], nc[0]) +
-                                        nc[0] * (wrap(y + o.d[1], nc[1]) +
-                                                 nc[1] * wrap(z + o.d[2], nc[2]))));
-                                }
-                            }
+                    block_tasks(nc, bs, (int)bx, (int)by, (int)bz, shell, gr.A, gr.B);
                     groups.push_back(std::move(gr));
                 }
         std::stable_sort(groups.begin(), groups.end(),
@@ -483,18 +492,7 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
                             (bz % ncol[2]) != col[2])
                             continue;
                         std::vector<int32_t> A, B;
-                        for (int z = bs[2][bz]; z < bs[2][bz + 1]; ++z)
-                            for (int y = bs[1][by]; y < bs[1][by + 1]; ++y)
-                                for (int x = bs[0][bx]; x < bs[0][bx + 1]; ++x) {
-                                    const int32_t a = x + nc[0] * (y + nc[1] * z);
-                                    for (const Offset &o : order) {
-                                        A.push_back(a);
-                                        B.push_back((int32_t)(
-                                            wrap(x + o.d[0], nc[0]) +
-                                            nc[0] * (wrap(y + o.d[1], nc[1]) +
-                                                     nc[1] * wrap(z + o.d[2], nc[2]))));
-                                    }
-                                }
+                        block_tasks(nc, bs, bx, by, bz, order, A, B);
                         groups.emplace_back(std::move(A), std::move(B));
                     }
             std::stable_sort(groups.begin(), groups.end(), [](const auto &x, const auto &y) {
