@@ -301,6 +301,20 @@ def main():
         "wall_s_timed": wall,
     }
 
+    # ---- the cell build (a1) alone and the evaluation with it, candidate rate
+    copy_gbs = copy_bandwidth_gbs()
+    out["cell_build"] = cell_build_stats(lc, g, pos, ws, copy_gbs)
+    cs_b = torch.empty_like(cs)
+    perm_b = torch.empty_like(perm)
+    coord_b = torch.empty_like(coord)
+
+    def build_and_eval():
+        lc.build_cells(g, pos, ws, cs_b, perm_b, coord_b, tile_hint=False)
+        lc.compute_forces(g, sched, cs_b, coord_b, ws, "fp32", F, ew)
+    ms_wb = statistics.median(_time_evals(build_and_eval, 20, 3) for _ in range(3))
+    out["with_cell_build"] = {"ms_per_step": ms_wb, "pairs_per_s": pairs / (ms_wb * 1e-3)}
+    out["candidate_pairs_per_s"] = ncand / (ms * 1e-3)
+
     # ---- baselines: same evaluation under the other schedules
     if not args.no_extra:
         extra = {}
@@ -437,6 +451,48 @@ def _time_evals(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+# algorithmic bytes of the cell build: read the positions (3 x f64), write
+# the permutation (int32) and the box fractions (3 x u32) of every particle,
+# and cell_start (int32) of every cell.  The counting sort as built moves
+# 84 B per particle: the bin pass reads the positions and writes cell and
+# rank (32 B), the scatter pass reads them again with cell and rank and the
+# cell's start and writes the permutation and box fractions (52 B).
+BUILD_BYTES_PER_PARTICLE = 24 + 4 + 12
+BUILD_BYTES_PER_CELL = 4
+BUILD_BYTES_MOVED_PER_PARTICLE = 84
+
+
+def copy_bandwidth_gbs(nbytes=256 * 2 ** 20):
+    """Device-to-device copy bandwidth, bytes read + written per second
+    (GB/s), median of 5 timings of 10 copies."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    ms = statistics.median(_time_evals(lambda: y.copy_(x), 10, 2) for _ in range(5))
+    del x, y
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cell_build_stats(lc, g, pos, ws, copy_gbs, reps=20):
+    """The cell build (counting sort of `pos` into the cells of `g`) into
+    outputs of its own: time and HBM rate against 8 TB/s and against the
+    measured copy bandwidth."""
+    import torch
+    n = pos.shape[1]
+    cs = torch.empty(g.ncell + 1, dtype=torch.int32, device=pos.device)
+    perm = torch.empty(n, dtype=torch.int32, device=pos.device)
+    coord = torch.empty((3, n), dtype=torch.int32, device=pos.device)
+    ms = statistics.median(
+        _time_evals(lambda: lc.build_cells(g, pos, ws, cs, perm, coord, tile_hint=False), reps, 3)
+        for _ in range(3))
+    alg = n * BUILD_BYTES_PER_PARTICLE + (g.ncell + 1) * BUILD_BYTES_PER_CELL
+    gbs = alg / (ms * 1e-3) / 1e9
+    return {"ms": ms, "n": n, "cells": g.ncell, "algorithmic_bytes": alg, "GBps": gbs,
+            "hbm_frac": gbs / HBM_PEAK_GBS, "copy_GBps": copy_gbs, "frac_of_copy": gbs / copy_gbs,
+            "bytes_moved_per_particle": BUILD_BYTES_MOVED_PER_PARTICLE,
+            "moved_GBps": (n * BUILD_BYTES_MOVED_PER_PARTICLE) / (ms * 1e-3) / 1e9}
+
+
 def _line(metric, value, unit, ms, args, config, dtype="f32 pair math, int64 fixed-point accumulation",
           **extra):
     out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
@@ -482,12 +538,19 @@ def bench_md(args):
     cs2, _, co2 = lc.build_cells(g, pos, ws)
     _, ew = lc.compute_forces(g, sched, cs2, co2, ws)
     pairs = int(ew[2].item())
+    # the cell build at 4M: on the final positions (stored in cell order by
+    # the rebuilds) and on the starting ones (lattice order)
+    copy_gbs = copy_bandwidth_gbs()
+    build = {"cell_order": cell_build_stats(lc, g, pos, ws, copy_gbs),
+             "lattice_order": cell_build_stats(
+                 lc, g, torch.from_numpy(box.pos).to(dev), ws, copy_gbs)}
     _line("pair interactions/sec during velocity-Verlet MD (step incl. kick/drift, rebuilds, energies)",
           pairs / (ms * 1e-3), "pairs/s", ms, args,
           {"workload": "LJ FCC+jitter N=4000000 rho=0.8 rc=2.5, MB T=1, dt=0.005, "
                        "rebuild every 10, skin 0.6, 54^3 cells", "nsteps": nsteps,
            "schedule": tune["kind"], "block": tune["block"], "status_flags": st},
           dtype="f32 pairs, int64 forces, f64 positions/velocities/energies",
+          cell_build=build,
           energy={"E0_per_particle": etot[0] / box.n,
                   "drift_per_particle": (etot[-1] - etot[0]) / box.n,
                   "fluct_per_particle": float(etot.max() - etot.min()) / box.n,

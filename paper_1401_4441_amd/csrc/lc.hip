@@ -3,7 +3,8 @@
 // Kernels
 //   k_fill64 / k_fill32     zero-fill (used instead of hipMemsetAsync so the
 //                           whole path can sit inside a captured graph)
-//   k_bin                   cell of each particle + atomic rank in its cell
+//   k_bin                   cell of each particle + its rank in the cell (one
+//                           counter atomic per cell and wave)
 //   k_scan_*                exclusive scan of per-cell counts -> cell_start
 //   k_scatter               counting-sort scatter: perm + sorted box fractions
 //   k_sweep<CAP,WMODE,F64,FF>  one phase of cell-cell tasks (Sec. IV): per
@@ -376,16 +377,47 @@ struct GridArgs {
     int nc[3];
 };
 
-__global__ void k_bin(const double *__restrict__ pos, int64_t n, GridArgs ga,
-                      int *__restrict__ cid, int *__restrict__ rank,
-                      int *__restrict__ counts) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int c[3];
-    for (int d = 0; d < 3; ++d) c[d] = cell_of(canon(pos[d * n + i], ga.inv[d]), ga.nc[d]);
-    int cc = c[0] + ga.nc[0] * (c[1] + ga.nc[1] * c[2]);
-    cid[i] = cc;
-    rank[i] = atomicAdd(&counts[cc], 1);
+// Rank of this lane's particle among the particles of its cell cc (act:
+// the lane holds a particle), from the cell counters.  The lanes of a wave
+// that fall into one cell share a single atomic: the lowest of them adds the
+// group's size and every lane takes the group's base plus its place in the
+// group.  Particles stored near each other (a lattice, or an array already
+// sorted by cell) then cost one counter update per cell and wave instead of
+// one per particle, all of them on the same address.
+__device__ __forceinline__ int wave_cell_rank(bool act, int cc, int *__restrict__ counts) {
+    const int lane = threadIdx.x & 63;
+    if (!act) cc = -1;
+    // group the active lanes by cell (one pass per distinct cell, at most 64)
+    unsigned long long todo = __ballot(act), mine = 0ull;
+    while (todo) {
+        const int lead = (int)__builtin_ctzll(todo);
+        const int lcell = __builtin_amdgcn_readlane(cc, lead);
+        const unsigned long long same = __ballot(cc == lcell);
+        if (cc == lcell) mine = same;
+        todo &= ~same;
+    }
+    const unsigned long long below = mine & ((1ull << lane) - 1ull);
+    int base = 0;
+    if (act && below == 0ull) base = atomicAdd(&counts[cc], __popcll(mine));
+    base = __shfl(base, act ? (int)__builtin_ctzll(mine) : lane);
+    return base + __popcll(below);
+}
+
+// Cell of every particle and its rank in the cell.
+__global__ __launch_bounds__(256) void k_bin(const double *__restrict__ pos, int64_t n,
+                                             GridArgs ga, int *__restrict__ cid,
+                                             int *__restrict__ rank, int *__restrict__ counts) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = i < n;
+    int cc = 0;
+    if (act) {
+        int c[3];
+        for (int d = 0; d < 3; ++d) c[d] = cell_of(canon(pos[d * n + i], ga.inv[d]), ga.nc[d]);
+        cc = c[0] + ga.nc[0] * (c[1] + ga.nc[1] * c[2]);
+        cid[i] = cc;
+    }
+    const int r = wave_cell_rank(act, cc, counts);
+    if (act) rank[i] = r;
 }
 
 constexpr int kScanBS = 256, kScanIPT = 4, kScanTile = kScanBS * kScanIPT;
@@ -2535,18 +2567,23 @@ __device__ __forceinline__ int box_of(const int64_t *__restrict__ pstart, int nb
     return lo;
 }
 
-__global__ void k_bin_batch(const double *__restrict__ pos, int64_t ntot,
-                            const int64_t *__restrict__ pstart, int nbox,
-                            const BoxGeo *__restrict__ geo, int *__restrict__ cid,
-                            int *__restrict__ rank, int *__restrict__ counts) {
+__global__ __launch_bounds__(256) void k_bin_batch(const double *__restrict__ pos, int64_t ntot,
+                                                   const int64_t *__restrict__ pstart, int nbox,
+                                                   const BoxGeo *__restrict__ geo,
+                                                   int *__restrict__ cid, int *__restrict__ rank,
+                                                   int *__restrict__ counts) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ntot) return;
-    const BoxGeo gb = geo[box_of(pstart, nbox, i)];
-    int c[3];
-    for (int d = 0; d < 3; ++d) c[d] = cell_of(canon(pos[d * ntot + i], gb.inv[d]), gb.nc[d]);
-    const int cc = gb.cstart + c[0] + gb.nc[0] * (c[1] + gb.nc[1] * c[2]);
-    cid[i] = cc;
-    rank[i] = atomicAdd(&counts[cc], 1);
+    const bool act = i < ntot;
+    int cc = 0;
+    if (act) {
+        const BoxGeo gb = geo[box_of(pstart, nbox, i)];
+        int c[3];
+        for (int d = 0; d < 3; ++d) c[d] = cell_of(canon(pos[d * ntot + i], gb.inv[d]), gb.nc[d]);
+        cc = gb.cstart + c[0] + gb.nc[0] * (c[1] + gb.nc[1] * c[2]);
+        cid[i] = cc;
+    }
+    const int r = wave_cell_rank(act, cc, counts);
+    if (act) rank[i] = r;
 }
 
 __global__ void k_scatter_batch(const double *__restrict__ pos, int64_t ntot,
