@@ -123,7 +123,9 @@ typedef struct lc_workspace lc_workspace;
 /* [host] Device scratch for up to max_n particles and max_cells cells
  * (cell ids, per-cell counters, scan partials, status flags, Verlet
  * reference positions and staging).  Allocates with hipMalloc on the
- * current device. */
+ * current device and clears it (synchronises the device).  A workspace
+ * serves one stream at a time: the cell build keeps its per-cell counters
+ * cleared between calls instead of clearing them at the start of each. */
 int lc_workspace_create(int64_t max_n, int64_t max_cells, lc_workspace **out);
 void lc_workspace_destroy(lc_workspace *ws);
 

@@ -5,7 +5,8 @@
 //                           whole path can sit inside a captured graph)
 //   k_bin                   cell of each particle + its rank in the cell (one
 //                           counter atomic per cell and wave)
-//   k_scan_*                exclusive scan of per-cell counts -> cell_start
+//   k_scan_one / k_scan_*   exclusive scan of per-cell counts -> cell_start
+//                           (one work-group up to 65,536 cells, else 3 passes)
 //   k_scatter               counting-sort scatter: perm + sorted box fractions
 //   k_sweep<CAP,WMODE,F64,FF>  one phase of cell-cell tasks (Sec. IV): per
 //                           work-group a group of tasks whose footprint cells
@@ -301,18 +302,16 @@ __device__ __forceinline__ int wave_max32(int v) {
 // Exclusive scan of one value per thread over a work-group of NT threads.
 template <int NT, typename T>
 __device__ T block_scan_excl(T v, T *s_w, T &total) {
+    static_assert(NT % 64 == 0 && NT <= 64 * 64, "whole waves, at most 64 of them");
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const T x = wave_scan_incl(v);
     if (lane == 63) s_w[w] = x;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        T acc = 0;
-        for (int k = 0; k < NT / 64; ++k) {
-            T t = s_w[k];
-            s_w[k] = acc;
-            acc += t;
-        }
-        s_w[NT / 64] = acc;
+    if (w == 0) {  // the wave totals, scanned by wave 0 (all of its lanes active)
+        const T t = lane < NT / 64 ? s_w[lane] : (T)0;
+        const T inc = wave_scan_incl(t);
+        if (lane < NT / 64) s_w[lane] = inc - t;
+        if (lane == NT / 64 - 1) s_w[NT / 64] = inc;
     }
     __syncthreads();
     total = s_w[NT / 64];
@@ -447,7 +446,9 @@ __global__ __launch_bounds__(kScanBS) void k_scan_top(int *__restrict__ partial,
     }
 }
 
-__global__ __launch_bounds__(kScanBS) void k_scan_final(const int *__restrict__ in, int64_t m,
+// (the last pass over the cell counters: it also clears them for the next
+// build, so no separate fill is needed)
+__global__ __launch_bounds__(kScanBS) void k_scan_final(int *__restrict__ in, int64_t m,
                                                         const int *__restrict__ partial,
                                                         int *__restrict__ out) {
     __shared__ int s_w[kScanBS / 64 + 1];
@@ -458,6 +459,8 @@ __global__ __launch_bounds__(kScanBS) void k_scan_final(const int *__restrict__ 
         v[k] = base + k < m ? in[base + k] : 0;
         sum += v[k];
     }
+    for (int k = 0; k < kScanIPT; ++k)
+        if (base + k < m) in[base + k] = 0;
     int total;
     int e = block_scan_excl<kScanBS>(sum, s_w, total) + partial[blockIdx.x];
     for (int k = 0; k < kScanIPT; ++k) {
@@ -466,6 +469,81 @@ __global__ __launch_bounds__(kScanBS) void k_scan_final(const int *__restrict__ 
     }
     // the end marker: total particle count
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[m] = partial[blockIdx.x] + total;
+}
+
+// Exclusive scan of up to kScanOneMax cell counters by one work-group, with
+// the end marker, clearing the counters as it goes.  Thread t owns one run of
+// `per4` int4 words; all its loads are issued before the one work-group
+// scan, so a small grid costs one memory round trip and one launch instead
+// of three.  Needs a 16-byte aligned output.
+constexpr int kScanOneBS = 1024, kScanOneVec = 16;
+constexpr int kScanOneMax = kScanOneBS * kScanOneVec * 4;
+
+__global__ __launch_bounds__(kScanOneBS) void k_scan_one(int *__restrict__ counts, int m,
+                                                         int *__restrict__ out) {
+    __shared__ int s_w[kScanOneBS / 64 + 1];
+    const int per4 = (m + 4 * kScanOneBS - 1) / (4 * kScanOneBS);
+    const int b4 = (int)threadIdx.x * per4, m4 = m >> 2;
+    int4 *c4 = reinterpret_cast<int4 *>(counts);  // hipMalloc: 256-B aligned
+    int4 *o4 = reinterpret_cast<int4 *>(out);
+    int4 v[kScanOneVec];
+    int sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanOneVec; ++j) {
+        const int q = b4 + j;
+        v[j] = make_int4(0, 0, 0, 0);
+        if (j < per4) {
+            if (q < m4) {
+                v[j] = c4[q];
+            } else if (q == m4) {  // the ragged last word
+                const int e = 4 * q;
+                v[j].x = e < m ? counts[e] : 0;
+                v[j].y = e + 1 < m ? counts[e + 1] : 0;
+                v[j].z = e + 2 < m ? counts[e + 2] : 0;
+            }
+        }
+        sum += v[j].x + v[j].y + v[j].z + v[j].w;
+    }
+    int total;
+    int run = block_scan_excl<kScanOneBS>(sum, s_w, total);
+#pragma unroll
+    for (int j = 0; j < kScanOneVec; ++j) {
+        const int q = b4 + j;
+        if (j < per4) {
+            const int4 o = make_int4(run, run + v[j].x, run + v[j].x + v[j].y,
+                                     run + v[j].x + v[j].y + v[j].z);
+            if (q < m4) {
+                o4[q] = o;
+                c4[q] = make_int4(0, 0, 0, 0);
+            } else if (q == m4) {
+                const int e = 4 * q;
+                if (e < m) { out[e] = o.x; counts[e] = 0; }
+                if (e + 1 < m) { out[e + 1] = o.y; counts[e + 1] = 0; }
+                if (e + 2 < m) { out[e + 2] = o.z; counts[e + 2] = 0; }
+            }
+        }
+        run += v[j].x + v[j].y + v[j].z + v[j].w;
+    }
+    if (threadIdx.x == 0) out[m] = total;
+}
+
+// cell_start from the cell counters (which are left cleared).
+static int scan_counts(lc_workspace *ws, int64_t m, int32_t *cell_start, hipStream_t st) {
+    if (m <= kScanOneMax && ((uintptr_t)cell_start & 15u) == 0) {
+        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kScanOneBS), 0, st, ws->counts, (int)m,
+                           cell_start);
+        LAUNCHCHK("k_scan_one");
+        return LC_OK;
+    }
+    const int nb = (int)((m + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBS), 0, st, ws->counts, m, ws->partial);
+    LAUNCHCHK("k_scan_reduce");
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBS), 0, st, ws->partial, nb);
+    LAUNCHCHK("k_scan_top");
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanBS), 0, st, ws->counts, m, ws->partial,
+                       cell_start);
+    LAUNCHCHK("k_scan_final");
+    return LC_OK;
 }
 
 __global__ void k_scatter(const double *__restrict__ pos, int64_t n, GridArgs ga,
@@ -487,21 +565,15 @@ static int build_cells_impl(const lc_grid *g, const double *pos, int64_t n, int3
         ga.inv[d] = g->inv_box[d];
         ga.nc[d] = g->nc[d];
     }
-    int rc = fill32(ws->counts, m, st);
-    if (rc) return rc;
+    // the cell counters are clear: the workspace starts so and every scan
+    // leaves them so
     if (n > 0) {
         hipLaunchKernelGGL(k_bin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n, ga,
                            ws->cid, ws->rank, ws->counts);
         LAUNCHCHK("k_bin");
     }
-    const int nb = (int)((m + kScanTile - 1) / kScanTile);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBS), 0, st, ws->counts, m, ws->partial);
-    LAUNCHCHK("k_scan_reduce");
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBS), 0, st, ws->partial, nb);
-    LAUNCHCHK("k_scan_top");
-    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanBS), 0, st, ws->counts, m, ws->partial,
-                       cell_start);
-    LAUNCHCHK("k_scan_final");
+    int rc = scan_counts(ws, m, cell_start, st);
+    if (rc) return rc;
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n,
                            ga, ws->cid, ws->rank, cell_start, perm, coord);
@@ -1944,9 +2016,11 @@ extern "C" int lc_workspace_create(int64_t max_n, int64_t max_cells, lc_workspac
         return rc;
     }
     if (hipMemset(ws->flags, 0, sizeof(uint32_t)) != hipSuccess ||
-        hipMemset(ws->part, 0, 3 * kPartSlots * sizeof(int64_t)) != hipSuccess) {
+        hipMemset(ws->part, 0, 3 * kPartSlots * sizeof(int64_t)) != hipSuccess ||
+        hipMemset(ws->counts, 0, (size_t)max_cells * sizeof(int)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
         lc_workspace_destroy(ws);
-        return fail(LC_EHIP, "hipMemset flags");
+        return fail(LC_EHIP, "lc_workspace_create: clearing the workspace");
     }
     *out = ws;
     return LC_OK;
@@ -2858,21 +2932,14 @@ extern "C" int lc_batch_build_cells(const lc_batch *b, const double *pos, int32_
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     const int64_t m = b->ncell, n = b->ntot;
-    if ((rc = fill32(ws->counts, m, st))) return rc;
+    // the cell counters are clear (see build_cells_impl)
     if (n > 0) {
         hipLaunchKernelGGL(k_bin_batch, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n,
                            (const int64_t *)b->d_pstart, b->nbox, (const BoxGeo *)b->d_geo, ws->cid,
                            ws->rank, ws->counts);
         LAUNCHCHK("k_bin_batch");
     }
-    const int nb = (int)((m + kScanTile - 1) / kScanTile);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBS), 0, st, ws->counts, m, ws->partial);
-    LAUNCHCHK("k_scan_reduce");
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBS), 0, st, ws->partial, nb);
-    LAUNCHCHK("k_scan_top");
-    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanBS), 0, st, ws->counts, m, ws->partial,
-                       cell_start);
-    LAUNCHCHK("k_scan_final");
+    if ((rc = scan_counts(ws, m, cell_start, st))) return rc;
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter_batch, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos,
                            n, (const int64_t *)b->d_pstart, b->nbox, (const BoxGeo *)b->d_geo,

@@ -78,6 +78,26 @@ def test_build_cells_c1():
     assert (coord == S.u[:, perm]).all()
 
 
+def test_cell_build_reuses_workspace_counters():
+    """Each scan leaves the per-cell counters cleared for the next build:
+    builds on one workspace that alternate a grid scanned by one work-group
+    (6^3 cells) and one scanned in three passes (41^3 = 68,921 cells, above
+    the one-work-group limit of 65,536) all match the oracle's cell table."""
+    small = synth.fcc(4000, 0.8, rc=2.5, seed=51)
+    big = synth.fcc(20000, 0.0185, rc=2.5, seed=52)
+    gs, gb = lc.Grid(small.L, small.rc), lc.Grid(big.L, big.rc)
+    assert gs.ncell <= 65536 < gb.ncell
+    ws = lc.Workspace(big.n, gb.ncell)
+    for box, g in ((small, gs), (big, gb), (small, gs), (big, gb), (big, gb)):
+        _say("cell build", g.nc)
+        cs, perm, coord = lc.build_cells(g, torch.from_numpy(box.pos).to(DEV), ws)
+        u = O.canonical(box.pos, box.L)
+        csh = cs.cpu().numpy()
+        assert (csh == O.cell_start(u, g.nc)).all()
+        slot_cell = np.repeat(np.arange(g.ncell), np.diff(csh))
+        assert (O.cell_ids(u, g.nc)[perm.cpu().numpy()] == slot_cell).all()
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_forces_bit_exact_c1(kind):
     S = c1()
