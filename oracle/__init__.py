@@ -64,6 +64,8 @@ def lib():
         L.orc_forces_brute_fx.argtypes = [i64, P, P, f64, P, P, P]
         L.orc_forces_lc_fx.argtypes = [i64, P, P, f64, P, P, ctypes.c_int, P, P, P]
         L.orc_forces_lc_f64.argtypes = [i64, P, P, P, f64, P, P, ctypes.c_int, P, P, P]
+        L.orc_forces_loopex_omp.argtypes = [i64, P, P, f64, P, P, ctypes.c_int, ctypes.c_int,
+                                            P, P, P, P]
         L.orc_lc_tasks.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P]
         L.orc_dag_generic.argtypes = [ctypes.c_int, P, P, P, P, P, P]
         L.orc_dag_lc.argtypes = [ctypes.c_int, P, P, P, P]
@@ -238,6 +240,29 @@ def forces_lc_fx(u, L, rc, nc, stencil=H3):
                                   _ptr(offs), len(offs), _ptr(F), _ptr(ew),
                                   ctypes.byref(np_)), "forces_lc_fx")
     return F, int(ew[0]), int(ew[1]), int(np_.value)
+
+
+def forces_loopex_omp(u, L, rc, nc, stencil=H3, threads=0):
+    """The fixed-point link-cell sweep in the loop-exchange order with
+    two-strided colouring (Sec. VI, strategy 1), parallel over the cells of
+    each colour with OpenMP; needs even cell counts.  Same bits as
+    forces_lc_fx.  threads <= 0: OpenMP's default.
+
+    Returns (F, E, W, npairs, threads_used)."""
+    u = np.ascontiguousarray(u, dtype=np.uint32)
+    n = u.shape[1]
+    Lv = np.ascontiguousarray(np.asarray(L, dtype=np.float64).reshape(3))
+    ncv = np.ascontiguousarray(np.asarray(nc, dtype=np.int32).reshape(3))
+    offs = offsets_array(stencil)
+    F = np.empty((3, n), dtype=np.int64)
+    ew = np.empty(2, dtype=np.int64)
+    np_ = ctypes.c_int64(0)
+    used = ctypes.c_int(0)
+    _check(lib().orc_forces_loopex_omp(n, _ptr(u), _ptr(Lv), rc, _ptr(ncv), _ptr(offs),
+                                       len(offs), int(threads), _ptr(F), _ptr(ew),
+                                       ctypes.byref(np_), ctypes.byref(used)),
+           "forces_loopex_omp")
+    return F, int(ew[0]), int(ew[1]), int(np_.value), int(used.value)
 
 
 def forces_lc_f64(pos, u, L, rc, nc, stencil=H3):

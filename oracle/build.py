@@ -2,7 +2,8 @@
 
 Test infrastructure only.  -ffp-contract=off keeps every floating-point
 operation separately rounded (no fused multiply-add), which the oracle's
-canonical FP32 pair sequence relies on.
+canonical FP32 pair sequence relies on.  -fopenmp: the loop-exchange
+sweep (the benchmark's parallel CPU reference) runs with OpenMP.
 """
 from __future__ import annotations
 
@@ -15,7 +16,7 @@ SRC = os.path.join(HERE, "lc_oracle.c")
 LIB = os.path.join(HERE, "liblc_oracle.so")
 
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
-          "-fPIC", "-shared", "-Wall", "-Wextra"]
+          "-fPIC", "-shared", "-Wall", "-Wextra", "-fopenmp"]
 
 
 def build(verbose: bool = False) -> str:

@@ -16,7 +16,10 @@
  *   2. Lennard-Jones pair terms, FP64 and canonical FP32 + int64 fixed point
  *   3. forces by brute force O(N^2) and by the serial link-cell method
  *      (Sec. IV: cells of side >= rc, Newton's third law, half stencil of
- *      Fig. 3; every cell-cell interaction updates both cells)
+ *      Fig. 3; every cell-cell interaction updates both cells); the same
+ *      sweep in the paper's loop-exchange order with two-strided colouring
+ *      (Sec. VI, strategy 1), run with OpenMP: the benchmark's parallel CPU
+ *      reference, checked against the serial sweep bit for bit
  *   4. task creation orders of the link-cell traversal: the basic order
  *      (Sec. V: per cell, intra first then inter; cells x, then y, then z)
  *      and the loop-exchanged two-strided coloured order (Sec. VI, strategy 1)
@@ -26,6 +29,7 @@
  *   6. velocity Verlet in FP64 with fixed-point forces
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -418,6 +422,79 @@ int orc_forces_lc_f64(int64_t n, const double *pos, const uint32_t *u,
                       int64_t *npairs)
 {
     return lc_sweep(1, n, pos, u, L, rc, nc, offs, noff, F, ew, npairs);
+}
+
+/* The sweep in the loop-exchange order of Sec. VI (strategy 1): for the
+ * intra-cell interaction and then every offset of the half stencil, for each
+ * of the 8 parity classes of cells (x, y, z each even or odd), the tasks
+ * (cell, cell + offset) of that class run in parallel.  With even cell
+ * counts two cells of one class differ by an even number of cells along
+ * every axis, while a nonzero offset moves one cell along some axis, so no
+ * two tasks of one class touch a common cell and the int64 force adds need
+ * no atomics.  The pair arithmetic is the serial sweep's, and integer sums do
+ * not depend on their order: the result equals orc_forces_lc_fx bit for bit.
+ * nthreads <= 0 takes OpenMP's default; *threads_used reports the count. */
+int orc_forces_loopex_omp(int64_t n, const uint32_t *u, const double *L, double rc,
+                          const int32_t *nc, const int8_t *offs, int noff, int nthreads,
+                          int64_t *F, int64_t *ew, int64_t *npairs, int *threads_used)
+{
+    int rcode = check_grid(L, rc, nc);
+    if (rcode) return rcode;
+    for (int d = 0; d < 3; ++d)
+        if (nc[d] % 2) return ORC_EINVAL;  /* the colouring needs even counts */
+    int32_t *cid = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!cid) return ORC_ENOMEM;
+    orc_cell_ids(n, u, nc, cid);
+    lc_cells c;
+    rcode = cells_build(&c, n, cid, nc);
+    if (rcode) { free(cid); return rcode; }
+    fx_par p;
+    fx_par_init(&p, L, rc);
+    memset(F, 0, sizeof(int64_t) * 3 * (size_t)n);
+    const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+    int64_t Eq = 0, Wq = 0, np = 0;
+    int ovf = 0, used = 1;
+    const int64_t hx = nc[0] / 2, hy = nc[1] / 2, hz = nc[2] / 2;
+    for (int k = -1; k < noff; ++k) {  /* k = -1: the intra-cell interaction */
+        for (int col = 0; col < 8; ++col) {
+            const int64_t cx = col & 1, cy = (col >> 1) & 1, cz = col >> 2;
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : Eq, Wq, np) \
+    reduction(| : ovf)
+            for (int64_t t = 0; t < hx * hy * hz; ++t) {
+                if (t == 0) used = omp_get_num_threads();
+                const int64_t x = cx + 2 * (t % hx), y = cy + 2 * ((t / hx) % hy),
+                              z = cz + 2 * (t / (hx * hy));
+                const int64_t a = x + nc[0] * (y + nc[1] * z);
+                int64_t b = a;
+                if (k >= 0) {
+                    const int64_t bx = wrapi(x + offs[3 * k + 0], nc[0]);
+                    const int64_t by = wrapi(y + offs[3 * k + 1], nc[1]);
+                    const int64_t bz = wrapi(z + offs[3 * k + 2], nc[2]);
+                    b = bx + nc[0] * (by + nc[1] * bz);
+                }
+                for (int64_t i = c.head[a]; i >= 0; i = c.next[i])
+                    for (int64_t j = k < 0 ? c.next[i] : c.head[b]; j >= 0; j = c.next[j]) {
+                        int64_t q[3], qe, qw;
+                        int o = 0;
+                        if (pair_fx(u, n, i, j, &p, q, &qe, &qw, &o)) {
+                            for (int d = 0; d < 3; ++d) {
+                                F[d * n + i] -= q[d];
+                                F[d * n + j] += q[d];
+                            }
+                            Eq += qe; Wq += qw; ++np;
+                        }
+                        ovf |= o;
+                    }
+            }
+        }
+    }
+    ew[0] = Eq;
+    ew[1] = Wq;
+    if (npairs) *npairs = np;
+    if (threads_used) *threads_used = used;
+    cells_free(&c);
+    free(cid);
+    return ovf ? ORC_EOVERFLOW : ORC_OK;
 }
 
 /* ------------------------------------------------------------------------- */

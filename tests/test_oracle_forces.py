@@ -84,6 +84,38 @@ def test_lc_fixed_point_bit_exact_vs_brute():
     assert (Eb, Wb) == (El, Wl)
 
 
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_loopex_omp_equals_serial_sweep(threads):
+    """The OpenMP loop-exchange sweep (8 parity classes per stencil offset,
+    cells of one class in parallel) gives the serial sweep's bits: a dense
+    crystal on 6^3 cells, a dilute one with empty cells on 8^3, and a skin
+    grid; it is pinned to brute force through the serial sweep."""
+    cases = [(_tiny(4000, seed=21), 0.0), (synth.fcc(600, 0.12, rc=2.5, seed=22), 0.0),
+             (_tiny(3000, seed=23), 0.4)]
+    for b, skin in cases:
+        u = O.canonical(b.pos, b.L)
+        nc = O.grid_dims(b.L, b.rc, skin, even=True)
+        assert (nc % 2 == 0).all()
+        Fs, Es, Ws, nps = O.forces_lc_fx(u, b.L, b.rc, nc)
+        Fp, Ep, Wp, npp, used = O.forces_loopex_omp(u, b.L, b.rc, nc, threads=threads)
+        assert used == threads
+        assert (Fp == Fs).all() and (Ep, Wp, npp) == (Es, Ws, nps)
+    Fb, Eb, Wb, npb = O.forces_brute_fx(O.canonical(cases[1][0].pos, cases[1][0].L),
+                                        cases[1][0].L, 2.5)
+    assert npb == O.forces_lc_fx(O.canonical(cases[1][0].pos, cases[1][0].L), cases[1][0].L,
+                                 2.5, O.grid_dims(cases[1][0].L, 2.5, even=True))[3]
+
+
+def test_loopex_omp_needs_even_counts():
+    b = _tiny(2000, seed=24)
+    u = O.canonical(b.pos, b.L)
+    nc = O.grid_dims(b.L, b.rc)
+    if (nc % 2 == 0).all():
+        nc = nc - 1
+    with pytest.raises(RuntimeError):
+        O.forces_loopex_omp(u, b.L, b.rc, nc)
+
+
 def test_lc_f64_matches_brute():
     b = _tiny(500, seed=12)
     u = O.canonical(b.pos, b.L)
