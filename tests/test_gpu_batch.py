@@ -77,6 +77,30 @@ def test_batch_build_cells_matches_oracle():
         assert (loc == O.cell_start(u, g.nc)).all(), k
 
 
+def test_batch_many_cells_three_pass_scan():
+    """Dilute boxes whose cells total more than 65,536, so the batched cell
+    build takes the three-pass scan: cell tables and forces bit-exact per box,
+    twice on one workspace (the counters are left cleared between builds)."""
+    boxes = synth.boxes(30, 1500, 3000, 0.04, 0.08, rc=2.5, seed=13)
+    grids = [lc.Grid(b.L, b.rc) for b in boxes]
+    pos = np.ascontiguousarray(np.concatenate([b.pos for b in boxes], axis=1))
+    batch = lc.Batch(grids, [b.n for b in boxes])
+    info = batch.info()
+    print("batch cells", info["ncell"], flush=True)
+    assert info["ncell"] > 65536
+    want = _oracle(boxes, grids)
+    ws = lc.Workspace(info["ntot"], info["ncell"])
+    posd = torch.from_numpy(pos).to(DEV)
+    ps, cst = batch.offsets()
+    for _ in range(2):
+        cs, perm, coord = batch.build_cells(posd, ws)
+        csh = cs.cpu().numpy()
+        for k, (b, g) in enumerate(zip(boxes, grids)):
+            loc = csh[cst[k]:cst[k + 1] + 1] - ps[k]
+            assert (loc == O.cell_start(O.canonical(b.pos, b.L), g.nc)).all(), k
+        _check(batch, boxes, grids, cs, perm, coord, ws, want, persistent=False)
+
+
 def test_batch_graph_replays_bit_identical():
     boxes, grids, pos = _batch_inputs(8, 500, 3000, seed=9)
     want = _oracle(boxes, grids)
