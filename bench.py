@@ -551,6 +551,27 @@ def bench_md(args):
     vel = torch.from_numpy(box.vel).to(dev)
     ids = torch.arange(box.n, dtype=torch.int32, device=dev)
     cs, perm, coord = lc.build_cells(g, pos, ws)  # sets the tile hint
+    # launch order: fixed, or heaviest groups first by the starting cell
+    # counts (any order gives the same bits; a crystal's counts barely move);
+    # 20 steps of each on copies of the state decide
+    sched_la = lc.Schedule(g, tune["kind"], block=tune["block"],
+                           cell_counts=lc.cell_counts_of(cs))
+    order_ms = {}
+    for name, sc in (("fixed", sched), ("load_aware", sched_la)):
+        p_, v_, i_ = pos.clone(), vel.clone(), ids.clone()
+        lc.verlet_step(g, sc, p_, v_, i_, ws, 0.005, 2, 10)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        lc.verlet_step(g, sc, p_, v_, i_, ws, 0.005, 20, 10)
+        t1.record()
+        torch.cuda.synchronize()
+        order_ms[name] = t0.elapsed_time(t1) / 20
+        del p_, v_, i_
+    load_aware = order_ms["load_aware"] < order_ms["fixed"]
+    if load_aware:
+        sched = sched_la
     nsteps = 100 if args.steps >= 10 else args.steps
     ws.clear_status()
     torch.cuda.synchronize()
@@ -578,7 +599,8 @@ def bench_md(args):
           pairs / (ms * 1e-3), "pairs/s", ms, args,
           {"workload": "LJ FCC+jitter N=4000000 rho=0.8 rc=2.5, MB T=1, dt=0.005, "
                        "rebuild every 10, skin 0.6, 54^3 cells", "nsteps": nsteps,
-           "schedule": tune["kind"], "block": tune["block"], "status_flags": st},
+           "schedule": tune["kind"], "block": tune["block"], "load_aware": load_aware,
+           "launch_order_trials_ms_per_step": order_ms, "status_flags": st},
           dtype="f32 pairs, int64 forces, f64 positions/velocities/energies",
           cell_build=build,
           energy={"E0_per_particle": etot[0] / box.n,
