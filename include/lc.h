@@ -471,7 +471,9 @@ int lc_batch_build_cells(const lc_batch *b, const double *pos,
 
 /* One force evaluation of every box: all work-groups of all boxes in ONE
  * sweep launch (persistent != 0: a grid sized to the device draws groups from
- * a ticket counter, largest first) plus one gather launch.  F [device] int64
+ * a ticket counter) plus one gather launch.  Groups are launched heaviest
+ * first: task count times the square of the box's particles per cell.
+ * F [device] int64
  * 3 x ntot; ew [device] int64 nbox x 3 {energy, virial, pairs} per box. */
 int lc_batch_forces(const lc_batch *b, const int32_t *cell_start,
                     const uint32_t *coord, int64_t *F, int64_t *ew,

@@ -2850,9 +2850,13 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
         gg.cstart = c0;
         b->geo.push_back(gg);
     }
-    // one launch: largest groups first
-    std::stable_sort(groups.begin(), groups.end(),
-                     [](const Grp &x, const Grp &y) { return x.ab.size() > y.ab.size(); });
+    // one launch, heaviest groups first: a group's pair work grows with its
+    // task count times the square of its box's particles per cell
+    std::stable_sort(groups.begin(), groups.end(), [&](const Grp &x, const Grp &y) {
+        const double dx = (double)boxes[x.box].n / (double)boxes[x.box].grid.ncell;
+        const double dy = (double)boxes[y.box].n / (double)boxes[y.box].grid.ncell;
+        return (double)x.ab.size() * dx * dx > (double)y.ab.size() * dy * dy;
+    });
     lcs::HostSchedule &h = b->h;
     h.write_mode = 3;
     h.grp_task.assign(1, 0);
