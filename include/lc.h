@@ -351,6 +351,30 @@ int lc_compute_forces_profiled(const lc_grid *g, const lc_schedule *s,
                                lc_workspace *ws, void *stream, double *sweep_ms,
                                double *phase_ms);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * force evaluation as lc_compute_forces, with no workspace.  Its scratch --
+ * the energy slots, a status word and the replica buffer of LC_SCHED_BUFFER
+ * -- is a file-scope device array of LC_NOALLOC_SCRATCH_BYTES that every
+ * device the library runs on holds until the process ends.  The call makes
+ * no hipMalloc, hipFree or other allocating call.
+ *   arguments as lc_compute_forces;
+ *   flags [device, optional] uint32: status bits (LC_FLAG_*) are OR-ed into
+ *         it (the caller clears it); NULL: the bits go to the scratch and are
+ *         not reported;
+ *   the LDS tile is sized from the mean density (no tile hint).
+ * LC_ECAPACITY, before anything is enqueued, when LC_SCHED_BUFFER's replica
+ * buffer (max_replicas x 24 B + 4 B per particle) exceeds the scratch (about
+ * 2.6 M particles at 8 replicas).  All calls on one device share the one
+ * array and each clears what it needs on `stream` first: calls that overlap
+ * on one device (other streams, other threads) race and give wrong results;
+ * serialise them. */
+#define LC_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int lc_compute_forces_noalloc(const lc_grid *g, const lc_schedule *s,
+                              const int32_t *cell_start, const uint32_t *coord, int64_t n,
+                              int64_t *F, int64_t *ew, int precision, uint32_t *flags,
+                              void *stream);
+
 /* Self-check of the sweep's fast reciprocal (the FP32 pair arithmetic takes
  * 1/r^2 as the IEEE quotient; pairs with 0.3 <= r^2 < 128 get it from the
  * hardware estimate plus one Newton-Raphson step).  Compares that device

@@ -30,6 +30,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1763,14 +1764,24 @@ static int ensure_pbuf(lc_workspace *ws, int64_t need) {
     return LC_OK;
 }
 
-static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *cell_start,
-                       const uint32_t *coord, int64_t n, int64_t *F, int64_t *ew, int precision,
-                       lc_workspace *ws, hipStream_t st, hipEvent_t *ev = nullptr) {
+// Device memory a force evaluation uses beyond its inputs and outputs: the
+// spread energy slots (zero on entry, left zero), the status word, the
+// replica buffer of buffer + reduce (pbuf_elems(rmax, n) elements, only read
+// for that kind) and the tile sizing hint.
+struct SweepScratch {
+    long long *part;
+    uint32_t *flags;
+    long long *pbuf;
+    int32_t max_per_cell;
+};
+
+static int forces_run(const lc_grid *g, const lc_schedule *s, const int32_t *cell_start,
+                      const uint32_t *coord, int64_t n, int64_t *F, int64_t *ew, int precision,
+                      const SweepScratch &sc, hipStream_t st, hipEvent_t *ev) {
     const bool buffered = s->h.write_mode == 3;
     const bool fullshell = s->h.write_mode == 4;  // writes every particle itself
     int rc = (buffered || fullshell) ? LC_OK : fill64((long long *)F, 3 * n, st);
     if (rc) return rc;
-    if (buffered && (rc = ensure_pbuf(ws, pbuf_elems(s->h.rmax, n)))) return rc;
     const int nphase = (int)s->h.phase_grp.size() - 1;
     SweepArgs a;
     a.grp_task = s->grp_task;
@@ -1782,30 +1793,31 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     a.n = n;
     a.F = (long long *)F;
     a.foot_rep = s->foot_rep;
-    a.pbuf = ws->pbuf;
-    a.rcnt = buffered ? rcnt_of(ws, s->h.rmax, n) : nullptr;
+    a.pbuf = sc.pbuf;
+    a.rcnt = buffered ? (int *)(sc.pbuf + (int64_t)s->h.rmax * 3 * n) : nullptr;
     a.fx_task = s->fx_task;
     a.fx_foot = s->fx_foot;
     a.fx_rep = s->fx_rep;
     a.fx_cnt = s->fx_cnt;
     a.fx_tmax = s->fx_tmax;
     a.fx_fmax = s->fx_fmax;
-    a.part = (long long *)ws->part;
+    a.part = sc.part;
     a.grp_box = nullptr;
     a.ppar = nullptr;
     a.ew_box = nullptr;
     a.ticket = nullptr;
     a.ngroups = 0;
-    a.flags = ws->flags;
+    a.flags = sc.flags;
     a.pp = pair_params(g);
     // LDS tile: expected particles of the largest footprint with headroom
     const double mean = g->ncell > 0 ? (double)n / (double)g->ncell : 0.0;
     // the filter stages cells of up to kFFCell particles; denser cells take
     // the unfiltered kernel rather than the global fallback
-    const bool dense = ws->max_per_cell > 0 ? ws->max_per_cell > kFFCell : mean > 0.5 * kFFCell;
+    const int32_t hint = sc.max_per_cell;
+    const bool dense = hint > 0 ? hint > kFFCell : mean > 0.5 * kFFCell;
     const bool ff = a.pp.thr16 > 0 && precision == LC_PREC_FP32 && s->h.write_mode != 2 && !dense;
-    const double need = ws->max_per_cell > 0 ? (double)ws->max_per_cell * s->h.max_cells * 0.8
-                                             : mean * s->h.max_cells * 1.35;
+    const double need = hint > 0 ? (double)hint * s->h.max_cells * 0.8
+                                 : mean * s->h.max_cells * 1.35;
     int cap;
     if (ff)
         cap = need <= 768 ? 768 : (need <= 1024 ? 1024 : 2048);
@@ -1825,15 +1837,32 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     }
     if (buffered && n > 0) {  // gather + the energy sums in one launch
         hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((n + 255) / 256 + 1)), dim3(256), 0,
-                           st, (const long long *)ws->pbuf, (const int *)a.rcnt, n,
-                           (long long *)F, (long long *)ws->part, (long long *)ew);
+                           st, (const long long *)sc.pbuf, (const int *)a.rcnt, n,
+                           (long long *)F, sc.part, (long long *)ew);
         LAUNCHCHK("k_gather_partials");
         return LC_OK;
     }
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (long long *)ws->part, 3,
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, sc.part, 3,
                        (long long *)ew, fullshell ? 1 : 0);
     LAUNCHCHK("k_reduce_parts");
     return LC_OK;
+}
+
+// A force evaluation with the workspace's scratch; buffer + reduce grows
+// the workspace's replica buffer on first use.
+static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *cell_start,
+                       const uint32_t *coord, int64_t n, int64_t *F, int64_t *ew, int precision,
+                       lc_workspace *ws, hipStream_t st, hipEvent_t *ev = nullptr) {
+    if (s->h.write_mode == 3) {
+        int rc = ensure_pbuf(ws, pbuf_elems(s->h.rmax, n));
+        if (rc) return rc;
+    }
+    SweepScratch sc;
+    sc.part = (long long *)ws->part;
+    sc.flags = ws->flags;
+    sc.pbuf = ws->pbuf;
+    sc.max_per_cell = ws->max_per_cell;
+    return forces_run(g, s, cell_start, coord, n, F, ew, precision, sc, st, ev);
 }
 
 // ---------------------------------------------------------------------------
@@ -2385,6 +2414,71 @@ extern "C" int lc_compute_forces(const lc_grid *g, const lc_schedule *s, const i
     int rc = check_ws(ws, 0, 0);
     if (rc) return rc;
     return forces_impl(g, s, cell_start, coord, n, F, ew, precision, ws, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Force evaluation without allocation: the scratch lives in a file-scope
+// device array, one copy per device, held until the process ends.
+// ---------------------------------------------------------------------------
+
+// Layout: the spread energy slots (kPartSlots x 3 int64), the status word
+// (one int64 slot), then the replica buffer of buffer + reduce.
+constexpr int64_t kScratchPartElems = 3 * kPartSlots + 1;
+constexpr int64_t kScratchPbufOff = 24832;  // bytes, 256-aligned, past the slots
+static_assert(kScratchPartElems * 8 <= kScratchPbufOff && kScratchPbufOff % 256 == 0,
+              "scratch layout");
+static __device__ __align__(256) unsigned char scratch[LC_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device
+
+// The device address of the current device's `scratch` (looked up once per
+// device, with that device current).
+static int scratch_address(void **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LC_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(LC_EHIP, "hipGetSymbolAddress(scratch) gave NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LC_OK;
+}
+
+extern "C" int lc_compute_forces_noalloc(const lc_grid *g, const lc_schedule *s,
+                                         const int32_t *cell_start, const uint32_t *coord,
+                                         int64_t n, int64_t *F, int64_t *ew, int precision,
+                                         uint32_t *flags, void *stream) {
+    if (!g || !s || !cell_start || !F || !ew || (n > 0 && !coord))
+        return fail(LC_EINVAL, "lc_compute_forces_noalloc: null argument");
+    if (precision != LC_PREC_FP32 && precision != LC_PREC_FP64)
+        return fail(LC_EINVAL, "lc_compute_forces_noalloc: precision");
+    if (s->nc[0] != g->nc[0] || s->nc[1] != g->nc[1] || s->nc[2] != g->nc[2])
+        return fail(LC_EINVAL, "lc_compute_forces_noalloc: schedule built for another grid");
+    if (n < 0 || n >= 2147483647LL) return fail(LC_EINVAL, "lc_compute_forces_noalloc: bad n");
+    const int64_t pbuf_bytes = s->h.write_mode == 3 ? 8 * pbuf_elems(s->h.rmax, n) : 0;
+    if (pbuf_bytes > (int64_t)LC_NOALLOC_SCRATCH_BYTES - kScratchPbufOff)
+        return fail(LC_ECAPACITY,
+                    "lc_compute_forces_noalloc: the replica buffer needs %lld bytes, the static "
+                    "scratch holds %lld",
+                    (long long)pbuf_bytes, (long long)(LC_NOALLOC_SCRATCH_BYTES - kScratchPbufOff));
+    void *base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    SweepScratch sc;
+    sc.part = (long long *)base;
+    sc.flags = flags ? flags : (uint32_t *)(sc.part + 3 * kPartSlots);
+    sc.pbuf = (long long *)((unsigned char *)base + kScratchPbufOff);
+    sc.max_per_cell = 0;
+    // the slots and the status word keep what the last call left: clear them
+    if ((rc = fill64(sc.part, kScratchPartElems, st))) return rc;
+    return forces_run(g, s, cell_start, coord, n, F, ew, precision, sc, st, nullptr);
 }
 
 __global__ __launch_bounds__(256) void k_selftest_recip(uint32_t lo, uint32_t n,

@@ -92,6 +92,7 @@ SYMBOLS = {
     "lc_compute_forces": ([P, P, P, P, I64, P, P, INT, P, P], INT),
     "lc_compute_forces_dataflow": ([P, P, INT, P, P, I64, P, P, ctypes.c_double, P, P], INT),
     "lc_compute_forces_profiled": ([P, P, P, P, I64, P, P, INT, P, P, P, P], INT),
+    "lc_compute_forces_noalloc": ([P, P, P, P, I64, P, P, INT, P, P], INT),
     "lc_verlet_step": ([P, P, P, P, P, I64, P, P, P, P, ctypes.c_double, INT,
                         INT, P, P, P], INT),
     "lc_kinetic_energy": ([P, I64, P, P, P], INT),
@@ -384,6 +385,20 @@ def compute_forces(grid: Grid, sched: Schedule, cell_start, coord, ws: Workspace
     _chk(lib().lc_compute_forces(grid.ptr, sched.ptr, _p(cell_start), _p(coord), n,
                                  _p(F), _p(ew), PREC[precision], ws.ptr,
                                  _stream(stream)))
+    return F, ew
+
+
+def compute_forces_noalloc(grid: Grid, sched: Schedule, cell_start, coord, F, ew,
+                           precision: str = "fp32", flags=None, stream=None):
+    """lc_compute_forces_noalloc: the force evaluation of compute_forces with
+    no workspace and no allocation; F (int64 (3, N)) and ew (int64 [3]) are
+    caller-given outputs, flags an optional device uint32/int32 [1] that the
+    status bits are OR-ed into."""
+    n = coord.shape[1]
+    _chk(lib().lc_compute_forces_noalloc(grid.ptr, sched.ptr, _p(cell_start), _p(coord), n,
+                                         _p(F), _p(ew), PREC[precision],
+                                         _p(flags),
+                                         _stream(stream)))
     return F, ew
 
 
