@@ -64,6 +64,7 @@ extern "C" {
 #define LC_EOVERFLOW (-5) /* fixed-point range exceeded (device flag)       */
 #define LC_EDISP (-6)     /* a particle moved more than skin/2 (device flag)*/
 #define LC_ECAPACITY (-7) /* a size exceeds a documented maximum            */
+#define LC_EABORT (-8)    /* a dataflow evaluation was abandoned (flag)     */
 
 /* Device status flags (lc_workspace_status). */
 #define LC_FLAG_OVERFLOW 1u  /* |quantised term| >= 2^62 or r2 == 0          */
@@ -144,6 +145,15 @@ int lc_workspace_set_tile_hint(lc_workspace *ws, int32_t max_per_cell);
 int lc_workspace_clear_status(lc_workspace *ws, void *stream);
 /* Synchronise `stream` and return the device status flags (LC_FLAG_*). */
 int lc_workspace_status(lc_workspace *ws, void *stream, uint32_t *flags);
+/* Synchronise `stream` and turn the status flags into a status: LC_EOVERFLOW
+ * when a pair term left the fixed-point range (forces wrong), else LC_EABORT
+ * when a dataflow evaluation was abandoned (forces incomplete), else LC_EDISP
+ * when a Verlet run moved a particle more than skin / 2 between rebuilds
+ * (pairs may have been missed since), else LC_OK (LC_FLAG_FALLBACK is
+ * information only).  The flags stay set until lc_workspace_clear_status.
+ * Device calls return before their kernels run, so this is where the three
+ * device-side failures surface as status codes. */
+int lc_workspace_check(lc_workspace *ws, void *stream);
 
 /* ---- a1: cell build (Sec. IV) ------------------------------------------- */
 
@@ -286,9 +296,11 @@ typedef struct lc_sd_result {
     double speedup;   /* S = T / cp  (Eq. 1)                                */
     double degree;    /* cp / T, 1 = fully serial                           */
     int32_t n;        /* tasks per stencil                                  */
-    int32_t delta;    /* stencil displacement Delta (0 for LC_SCHED_LOOPEX) */
-    double s_eq2;     /* Eq. 2 with k = number of cells                     */
-    double s_max;     /* Eq. 3: n / Delta                                   */
+    int32_t delta;    /* stencil displacement Delta (0 for LC_SCHED_LOOPEX:
+                         no stencil displacement chains the cells)          */
+    double s_eq2;     /* Eq. 2 with k = number of cells (k itself when
+                         Delta = 0)                                         */
+    double s_max;     /* Eq. 3: n / Delta (+infinity when Delta = 0)        */
 } lc_sd_result;
 
 /* [host only] Critical path of the task DAG of a creation order under the
@@ -327,7 +339,10 @@ int lc_serialization_degree_weighted(const int32_t dims[3], int kind,
                           quantisation -- a precision reference             */
 
 /* One Lennard-Jones force evaluation over all cell-cell tasks of s, phase by
- * phase.  Inputs come from lc_build_cells on the same grid:
+ * phase: the link-cell sweep of Sec. IV, where each task is one cell-cell
+ * interaction of the half stencil (Fig. 3) that, with Newton's third law,
+ * adds every pair's force into both of its cells.  Inputs come from
+ * lc_build_cells on the same grid:
  *   cell_start [device] int32 ncell+1;  coord [device] uint32 3 x N
  *   F   [device] int64 3 x N, cell-sorted order, OVERWRITTEN with the force
  *   ew  [device] int64 [3]: OVERWRITTEN with {energy, virial, pairs in
@@ -479,6 +494,24 @@ typedef struct lc_batch_info {
  * the current device.  modes: per-box LC_BATCH_* (NULL = all AUTO). */
 int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t *modes,
                     lc_batch **out);
+
+#define LC_BATCH_WRITE_BUFFER 0 /* each group stores into its replica slots,
+                                   a gather sums them (Sec. VI strategy 3)  */
+#define LC_BATCH_WRITE_ATOMIC 1 /* the same groups add their LDS sums into F
+                                   with global int64 atomics, no gather (the
+                                   tile-atomics baseline)                    */
+typedef struct lc_batch_opts {
+    int32_t tile;       /* LDS tile (particles) a split box's block shape is
+                           sized for: the largest blocks of {2,3,3}, {1,3,3},
+                           {1,2,2}, {1,1,2}, {1,1,1} whose footprint is
+                           expected (box density + 35%) to fit; 768 (0 =
+                           default, three work-groups per CU), 1024 or 2048 */
+    int32_t write_mode; /* LC_BATCH_WRITE_*                                 */
+} lc_batch_opts;
+/* lc_batch_create with options (NULL = defaults); LC_EINVAL on other tile
+ * sizes or write modes.  The autotuner tries the tile sizes. */
+int lc_batch_create_ex(const lc_box_desc *boxes, int nbox, const int32_t *modes,
+                       const lc_batch_opts *opts, lc_batch **out);
 int lc_batch_info_get(const lc_batch *b, lc_batch_info *out);
 /* [host] pstart, cstart: host int64 arrays of nbox + 1 entries. */
 int lc_batch_offsets(const lc_batch *b, int64_t *pstart, int64_t *cstart);
@@ -505,7 +538,12 @@ int lc_batch_forces(const lc_batch *b, const int32_t *cell_start,
 
 /* HIP graph of lc_batch_forces with fixed buffers, captured on `stream`
  * (which must not be the legacy null stream); replays are bit-identical
- * evaluations.  lc_graph_launch enqueues one replay on `stream`. */
+ * evaluations.  lc_graph_launch enqueues one replay on `stream`.  The graph
+ * holds the addresses of the batch's tables, of ws's scratch and of the
+ * caller's buffers: all of them must outlive it (free the graph first).
+ * While it lives, ws's replica buffer cannot grow: a call that would need a
+ * larger one on ws (lc_compute_forces / lc_batch_forces / another capture)
+ * returns LC_ECAPACITY instead of moving it. */
 typedef struct lc_graph lc_graph;
 int lc_batch_graph_create(const lc_batch *b, const int32_t *cell_start,
                           const uint32_t *coord, int64_t *F, int64_t *ew,

@@ -5,9 +5,10 @@ the fastest: the cell grid (cell side rc, optionally widened, cell counts
 rounded to even or not), the conflict-free schedule (BLOCK8 colouring or
 BUFFER buffer + reduce; ATOMIC_TILE when atomics are allowed) and the block
 shape (for BLOCK8 the smallest block per axis, for the uncoloured kinds the
-largest).  For a batch of boxes it picks how boxes
-are split (whole-box work-groups where they fit, or blocks) and whether the
-sweep runs as a persistent launch.  Results are cached in a JSON file keyed
+largest).  For a batch of boxes it picks the cell grids (side rc or widened),
+the LDS tile the split boxes' block shapes are sized for, how boxes are split
+(whole-box work-groups where they fit, or blocks) and whether the sweep runs
+as a persistent launch.  Results are cached in a JSON file keyed
 by the device name and a bucket of (N, density, rc).
 """
 from __future__ import annotations
@@ -214,40 +215,55 @@ def tune_shape(grid, pos: torch.Tensor, kinds=BOX_KINDS_CONFLICT_FREE, reps: int
     return out
 
 
-def tune_batch(grids, ns, pos_all: torch.Tensor, reps: int = 5) -> dict:
-    """Pick the box split (auto: whole-box work-groups where they fit, or
-    blocks everywhere) and persistent vs one-group-per-work-group launch for a
-    batch.  Returns {"modes": str, "persistent": bool, "ms": float,
-    "trials": [...]}."""
+BATCH_TILES = (768, 1024, 2048)
+
+
+def tune_batch(grids, ns, pos_all: torch.Tensor, reps: int = 5, grid_sets=None,
+               tiles=BATCH_TILES) -> dict:
+    """Pick, for a batch, the cell grids (``grid_sets``: name -> one grid per
+    box, e.g. cells of side rc and cells widened by a skin; default: the
+    given ``grids`` as "given"), the LDS tile the split boxes' block shapes
+    are sized for (``tiles``), the box split (auto: whole-box work-groups
+    where they fit, or blocks everywhere) and persistent vs
+    one-group-per-work-group launch, all with buffer + reduce write-back.
+    Returns {"grid", "tile", "modes", "persistent", "ms", "trials": [...]}."""
+    if grid_sets is None:
+        grid_sets = {"given": grids}
     trials = []
     best = None
-    for modes in ("auto", "blocks"):
-        batch = lc.Batch(grids, ns, None if modes == "auto" else ["blocks"] * len(ns))
-        info = batch.info()
-        ws = lc.Workspace(info["ntot"], info["ncell"])
-        cs, perm, coord = batch.build_cells(pos_all, ws)
-        F = torch.empty((3, info["ntot"]), dtype=torch.int64, device=pos_all.device)
-        ew = torch.empty((len(ns), 3), dtype=torch.int64, device=pos_all.device)
-        for persistent in (True, False):
-            for _ in range(2):
-                batch.forces(cs, coord, ws, F, ew, persistent)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
-                batch.forces(cs, coord, ws, F, ew, persistent)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            rec = {"modes": modes, "persistent": persistent, "ms": ms,
-                   "nwhole": info["nwhole"], "ngroup": info["ngroup"]}
-            trials.append(rec)
-            if best is None or ms < best["ms"]:
-                best = rec
-        batch.close()
-        ws.close()
+    for gname, gset in grid_sets.items():
+        for tile in tiles:
+            for modes in ("auto", "blocks"):
+                batch = lc.Batch(gset, ns, None if modes == "auto" else ["blocks"] * len(ns),
+                                 tile=tile)
+                info = batch.info()
+                ws = lc.Workspace(info["ntot"], info["ncell"])
+                cs, perm, coord = batch.build_cells(pos_all, ws)
+                F = torch.empty((3, info["ntot"]), dtype=torch.int64, device=pos_all.device)
+                ew = torch.empty((len(ns), 3), dtype=torch.int64, device=pos_all.device)
+                for persistent in (True, False):
+                    for _ in range(2):
+                        batch.forces(cs, coord, ws, F, ew, persistent)
+                    torch.cuda.synchronize()
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(reps):
+                        batch.forces(cs, coord, ws, F, ew, persistent)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ms = e0.elapsed_time(e1) / reps
+                    rec = {"grid": gname, "tile": tile, "modes": modes,
+                           "persistent": persistent, "ms": ms, "nwhole": info["nwhole"],
+                           "ngroup": info["ngroup"], "lds_tile": info["lds_tile"],
+                           "fallback": bool(ws.status() & lc.FLAG_FALLBACK)}
+                    trials.append(rec)
+                    if not rec["fallback"] and (best is None or ms < best["ms"]):
+                        best = rec
+                batch.close()
+                ws.close()
+    if best is None:  # every trial spilled out of its tile: take the fastest
+        best = min(trials, key=lambda t: t["ms"])
     out = dict(best)
     out["trials"] = trials
     return out

@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -94,6 +95,7 @@ struct lc_workspace {
     int32_t max_per_cell = 0;    // tile sizing hint (0: mean density)
     int32_t *df_sync = nullptr;  // dataflow: per-cell counter or lock
     int32_t *df_ctl = nullptr;   // dataflow: ticket, abort
+    int live_graphs = 0;         // graphs captured with this workspace, not yet freed
 };
 
 struct lc_schedule {
@@ -1755,6 +1757,12 @@ static int *rcnt_of(lc_workspace *ws, int rmax, int64_t n) {
 
 static int ensure_pbuf(lc_workspace *ws, int64_t need) {
     if (need <= ws->pbuf_elems) return LC_OK;
+    // a captured graph holds the current buffer's address
+    if (ws->live_graphs > 0)
+        return fail(LC_ECAPACITY,
+                    "the workspace's replica buffer would have to grow (%lld -> %lld elements) "
+                    "while %d graph(s) captured with it are alive",
+                    (long long)ws->pbuf_elems, (long long)need, ws->live_graphs);
     (void)hipFree(ws->pbuf);
     ws->pbuf = nullptr;
     ws->pbuf_elems = 0;
@@ -2077,6 +2085,19 @@ extern "C" int lc_workspace_status(lc_workspace *ws, void *stream, uint32_t *fla
     return LC_OK;
 }
 
+extern "C" int lc_workspace_check(lc_workspace *ws, void *stream) {
+    uint32_t f = 0;
+    int rc = lc_workspace_status(ws, stream, &f);
+    if (rc) return rc;
+    if (f & LC_FLAG_OVERFLOW)
+        return fail(LC_EOVERFLOW, "a quantised pair term left the fixed-point range (or r2 == 0)");
+    if (f & LC_FLAG_ABORT)
+        return fail(LC_EABORT, "a dataflow wait expired: the evaluation was abandoned");
+    if (f & LC_FLAG_DISP)
+        return fail(LC_EDISP, "a particle moved more than skin / 2 since the last cell rebuild");
+    return LC_OK;
+}
+
 static int check_ws(const lc_workspace *ws, int64_t n, int64_t ncell) {
     if (!ws) return fail(LC_EINVAL, "null workspace");
     if (n > ws->max_n || ncell > ws->max_cells)
@@ -2348,13 +2369,13 @@ extern "C" int lc_serialization_degree(const int32_t dims[3], int kind, const in
     out->speedup = cp ? (double)out->tasks / (double)cp : 0.0;
     out->degree = out->tasks ? (double)cp / (double)out->tasks : 0.0;
     out->n = (int32_t)order.size();
-    if (kind != LC_SCHED_LOOPEX) {
-        const int delta = lcs::delta_rule(order);
-        out->delta = delta;
-        const double k = (double)ncell, nn = (double)order.size();
-        out->s_eq2 = nn * k / (nn + delta * (k - 1.0));
-        out->s_max = nn / delta;
-    }
+    // loop exchange has no stencil displacement (Delta = 0): Eq. 2 then
+    // gives k (every cell at once) and Eq. 3 diverges
+    const int delta = kind == LC_SCHED_LOOPEX ? 0 : lcs::delta_rule(order);
+    out->delta = delta;
+    const double k = (double)ncell, nn = (double)order.size();
+    out->s_eq2 = nn * k / (nn + delta * (k - 1.0));
+    out->s_max = delta > 0 ? nn / delta : HUGE_VAL;
     if (level_hist) {
         for (int64_t l = 0; l < hist_len; ++l) level_hist[l] = 0;
         for (int32_t l : level)
@@ -2774,6 +2795,7 @@ struct lc_batch {
     int nwhole = 0;
     int cap = 1024;
     bool ff = true;  // every box admits the integer candidate filter
+    int wmode = 3;   // sweep write mode: 3 replica buffer + gather, 1 atomic write-back
     int64_t ntot = 0, ncell = 0;
     std::vector<int64_t> pstart, cstart;
     lcs::HostSchedule h;  // combined groups, global cell ids
@@ -2792,6 +2814,7 @@ struct lc_batch {
 struct lc_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    lc_workspace *ws = nullptr;  // its replica buffer must not move while the graph lives
 };
 
 extern "C" void lc_batch_free(lc_batch *b) {
@@ -2825,8 +2848,20 @@ static int upload(T **dst, const std::vector<T> &v) {
 
 extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t *modes,
                                lc_batch **out) {
+    return lc_batch_create_ex(boxes, nbox, modes, nullptr, out);
+}
+
+extern "C" int lc_batch_create_ex(const lc_box_desc *boxes, int nbox, const int32_t *modes,
+                                  const lc_batch_opts *opts, lc_batch **out) {
     if (!boxes || nbox < 1 || !out) return fail(LC_EINVAL, "lc_batch_create: bad arguments");
+    const int tile = opts && opts->tile ? opts->tile : 768;
+    const int wm = opts ? opts->write_mode : LC_BATCH_WRITE_BUFFER;
+    if (tile != 768 && tile != 1024 && tile != 2048)
+        return fail(LC_EINVAL, "lc_batch_create_ex: tile %d (768, 1024 or 2048)", tile);
+    if (wm != LC_BATCH_WRITE_BUFFER && wm != LC_BATCH_WRITE_ATOMIC)
+        return fail(LC_EINVAL, "lc_batch_create_ex: write mode %d", wm);
     lc_batch *b = new lc_batch();
+    b->wmode = wm == LC_BATCH_WRITE_ATOMIC ? 1 : 3;
     b->nbox = nbox;
     b->pstart.assign(1, 0);
     b->cstart.assign(1, 0);
@@ -2892,9 +2927,9 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
             b->nwhole++;
         } else {
             // the largest blocks whose footprint is expected (box density,
-            // 35% headroom) to fit a 768-particle tile, which runs three
-            // work-groups per CU; dense boxes take smaller blocks (more
-            // replicas)
+            // 35% headroom) to fit the tile (768 particles by default, which
+            // runs three work-groups per CU); dense boxes take smaller blocks
+            // (more replicas)
             static const int32_t kShapes[][3] = {{2, 3, 3}, {1, 3, 3}, {1, 2, 2}, {1, 1, 2},
                                                  {1, 1, 1}};
             lcs::HostSchedule hb;
@@ -2902,7 +2937,7 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
             int rc = 0;
             for (const auto &shape : kShapes) {
                 rc = lcs::build_schedule(g.nc, LC_SCHED_BUFFER, nullptr, 0, hb, err, shape);
-                if (rc || dens * hb.max_cells * 1.35 <= 768.0) break;
+                if (rc || dens * hb.max_cells * 1.35 <= (double)tile) break;
             }
             if (rc) {
                 lc_batch_free(b);
@@ -2952,7 +2987,7 @@ extern "C" int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t
         return (double)x.ab.size() * dx * dx > (double)y.ab.size() * dy * dy;
     });
     lcs::HostSchedule &h = b->h;
-    h.write_mode = 3;
+    h.write_mode = b->wmode;
     h.grp_task.assign(1, 0);
     h.grp_foot.assign(1, 0);
     h.phase_grp = {0};
@@ -3053,6 +3088,8 @@ static int batch_forces_impl(const lc_batch *b, const int32_t *cell_start, const
                              hipStream_t st) {
     int rc = fill64((long long *)ew, 3 * (int64_t)b->nbox, st);
     if (rc) return rc;
+    const bool atomic = b->wmode == 1;  // adds into F: clear it first
+    if (atomic && (rc = fill64((long long *)F, 3 * b->ntot, st))) return rc;
     const int ng = (int)b->grp_box.size();
     SweepArgs a;
     memset(&a, 0, sizeof a);
@@ -3066,8 +3103,8 @@ static int batch_forces_impl(const lc_batch *b, const int32_t *cell_start, const
     a.n = b->ntot;
     a.F = (long long *)F;
     a.foot_rep = b->d_foot_rep;
-    a.pbuf = ws->pbuf;
-    a.rcnt = rcnt_of(ws, b->h.rmax, b->ntot);
+    a.pbuf = atomic ? nullptr : ws->pbuf;
+    a.rcnt = atomic ? nullptr : rcnt_of(ws, b->h.rmax, b->ntot);
     a.fx_task = nullptr;
     a.fx_foot = a.fx_rep = a.fx_cnt = nullptr;
     a.fx_tmax = a.fx_fmax = 0;
@@ -3083,8 +3120,9 @@ static int batch_forces_impl(const lc_batch *b, const int32_t *cell_start, const
         if ((rc = fill32(b->d_ticket, 1, st))) return rc;
         tk = b->d_ticket;
     }
-    if (ng > 0 && (rc = launch_sweep(b->cap, 3, false, b->ff, a, ng, b->ncu, tk, st))) return rc;
-    if (b->ntot > 0) {
+    if (ng > 0 && (rc = launch_sweep(b->cap, b->wmode, false, b->ff, a, ng, b->ncu, tk, st)))
+        return rc;
+    if (!atomic && b->ntot > 0) {
         hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((b->ntot + 255) / 256)), dim3(256), 0,
                            st, (const long long *)ws->pbuf, (const int *)a.rcnt, b->ntot,
                            (long long *)F, (long long *)nullptr, (long long *)nullptr);
@@ -3100,7 +3138,7 @@ extern "C" int lc_batch_forces(const lc_batch *b, const int32_t *cell_start, con
         return fail(LC_EINVAL, "lc_batch_forces: null argument");
     int rc = check_ws(ws, b->ntot, b->ncell);
     if (rc) return rc;
-    if ((rc = ensure_pbuf(ws, pbuf_elems(b->h.rmax, b->ntot)))) return rc;
+    if (b->wmode == 3 && (rc = ensure_pbuf(ws, pbuf_elems(b->h.rmax, b->ntot)))) return rc;
     return batch_forces_impl(b, cell_start, coord, F, ew, persistent, ws, (hipStream_t)stream);
 }
 
@@ -3111,7 +3149,8 @@ extern "C" int lc_batch_graph_create(const lc_batch *b, const int32_t *cell_star
     if (!b || !out || !stream) return fail(LC_EINVAL, "lc_batch_graph_create: bad arguments");
     int rc = check_ws(ws, b->ntot, b->ncell);
     if (rc) return rc;
-    if ((rc = ensure_pbuf(ws, pbuf_elems(b->h.rmax, b->ntot)))) return rc;  // outside capture
+    if (b->wmode == 3 && (rc = ensure_pbuf(ws, pbuf_elems(b->h.rmax, b->ntot))))
+        return rc;  // outside capture
     hipStream_t st = (hipStream_t)stream;
     lc_graph *gr = new lc_graph();
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -3128,6 +3167,8 @@ extern "C" int lc_batch_graph_create(const lc_batch *b, const int32_t *cell_star
         delete gr;
         return fail(LC_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
+    gr->ws = ws;
+    ws->live_graphs++;
     *out = gr;
     return LC_OK;
 }
@@ -3140,6 +3181,7 @@ extern "C" int lc_graph_launch(lc_graph *gr, void *stream) {
 
 extern "C" void lc_graph_free(lc_graph *gr) {
     if (!gr) return;
+    if (gr->ws) gr->ws->live_graphs--;
     if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
     if (gr->graph) (void)hipGraphDestroy(gr->graph);
     delete gr;

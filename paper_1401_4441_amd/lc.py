@@ -76,6 +76,7 @@ SYMBOLS = {
     "lc_workspace_clear_status": ([P, P], INT),
     "lc_workspace_set_tile_hint": ([P, ctypes.c_int32], INT),
     "lc_workspace_status": ([P, P, P], INT),
+    "lc_workspace_check": ([P, P], INT),
     "lc_build_cells": ([P, P, I64, P, P, P, P, P], INT),
     "lc_gather": ([P, I64, P, P, P, P, P], INT),
     "lc_make_schedule": ([P, INT, P, INT, P], INT),
@@ -98,6 +99,7 @@ SYMBOLS = {
     "lc_kinetic_energy": ([P, I64, P, P, P], INT),
     "lc_selftest_recip": ([ctypes.c_uint32, ctypes.c_uint32, P], INT),
     "lc_batch_create": ([P, INT, P, P], INT),
+    "lc_batch_create_ex": ([P, INT, P, P, P], INT),
     "lc_batch_info_get": ([P, P], INT),
     "lc_batch_offsets": ([P, P, P], INT),
     "lc_batch_free": ([P], None),
@@ -198,6 +200,7 @@ class Grid:
 
 class Workspace:
     def __init__(self, max_n: int, max_cells: int):
+        self._live_graphs = 0  # graphs captured with this workspace, alive
         self._h = ctypes.c_void_p()
         _chk(lib().lc_workspace_create(int(max_n), int(max_cells),
                                        ctypes.byref(self._h)))
@@ -217,7 +220,14 @@ class Workspace:
         _chk(lib().lc_workspace_status(self._h, _stream(stream), ctypes.byref(v)))
         return int(v.value)
 
+    def check(self, stream=None):
+        """Synchronise and raise LCError (-5 overflow, -8 abandoned dataflow
+        evaluation, -6 displacement beyond skin / 2) if a device flag is set."""
+        _chk(lib().lc_workspace_check(self._h, _stream(stream)))
+
     def close(self):
+        if self._live_graphs:
+            raise LCError(-7, "the workspace is held by a live graph: close the graph first")
         if self._h:
             lib().lc_workspace_destroy(self._h)
             self._h = ctypes.c_void_p()
@@ -546,21 +556,36 @@ class _BatchInfo(ctypes.Structure):
 
 
 BATCH_MODES = {"auto": 0, "whole": 1, "blocks": 2}
+BATCH_WRITE = {"buffer": 0, "atomic": 1}
+
+
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("write_mode", ctypes.c_int32)]
 
 
 class Graph:
-    """A captured HIP graph of one batched force evaluation."""
+    """A captured HIP graph of one batched force evaluation.  It keeps the
+    batch, the workspace and the buffers it was captured with alive (the
+    graph holds their device addresses) until it is closed."""
 
-    def __init__(self, handle):
+    def __init__(self, handle, batch, ws, buffers):
         self._h = handle
+        self._batch, self._ws, self._bufs = batch, ws, buffers
+        batch._live_graphs += 1
+        ws._live_graphs += 1
 
     def launch(self, stream=None):
+        if not self._h:
+            raise LCError(-1, "graph is closed")
         _chk(lib().lc_graph_launch(self._h, _stream(stream)))
 
     def close(self):
         if self._h:
             lib().lc_graph_free(self._h)
             self._h = ctypes.c_void_p()
+            self._batch._live_graphs -= 1
+            self._ws._live_graphs -= 1
+            self._batch = self._ws = self._bufs = None
 
     def __del__(self):
         try:
@@ -572,8 +597,13 @@ class Graph:
 class Batch:
     """Many independent periodic boxes evaluated in one launch."""
 
-    def __init__(self, grids, ns, modes=None):
+    def __init__(self, grids, ns, modes=None, tile: int = 0, write: str = "buffer"):
+        """tile: LDS tile (particles) the split boxes' blocks are sized for
+        (768 = 0 default, 1024, 2048); write: "buffer" (replica slots and a
+        gather, Sec. VI strategy 3) or "atomic" (the same groups with global
+        atomic write-back, the tile-atomics baseline)."""
         import numpy as np
+        self._live_graphs = 0
         nbox = len(grids)
         arr = (_BoxDesc * nbox)()
         for k, (g, n) in enumerate(zip(grids, ns)):
@@ -589,7 +619,11 @@ class Batch:
         else:
             mp = None
         self._h = ctypes.c_void_p()
-        _chk(lib().lc_batch_create(ctypes.cast(arr, P), nbox, mp, ctypes.byref(self._h)))
+        opts = _BatchOpts()
+        opts.tile = int(tile)
+        opts.write_mode = BATCH_WRITE[write]
+        _chk(lib().lc_batch_create_ex(ctypes.cast(arr, P), nbox, mp, ctypes.byref(opts),
+                                      ctypes.byref(self._h)))
 
     @property
     def ptr(self):
@@ -637,9 +671,11 @@ class Batch:
         _chk(lib().lc_batch_graph_create(self._h, _p(cell_start), _p(coord), _p(F), _p(ew),
                                          1 if persistent else 0, ws.ptr, _stream(stream),
                                          ctypes.byref(h)))
-        return Graph(h)
+        return Graph(h, self, ws, (cell_start, coord, F, ew))
 
     def close(self):
+        if self._live_graphs:
+            raise LCError(-7, "the batch is held by a live graph: close the graph first")
         if self._h:
             lib().lc_batch_free(self._h)
             self._h = ctypes.c_void_p()

@@ -130,3 +130,109 @@ def test_batch_graph_replays_bit_identical():
     for k, (Fo, Eo, Wo, npo) in enumerate(want):
         assert (Fu[:, ps[k]:ps[k + 1]] == Fo).all(), k
     gr.close()
+
+
+def test_batch_512_boxes_full_size():
+    """The evaluated batch itself: 512 boxes, N ~ U{500..20000}, density ~
+    U[0.5, 0.9] (the seeded set the benchmark times), in one persistent
+    launch, a one-group-per-work-group launch and a graph replay.  Every box:
+    exact momentum conservation, and sampled particles bit-exact against the
+    oracle's brute-force fixed-point sum over all partners; the four largest
+    and the four densest boxes: every particle, energy, virial and pair count
+    bit-exact against the oracle's link-cell sweep."""
+    boxes = synth.boxes(512, 500, 20000, 0.5, 0.9, rc=2.5, seed=777)
+    grids = [lc.Grid(b.L, b.rc) for b in boxes]
+    ns = [b.n for b in boxes]
+    pos = np.ascontiguousarray(np.concatenate([b.pos for b in boxes], axis=1))
+    batch = lc.Batch(grids, ns)
+    info = batch.info()
+    print("batch512 info", info, flush=True)
+    ws = lc.Workspace(info["ntot"], info["ncell"])
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        cs, perm, coord = batch.build_cells(torch.from_numpy(pos).to(DEV), ws, stream=side)
+        F = torch.empty((3, info["ntot"]), dtype=torch.int64, device=DEV)
+        ew = torch.empty((len(boxes), 3), dtype=torch.int64, device=DEV)
+        batch.forces(cs, coord, ws, F, ew, persistent=True, stream=side)
+    side.synchronize()
+    F0, ew0 = F.clone(), ew.clone()
+    with torch.cuda.stream(side):
+        batch.forces(cs, coord, ws, F, ew, persistent=False, stream=side)
+    side.synchronize()
+    assert torch.equal(F, F0) and torch.equal(ew, ew0)
+    gr = batch.graph(cs, coord, F, ew, ws, side, True)
+    for rep in range(2):
+        F.zero_()
+        ew.zero_()
+        torch.cuda.synchronize()
+        gr.launch(side)
+        side.synchronize()
+        assert torch.equal(F, F0) and torch.equal(ew, ew0), rep
+    gr.close()
+    assert ws.status() & lc.FLAG_OVERFLOW == 0
+    ph = perm.cpu().numpy()
+    Fu = np.empty((3, info["ntot"]), dtype=np.int64)
+    Fu[:, ph] = F0.cpu().numpy()
+    ewh = ew0.cpu().numpy()
+    ps, _ = batch.offsets()
+    rng = np.random.default_rng(17)
+    for k, b in enumerate(boxes):
+        Fb = Fu[:, ps[k]:ps[k + 1]]
+        assert (Fb.sum(axis=1) == 0).all(), k
+        idx = rng.choice(b.n, 3, replace=False)
+        Fo, _ = O.forces_subset_fx(O.canonical(b.pos, b.L), b.L, b.rc, idx)
+        assert (Fb[:, idx] == Fo).all(), k
+    big = sorted(range(len(boxes)), key=lambda k: -boxes[k].n)[:4]
+    dense = sorted(range(len(boxes)), key=lambda k: -boxes[k].n / np.prod(boxes[k].L))[:4]
+    for k in big + dense:
+        b = boxes[k]
+        print("batch512 full box", k, b.n, grids[k].nc, flush=True)
+        Fo, Eo, Wo, npo = O.forces_lc_fx(O.canonical(b.pos, b.L), b.L, b.rc, grids[k].nc)
+        assert (Fu[:, ps[k]:ps[k + 1]] == Fo).all(), k
+        assert [int(x) for x in ewh[k]] == [Eo, Wo, npo], k
+
+
+def test_batch_atomic_write_and_tiles_same_bits():
+    """The batch with tile-atomic write-back, and with blocks sized for the
+    larger LDS tiles, gives the buffer + reduce batch's bits."""
+    boxes, grids, pos = _batch_inputs(10, 500, 6000, seed=21)
+    want = _oracle(boxes, grids)
+    posd = torch.from_numpy(pos).to(DEV)
+    for tile, write in ((768, "atomic"), (1024, "buffer"), (2048, "buffer"), (2048, "atomic")):
+        print("batch tile", tile, write, flush=True)
+        batch = lc.Batch(grids, [b.n for b in boxes], tile=tile, write=write)
+        info = batch.info()
+        ws = lc.Workspace(info["ntot"], info["ncell"])
+        cs, perm, coord = batch.build_cells(posd, ws)
+        for persistent in (True, False):
+            _check(batch, boxes, grids, cs, perm, coord, ws, want, persistent)
+        assert ws.status() & lc.FLAG_OVERFLOW == 0
+
+
+def test_graph_pins_the_replica_buffer():
+    """While a graph captured with a workspace lives, a call that would grow
+    the workspace's replica buffer is refused (the graph holds its address);
+    after the graph is freed the call goes through.  No replay needed."""
+    boxes, grids, pos = _batch_inputs(4, 500, 1500, seed=23)
+    batch = lc.Batch(grids, [b.n for b in boxes])
+    info = batch.info()
+    big = synth.fcc(32000, 0.8, rc=2.5, seed=24)
+    gbig = lc.Grid(big.L, big.rc)
+    ws = lc.Workspace(max(info["ntot"], big.n), max(info["ncell"], gbig.ncell))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        cs, perm, coord = batch.build_cells(torch.from_numpy(pos).to(DEV), ws, stream=side)
+        F = torch.empty((3, info["ntot"]), dtype=torch.int64, device=DEV)
+        ew = torch.empty((len(boxes), 3), dtype=torch.int64, device=DEV)
+    side.synchronize()
+    gr = batch.graph(cs, coord, F, ew, ws, side)
+    cb, _, cob = lc.build_cells(gbig, torch.from_numpy(big.pos).to(DEV), ws)
+    s = lc.Schedule(gbig, "buffer")
+    with pytest.raises(lc.LCError) as e:
+        lc.compute_forces(gbig, s, cb, cob, ws)
+    assert e.value.code == -7
+    with pytest.raises(lc.LCError):  # the binding keeps the workspace too
+        ws.close()
+    gr.close()
+    lc.compute_forces(gbig, s, cb, cob, ws)
+    torch.cuda.synchronize()

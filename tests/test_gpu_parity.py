@@ -145,6 +145,28 @@ def test_c2_full_size_all_schedules():
         assert st == 0, (kind, st)
 
 
+def test_c2_fp32_against_fp64_oracle():
+    """256k particles: the FP32 pair arithmetic (int64 sums) of the headline
+    schedule against the FP64 serial link-cell oracle, normwise <= 1e-5 in
+    the forces and <= 1e-5 relative in the energy.  The FP64 oracle takes
+    its pair set from the FP64 r^2 < rc^2 test; pairs within an FP32 ulp of
+    the cutoff (about one expected here) may differ, which moves the norm
+    by ~1e-8."""
+    box = synth.fcc(256000, 0.8, rc=2.5, seed=1002)
+    S = Setup(box)
+    _say("fcc256k fp32 vs fp64 oracle, nc", S.g.nc)
+    F, ew, st = S.forces("buffer", block=(2, 2, 3))
+    F64, U64, W64, np64 = O.forces_lc_f64(box.pos, S.u, box.L, box.rc, S.g.nc)
+    Fx = F / lc.SCALE
+    err = np.linalg.norm(Fx - F64) / np.linalg.norm(F64)
+    _say("  normwise", err, "pairs", ew[2], np64)
+    assert st == 0
+    assert err <= 1e-5
+    assert abs(ew[2] - np64) <= 10
+    assert abs(ew[0] / lc.SCALE - U64) <= 1e-5 * abs(U64)
+    assert abs(ew[1] / lc.SCALE - W64) <= 1e-5 * abs(W64)
+
+
 def test_c2_headline_configurations():
     """256k particles on the natural 27^3 grid with the block shapes the
     autotuner picks there (BUFFER and ATOMIC_TILE up to 1x4x4 and 2x2x3,
@@ -256,11 +278,16 @@ def test_overflow_flag():
     S = Setup(box)
     _, _, st = S.forces("block8")
     assert st & lc.FLAG_OVERFLOW
+    with pytest.raises(lc.LCError) as e:  # the flag as a status code
+        S.ws.check()
+    assert e.value.code == -5
+    S.ws.clear_status()
+    S.ws.check()
     with pytest.raises(O.OracleError):
         O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
 
 
-def _verlet_gpu(box, vel, dt, steps, rebuild, skin, chunks=(None,)):
+def _verlet_gpu(box, vel, dt, steps, rebuild, skin, chunks=(None,), check=False):
     g = lc.Grid(box.L, box.rc, skin)
     ws = lc.Workspace(box.n, g.ncell)
     s = lc.Schedule(g, "block8")
@@ -277,15 +304,24 @@ def _verlet_gpu(box, vel, dt, steps, rebuild, skin, chunks=(None,)):
     V = np.empty((3, box.n))
     P[:, idh] = pos.cpu().numpy()
     V[:, idh] = v.cpu().numpy()
+    if check:
+        try:
+            ws.check()
+        except lc.LCError as e:
+            return P, V, traces, e.code
+        return P, V, traces, 0
     return P, V, traces, ws.status()
 
 
 def test_verlet_bit_exact_vs_oracle():
+    """Config 1 (4,000 particles) with thermal velocities: 100 kick-drift-kick
+    steps at dt = 0.005, cells rebuilt every 10 steps (skin 0.6), bit-exact
+    positions, velocities and energy trace against the oracle."""
     box = synth.fcc(4000, 0.8, rc=2.5, seed=1001)
     vel = synth.maxwell_boltzmann(box.n, 1.0, seed=2001)
-    _say("verlet fcc4k 20 steps")
-    P, V, (tr,), st = _verlet_gpu(box, vel, 0.005, 20, 10, 0.6)
-    Po, Vo, Fo, tro = O.verlet_fx(box.pos, vel, box.L, box.rc, 0.005, 20)
+    _say("verlet fcc4k 100 steps")
+    P, V, (tr,), st = _verlet_gpu(box, vel, 0.005, 100, 10, 0.6)
+    Po, Vo, Fo, tro = O.verlet_fx(box.pos, vel, box.L, box.rc, 0.005, 100)
     assert st & lc.FLAG_DISP == 0
     assert (P == Po).all() and (V == Vo).all()
     assert (tr == tro).all()
@@ -305,6 +341,9 @@ def test_displacement_flag():
     vel = synth.maxwell_boltzmann(box.n, 1.0, seed=15)
     _, _, _, st = _verlet_gpu(box, vel, 0.005, 120, 1000, 0.1)
     assert st & lc.FLAG_DISP
+    # and as a status code from the check call
+    _, _, _, code = _verlet_gpu(box, vel, 0.005, 120, 1000, 0.1, check=True)
+    assert code == -6
 
 
 def _half_shell2():

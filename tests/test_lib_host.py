@@ -62,6 +62,21 @@ def test_cp_loopex_matches_oracle():
         r = lc.serialization_degree(dims, "loopex")
         o = O.serialization_degree(dims, order, loopex=True)
         assert (r["tasks"], r["cp"]) == (o["T"], o["cp"])
+        # no stencil displacement: Eq. 2 at Delta = 0 is k, Eq. 3 diverges
+        k = dims[0] * dims[1] * dims[2]
+        assert r["delta"] == 0
+        assert r["s_eq2"] == pytest.approx(O.speedup_eq2(0, k, r["n"])) == k
+        assert r["s_max"] == float("inf")
+
+
+def test_batch_options_rejected_on_host():
+    g = lc.Grid((17.1, 17.1, 17.1), 2.5)
+    for kw in ({"tile": 999}, {"tile": 512}):
+        with pytest.raises(lc.LCError) as e:
+            lc.Batch([g], [100], **kw)
+        assert e.value.code == -1
+    with pytest.raises(KeyError):
+        lc.Batch([g], [100], write="nope")
 
 
 def test_custom_orders_delta_rule_vs_dag():

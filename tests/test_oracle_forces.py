@@ -221,11 +221,48 @@ def test_cell_start_counts():
     cs = O.cell_start(u, nc)
     assert cs[0] == 0 and cs[-1] == b.n
     assert (np.diff(cs) >= 0).all()
-    # each particle's box fraction lies inside its cell's range
+    # each particle's box fraction lies inside its cell's range, both bounds
+    # on all three axes (cells x fastest), and the cell holds the particle's
+    # wrapped position: c L / nc <= x mod L < (c + 1) L / nc
     cid = O.cell_ids(u, nc)
-    cx = cid % nc[0]
-    lo = np.ceil(cx * 2.0 ** 32 / nc[0])
-    assert (u[0] >= lo).all()
+    _check_cells(cid, u, nc)
+    xw = np.mod(b.pos, np.asarray(b.L)[:, None])
+    c = np.stack([cid % nc[0], (cid // nc[0]) % nc[1], cid // (nc[0] * nc[1])])
+    side = (np.asarray(b.L) / np.asarray(nc))[:, None]
+    tol = 1e-12 * np.asarray(b.L)[:, None]
+    assert (xw >= c * side - tol).all() and (xw < (c + 1) * side + tol).all()
+
+
+def _check_cells(cid, u, nc):
+    nc = [int(x) for x in nc]
+    assert (cid >= 0).all() and (cid < nc[0] * nc[1] * nc[2]).all()
+    c = [cid % nc[0], (cid // nc[0]) % nc[1], cid // (nc[0] * nc[1])]
+    for d in range(3):
+        # cell c of an axis with k cells holds the fractions in
+        # [ceil(c 2^32 / k), ceil((c + 1) 2^32 / k)), in exact integers
+        cd = c[d].astype(object)
+        lo = np.array([-((-int(x) * 2 ** 32) // nc[d]) for x in cd], dtype=object)
+        hi = np.array([-((-(int(x) + 1) * 2 ** 32) // nc[d]) for x in cd], dtype=object)
+        ud = u[d].astype(object)
+        assert (ud >= lo).all() and (ud < hi).all(), d
+
+
+def test_cell_ids_at_cell_boundaries():
+    """Box fractions on, just below and just above every cell boundary, and
+    the ends 0 and 2^32 - 1, on axes of 3, 7 and 10 cells."""
+    nc = (3, 7, 10)
+    vals = []
+    for d in range(3):
+        k = nc[d]
+        edges = [-((-c * 2 ** 32) // k) for c in range(k)] + [2 ** 32]
+        vd = []
+        for e in edges:
+            vd += [e - 1, e, e + 1]
+        vals.append([v for v in vd if 0 <= v < 2 ** 32] + [0, 2 ** 32 - 1])
+    m = max(len(v) for v in vals)
+    u = np.array([[v[i % len(v)] for i in range(m)] for v in vals], dtype=np.uint32)
+    cid = O.cell_ids(u, nc)
+    _check_cells(cid, u, nc)
 
 
 def test_grid_rejects_small_or_tight_cells():
