@@ -251,6 +251,13 @@ int lc_make_schedule(const lc_grid *g, int kind, const int8_t *offsets, int n,
 int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *offsets,
                         int n, const int32_t *block_min, lc_schedule **out);
 int lc_schedule_info_get(const lc_schedule *s, lc_schedule_info *out);
+/* [host] The tasks of a creation-order schedule (LEX, OPT, BEST, BAD,
+ * CUSTOM, LOOPEX) in creation order, the order the dataflow executors take
+ * them: cells A[t], B[t] (host int32 arrays of cap >= T entries); *ntask =
+ * T.  LC_EINVAL for the other kinds, LC_ECAPACITY (with *ntask set) when
+ * cap < T. */
+int lc_schedule_tasks(const lc_schedule *s, int32_t *A, int32_t *B, int64_t cap,
+                      int64_t *ntask);
 void lc_schedule_free(lc_schedule *s);
 
 /* Load-aware variant of lc_make_schedule_ex (the weighted tasks of the
@@ -431,6 +438,22 @@ int lc_compute_forces_dataflow(const lc_grid *g, const lc_schedule *s, int mode,
                                const int32_t *cell_start, const uint32_t *coord, int64_t n,
                                int64_t *F, int64_t *ew, double limit_ms, lc_workspace *ws,
                                void *stream);
+/* lc_compute_forces_dataflow with an execution log, so that a checker can
+ * verify the strategy's constraint (Sec. VI strategy 2; the mutual exclusion
+ * of Sec. VII) from what the device did.  log [device] int32 2 x T (T = the
+ * schedule's task count): log[t] receives task t's start ticket, taken once
+ * its cells were granted and before any of its work, log[T + t] its end
+ * ticket, taken after all of its force adds have completed and before its
+ * cells are released; both come from one device counter (0, 1, 2, ... in the
+ * order the runners reach those points).  Hence ordered: start[t] >
+ * end[t'] for every earlier task t' sharing a cell with t; mutex and nested:
+ * the [start, end] intervals of tasks sharing a cell are disjoint; nested:
+ * a chain's tasks run one after another.  Entries of tasks an abandoned
+ * evaluation never ran are left as they were. */
+int lc_compute_forces_dataflow_log(const lc_grid *g, const lc_schedule *s, int mode,
+                                   const int32_t *cell_start, const uint32_t *coord, int64_t n,
+                                   int64_t *F, int64_t *ew, double limit_ms, int32_t *log,
+                                   lc_workspace *ws, void *stream);
 
 /* ---- a7: velocity Verlet ------------------------------------------------ */
 

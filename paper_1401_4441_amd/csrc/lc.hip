@@ -1431,11 +1431,13 @@ __global__ __launch_bounds__(256) void k_gather_partials(
 // exclusion Sec. VII asks for).
 // ---------------------------------------------------------------------------
 constexpr int kDfCell = 256;  // largest cell a runner stages (LDS)
+constexpr int kDfPre = kDfCell / 64;  // particles of cell A per lane
 
 struct DfArgs {
     const int32_t *ta, *tb;      // tasks in creation order: cells A, B
     const int32_t *seqa, *seqb;  // earlier tasks touching A, B (ORDERED)
     int64_t nunit;               // work units (tasks, or chains for NESTED)
+    int64_t ntask;
     int chain;                   // tasks per unit (NESTED)
     const int32_t *cell_start;
     const uint32_t *coord;
@@ -1443,7 +1445,9 @@ struct DfArgs {
     long long *F;
     long long *part;             // spread energy slots
     int *sync;                   // per cell: completed tasks (ORDERED) or lock
-    int *ctl;                    // [0] unit ticket, [1] abort
+    int *ctl;                    // [0] unit ticket, [1] abort, [2] log ticket
+    int *log;                    // optional: start ticket of task t at [t],
+                                 // end ticket at [ntask + t]
     uint32_t *flags;
     PairParams pp;
     unsigned long long limit;    // longest wait in s_memrealtime ticks (100 MHz)
@@ -1453,8 +1457,7 @@ struct DfArgs {
 // be free and taken (only lane 0 polls, inside a divergent branch, so the
 // accesses are vector memory operations).  Gives up when another runner has
 // aborted or after a.limit ticks, then aborts everyone.  Returns the outcome
-// to all lanes.  No fence: the force adds are device atomics, so the waits
-// carry no data, only the strategy's scheduling constraint.
+// to all lanes.
 template <class OK>
 __device__ __forceinline__ bool df_wait(const DfArgs &a, int *p, OK ok, bool cas) {
     int got = 1;
@@ -1478,72 +1481,158 @@ __device__ __forceinline__ bool df_wait(const DfArgs &a, int *p, OK ok, bool cas
                 got = 0;
                 break;
             }
-            __builtin_amdgcn_s_sleep(8);
+            __builtin_amdgcn_s_sleep(1);  // 64 clocks between polls
         }
     }
     got = __builtin_amdgcn_readfirstlane(got);
     return got != 0;
 }
 
-// One cell-pair task by one wave: A's box fractions staged in LDS, lanes own
-// B's particles 64 at a time and visit A in diagonal order (at each step the
-// lanes add into different A particles).  Intra tasks keep i before j.  The
-// sums go into F with device atomics: plain read-modify-writes would need a
-// device-scope release and acquire around every task, which on a GPU of
-// several L2 caches (one per XCD) writes back and invalidates a whole L2
-// each time; integer adds commute, so the result is the same.
-__device__ __forceinline__ void df_task(const DfArgs &a, int A, int B, uint32_t (*su)[kDfCell],
-                                        long long (*acc)[kDfCell], long long &e_sum,
-                                        long long &w_sum, long long &p_cnt, uint32_t &ovf) {
+// Ordered: bounded wait of lane 0 until the counters of cells A and B show
+// qa and qb completed earlier tasks; both counters are read in every poll,
+// so a task whose two predecessors finished long ago passes in one round
+// trip.  Outcome as df_wait.
+__device__ __forceinline__ bool df_wait2(const DfArgs &a, int A, int B, int qa, int qb) {
+    int got = 1;
+    if (threadIdx.x == 0) {
+        const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+        bool da = false, db = A == B;
+        for (;;) {
+            const int va = da ? qa : __hip_atomic_load(&a.sync[A], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            const int vb = db ? qb : __hip_atomic_load(&a.sync[B], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            da = va == qa;
+            db = vb == qb;
+            if (da && db) break;
+            if (__hip_atomic_load(&a.ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                got = 0;
+                break;
+            }
+            if (__builtin_amdgcn_s_memrealtime() - t0 > a.limit) {
+                __hip_atomic_store(&a.ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                atomicOr(a.flags, (uint32_t)LC_FLAG_ABORT);
+                got = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    got = __builtin_amdgcn_readfirstlane(got);
+    return got != 0;
+}
+
+// A task's inputs, loaded before the runner waits for its cells (they are
+// read-only, so the loads need no order with the waits and leave the
+// critical path): the two cells, their particle ranges, cell A's box
+// fractions (particle lane + 64 r in register r) and the box fraction of
+// cell B's particle `lane`.
+struct DfPre {
+    int A, B, sA, na, sB, nb;
+    uint32_t ax[kDfPre], ay[kDfPre], az[kDfPre];
+    uint4 ub;
+};
+
+__device__ __forceinline__ void df_load(const DfArgs &a, int64_t t, DfPre &p) {
     const int lane = threadIdx.x;
     const int64_t n = a.n;
-    const int sA = a.cell_start[A], na = a.cell_start[A + 1] - sA;
-    const int sB = a.cell_start[B], nb = a.cell_start[B + 1] - sB;
+    p.A = a.ta[t];
+    p.B = a.tb[t];
+    p.sA = a.cell_start[p.A];
+    p.na = a.cell_start[p.A + 1] - p.sA;
+    p.sB = a.cell_start[p.B];
+    p.nb = a.cell_start[p.B + 1] - p.sB;
+#pragma unroll
+    for (int r = 0; r < kDfPre; ++r) {
+        const int k = lane + 64 * r;
+        if (k < p.na) {
+            p.ax[r] = a.coord[p.sA + k];
+            p.ay[r] = a.coord[n + p.sA + k];
+            p.az[r] = a.coord[2 * n + p.sA + k];
+        }
+    }
+    p.ub = make_uint4(0u, 0u, 0u, 0u);
+    if (lane < p.nb)
+        p.ub = make_uint4(a.coord[p.sB + lane], a.coord[n + p.sB + lane],
+                          a.coord[2 * n + p.sB + lane], 0u);
+}
+
+// One cell-pair task by one wave.  A's box fractions are staged in LDS.  A
+// cell B of at most 64 particles is covered by 64 / nb lane groups: lane
+// (j, part) takes B's particle j and every parts-th i of A, in diagonal
+// order (i = (k + j) mod na), so each (i, j) is visited once and the lanes
+// of one step add into different A particles; larger cells take B 64
+// particles at a time.  Intra tasks keep i before j.  Both sides accumulate
+// in LDS, then go into F with device atomics: plain read-modify-writes would
+// need a device-scope release and acquire around every task, which on a GPU
+// of several L2 caches (one per XCD) writes back and invalidates a whole L2
+// each time; integer adds commute, so the result is the same.  The caller
+// waits for the adds to complete before it releases the cells.
+__device__ __forceinline__ void df_task(const DfArgs &a, const DfPre &p, uint32_t (*su)[kDfCell],
+                                        long long (*acc)[kDfCell], long long (*accb)[kDfCell],
+                                        long long &e_sum, long long &w_sum, long long &p_cnt,
+                                        uint32_t &ovf) {
+    const int lane = threadIdx.x;
+    const int64_t n = a.n;
+    const int na = p.na, nb = p.nb, sA = p.sA, sB = p.sB;
     if (na > kDfCell || nb > kDfCell) {  // the host checks the tile hint first
         if (lane == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_OVERFLOW);
         return;
     }
-    for (int k = lane; k < na; k += 64) {
-        su[0][k] = a.coord[sA + k];
-        su[1][k] = a.coord[n + sA + k];
-        su[2][k] = a.coord[2 * n + sA + k];
-        acc[0][k] = acc[1][k] = acc[2][k] = 0;
+    const bool intra = p.A == p.B;
+#pragma unroll
+    for (int r = 0; r < kDfPre; ++r) {
+        const int k = lane + 64 * r;
+        if (k < na) {
+            su[0][k] = p.ax[r];
+            su[1][k] = p.ay[r];
+            su[2][k] = p.az[r];
+            acc[0][k] = acc[1][k] = acc[2][k] = 0;
+        }
+        if (!intra && k < nb) accb[0][k] = accb[1][k] = accb[2][k] = 0;
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    const bool intra = A == B;
+    long long(*accj)[kDfCell] = intra ? acc : accb;
+    const int parts = (nb > 0 && nb <= 64) ? 64 / nb : 1;
     for (int j0 = 0; j0 < nb; j0 += 64) {
-        const int jl = j0 + lane;
-        const bool vj = jl < nb;
-        uint4 uj = make_uint4(0u, 0u, 0u, 0u);
-        if (vj) uj = make_uint4(a.coord[sB + jl], a.coord[n + sB + jl], a.coord[2 * n + sB + jl], 0u);
-        long long fx = 0, fy = 0, fz = 0;
-        int i = na > 0 ? lane % na : 0;  // diagonal: lane + k modulo na
-        for (int k = 0; k < na; ++k, i = i + 1 == na ? 0 : i + 1) {
-            if (!vj || (intra && i >= jl)) continue;
-            const uint4 ui = make_uint4(su[0][i], su[1][i], su[2][i], 0u);
-            long long qx, qy, qz, qe, qw;
-            if (!pair_terms_fast(ui, uj, a.pp, qx, qy, qz, qe, qw, ovf)) continue;
-            e_sum += qe;
-            w_sum += qw;
-            p_cnt += 1;
-            lds_sub64(&acc[0][i], qx);
-            lds_sub64(&acc[1][i], qy);
-            lds_sub64(&acc[2][i], qz);
-            fx += qx;
-            fy += qy;
-            fz += qz;
+        const int jr = parts > 1 ? lane % nb : lane;  // B particle within this chunk
+        const int part = parts > 1 ? lane / nb : 0;
+        const int jl = j0 + jr;
+        const bool vj = part < parts && jl < nb;
+        uint4 uj;
+        if (j0 == 0) {  // p.ub holds B's particle `lane`: fetch particle jr's
+            uj.x = (uint32_t)__shfl((int)p.ub.x, jr);
+            uj.y = (uint32_t)__shfl((int)p.ub.y, jr);
+            uj.z = (uint32_t)__shfl((int)p.ub.z, jr);
+        } else {
+            uj = vj ? make_uint4(a.coord[sB + jl], a.coord[n + sB + jl],
+                                 a.coord[2 * n + sB + jl], 0u)
+                    : make_uint4(0u, 0u, 0u, 0u);
         }
+        long long fx = 0, fy = 0, fz = 0;
         if (vj) {
-            if (intra) {  // j is a particle of A as well
-                atomicAdd((unsigned long long *)&acc[0][jl], (unsigned long long)fx);
-                atomicAdd((unsigned long long *)&acc[1][jl], (unsigned long long)fy);
-                atomicAdd((unsigned long long *)&acc[2][jl], (unsigned long long)fz);
-            } else {
-                atomicAdd((unsigned long long *)&a.F[sB + jl], (unsigned long long)fx);
-                atomicAdd((unsigned long long *)&a.F[n + sB + jl], (unsigned long long)fy);
-                atomicAdd((unsigned long long *)&a.F[2 * n + sB + jl], (unsigned long long)fz);
+            for (int k = part; k < na; k += parts) {
+                int i = k + jr;
+                i = i >= na ? i - na : i;
+                i = i >= na ? i % na : i;
+                if (intra && i >= jl) continue;
+                const uint4 ui = make_uint4(su[0][i], su[1][i], su[2][i], 0u);
+                long long qx, qy, qz, qe, qw;
+                if (!pair_terms_fast(ui, uj, a.pp, qx, qy, qz, qe, qw, ovf)) continue;
+                e_sum += qe;
+                w_sum += qw;
+                p_cnt += 1;
+                lds_sub64(&acc[0][i], qx);
+                lds_sub64(&acc[1][i], qy);
+                lds_sub64(&acc[2][i], qz);
+                fx += qx;
+                fy += qy;
+                fz += qz;
             }
+            atomicAdd((unsigned long long *)&accj[0][jl], (unsigned long long)fx);
+            atomicAdd((unsigned long long *)&accj[1][jl], (unsigned long long)fy);
+            atomicAdd((unsigned long long *)&accj[2][jl], (unsigned long long)fz);
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -1553,6 +1642,25 @@ __device__ __forceinline__ void df_task(const DfArgs &a, int A, int B, uint32_t 
         atomicAdd((unsigned long long *)&a.F[n + sA + k], (unsigned long long)acc[1][k]);
         atomicAdd((unsigned long long *)&a.F[2 * n + sA + k], (unsigned long long)acc[2][k]);
     }
+    if (!intra) {
+        for (int k = lane; k < nb; k += 64) {
+            atomicAdd((unsigned long long *)&a.F[sB + k], (unsigned long long)accb[0][k]);
+            atomicAdd((unsigned long long *)&a.F[n + sB + k], (unsigned long long)accb[1][k]);
+            atomicAdd((unsigned long long *)&a.F[2 * n + sB + k], (unsigned long long)accb[2][k]);
+        }
+    }
+}
+
+// A ticket of the log counter for task t's start (end: at[ntask + t]),
+// taken by lane 0.  The atomic returns its value before anything after it
+// is issued, so the ticket order follows the order in which the runners
+// passed these points.
+__device__ __forceinline__ void df_ticket(const DfArgs &a, int64_t at) {
+    if (a.log && threadIdx.x == 0) {
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        a.log[at] = atomicAdd(&a.ctl[2], 1);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    }
 }
 
 // MODE 0: ordered (sequence counters), 1: mutual exclusion per task,
@@ -1561,6 +1669,7 @@ template <int MODE>
 __global__ __launch_bounds__(64) void k_dataflow(DfArgs a) {
     __shared__ uint32_t su[3][kDfCell];
     __shared__ long long acc[3][kDfCell];
+    __shared__ long long accb[3][kDfCell];
     const int lane = threadIdx.x;
     long long e_sum = 0, w_sum = 0, p_cnt = 0;
     uint32_t ovf = 0;
@@ -1588,12 +1697,12 @@ __global__ __launch_bounds__(64) void k_dataflow(DfArgs a) {
         const int64_t t1 = MODE == 2 ? t0 + a.chain : t0 + 1;
         ++unit;
         for (int64_t t = t0; t < t1; ++t) {
-            const int A = a.ta[t], B = a.tb[t];
+            DfPre p;
+            df_load(a, t, p);  // in flight while the cells are awaited
+            const int A = p.A, B = p.B;
             const int lo = A < B ? A : B, hi = A < B ? B : A;
             if constexpr (MODE == 0) {
-                const int qa = a.seqa[t], qb = a.seqb[t];
-                if (!df_wait(a, &a.sync[A], [qa](int v) { return v == qa; }, false) ||
-                    (B != A && !df_wait(a, &a.sync[B], [qb](int v) { return v == qb; }, false))) {
+                if (!df_wait2(a, A, B, a.seqa[t], a.seqb[t])) {
                     stop = true;
                     break;
                 }
@@ -1610,8 +1719,16 @@ __global__ __launch_bounds__(64) void k_dataflow(DfArgs a) {
                     break;
                 }
             }
-            df_task(a, A, B, su, acc, e_sum, w_sum, p_cnt, ovf);
-            __builtin_amdgcn_wave_barrier();  // the whole wave is done with the task
+            df_ticket(a, t);
+            df_task(a, p, su, acc, accb, e_sum, w_sum, p_cnt, ovf);
+            // the task has finished when its force adds have completed:
+            // wait for them (the whole wave's memory operations) before the
+            // end ticket and the release
+            __builtin_amdgcn_wave_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_s_waitcnt(0);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            df_ticket(a, a.ntask + t);
             if (lane == 0) {
                 if constexpr (MODE == 0) {
                     atomicAdd(&a.sync[A], 1);
@@ -2279,6 +2396,19 @@ extern "C" void lc_schedule_free(lc_schedule *s) {
     delete s;
 }
 
+extern "C" int lc_schedule_tasks(const lc_schedule *s, int32_t *A, int32_t *B, int64_t cap,
+                                 int64_t *ntask) {
+    if (!s || !ntask) return fail(LC_EINVAL, "lc_schedule_tasks: null argument");
+    const int64_t t = (int64_t)s->h.order_a.size();
+    *ntask = t;
+    if (t == 0) return fail(LC_EINVAL, "lc_schedule_tasks: not a creation-order schedule");
+    if (!A || !B || cap < t) return fail(LC_ECAPACITY, "lc_schedule_tasks: need %lld entries",
+                                         (long long)t);
+    std::copy(s->h.order_a.begin(), s->h.order_a.end(), A);
+    std::copy(s->h.order_b.begin(), s->h.order_b.end(), B);
+    return LC_OK;
+}
+
 extern "C" int lc_schedule_info_get(const lc_schedule *s, lc_schedule_info *out) {
     if (!s || !out) return fail(LC_EINVAL, "null argument");
     memset(out, 0, sizeof *out);
@@ -2557,6 +2687,15 @@ extern "C" int lc_compute_forces_dataflow(const lc_grid *g, const lc_schedule *s
                                           const int32_t *cell_start, const uint32_t *coord,
                                           int64_t n, int64_t *F, int64_t *ew, double limit_ms,
                                           lc_workspace *ws, void *stream) {
+    return lc_compute_forces_dataflow_log(g, s, mode, cell_start, coord, n, F, ew, limit_ms,
+                                          nullptr, ws, stream);
+}
+
+extern "C" int lc_compute_forces_dataflow_log(const lc_grid *g, const lc_schedule *s, int mode,
+                                              const int32_t *cell_start, const uint32_t *coord,
+                                              int64_t n, int64_t *F, int64_t *ew,
+                                              double limit_ms, int32_t *log, lc_workspace *ws,
+                                              void *stream) {
     if (!g || !s || !cell_start || !F || !ew || (n > 0 && !coord))
         return fail(LC_EINVAL, "lc_compute_forces_dataflow: null argument");
     if (mode < LC_DF_ORDERED || mode > LC_DF_NESTED)
@@ -2577,9 +2716,9 @@ extern "C" int lc_compute_forces_dataflow(const lc_grid *g, const lc_schedule *s
                                   "(tile hint %d)", kDfCell, ws->max_per_cell);
     hipStream_t st = (hipStream_t)stream;
     if (!ws->df_sync) {
-        if ((rc = dalloc(&ws->df_sync, ws->max_cells)) || (rc = dalloc(&ws->df_ctl, 2))) return rc;
+        if ((rc = dalloc(&ws->df_sync, ws->max_cells)) || (rc = dalloc(&ws->df_ctl, 4))) return rc;
     }
-    if ((rc = fill32(ws->df_sync, g->ncell, st)) || (rc = fill32(ws->df_ctl, 2, st)) ||
+    if ((rc = fill32(ws->df_sync, g->ncell, st)) || (rc = fill32(ws->df_ctl, 4, st)) ||
         (rc = fill64((long long *)F, 3 * n, st)))
         return rc;
     DfArgs a;
@@ -2588,6 +2727,8 @@ extern "C" int lc_compute_forces_dataflow(const lc_grid *g, const lc_schedule *s
     a.seqa = s->df_seqa;
     a.seqb = s->df_seqb;
     const int64_t ntask = (int64_t)s->h.order_a.size();
+    a.ntask = ntask;
+    a.log = log;
     a.chain = mode == LC_DF_NESTED ? s->h.chain : 1;
     a.nunit = mode == LC_DF_NESTED ? ntask / s->h.chain : ntask;
     a.cell_start = cell_start;

@@ -92,6 +92,9 @@ SYMBOLS = {
     "lc_serialization_degree_weighted": ([P, INT, P, INT, P, P], INT),
     "lc_compute_forces": ([P, P, P, P, I64, P, P, INT, P, P], INT),
     "lc_compute_forces_dataflow": ([P, P, INT, P, P, I64, P, P, ctypes.c_double, P, P], INT),
+    "lc_compute_forces_dataflow_log": ([P, P, INT, P, P, I64, P, P, ctypes.c_double, P, P, P],
+                                       INT),
+    "lc_schedule_tasks": ([P, P, P, I64, P], INT),
     "lc_compute_forces_profiled": ([P, P, P, P, I64, P, P, INT, P, P, P, P], INT),
     "lc_compute_forces_noalloc": ([P, P, P, P, I64, P, P, INT, P, P], INT),
     "lc_verlet_step": ([P, P, P, P, P, I64, P, P, P, P, ctypes.c_double, INT,
@@ -308,6 +311,21 @@ class Schedule:
         _chk(lib().lc_schedule_info_get(self._h, ctypes.byref(i)))
         return {k: getattr(i, k) for k, _ in _SchedInfo._fields_ if k != "pad"}
 
+    def tasks(self):
+        """(A, B) int32 numpy arrays: a creation-order schedule's tasks in
+        creation order."""
+        import numpy as np
+        nt = ctypes.c_int64(0)
+        rc = lib().lc_schedule_tasks(self._h, None, None, 0, ctypes.byref(nt))
+        if rc < 0 and nt.value == 0:
+            _chk(rc)
+        A = np.empty(nt.value, dtype=np.int32)
+        B = np.empty(nt.value, dtype=np.int32)
+        _chk(lib().lc_schedule_tasks(self._h, ctypes.c_void_p(A.ctypes.data),
+                                     ctypes.c_void_p(B.ctypes.data), nt.value,
+                                     ctypes.byref(nt)))
+        return A, B
+
     def close(self):
         if self._h:
             lib().lc_schedule_free(self._h)
@@ -414,21 +432,23 @@ def compute_forces_noalloc(grid: Grid, sched: Schedule, cell_start, coord, F, ew
 
 def compute_forces_dataflow(grid: Grid, sched: Schedule, cell_start, coord, ws: Workspace,
                             mode: str = "ordered", F=None, ew=None, limit_ms: float = 2000.0,
-                            stream=None):
+                            stream=None, log=None):
     """One force evaluation by a dataflow executor over a creation-order
     schedule (mode: "ordered" = the creation order's dependences, "mutex" =
     per-cell mutual exclusion, "nested" = per-cell chains under mutual
     exclusion).  Every wait is bounded by limit_ms; an expired wait abandons
-    the evaluation and sets FLAG_ABORT.  Returns (F, ew) as compute_forces."""
+    the evaluation and sets FLAG_ABORT.  Returns (F, ew) as compute_forces.
+    log: an int32 device tensor of 2 x T entries receiving every task's
+    start and end tickets (lc_compute_forces_dataflow_log), or None."""
     n = coord.shape[1]
     dev = coord.device
     if F is None:
         F = torch.empty((3, n), dtype=torch.int64, device=dev)
     if ew is None:
         ew = torch.empty(3, dtype=torch.int64, device=dev)
-    _chk(lib().lc_compute_forces_dataflow(grid.ptr, sched.ptr, DATAFLOW[mode], _p(cell_start),
-                                          _p(coord), n, _p(F), _p(ew), float(limit_ms),
-                                          ws.ptr, _stream(stream)))
+    _chk(lib().lc_compute_forces_dataflow_log(grid.ptr, sched.ptr, DATAFLOW[mode],
+                                              _p(cell_start), _p(coord), n, _p(F), _p(ew),
+                                              float(limit_ms), _p(log), ws.ptr, _stream(stream)))
     return F, ew
 
 

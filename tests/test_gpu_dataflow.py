@@ -8,6 +8,7 @@ import pytest
 import torch
 
 import oracle as O
+from paper_1401_4441_amd import dataflow_check as D
 from paper_1401_4441_amd import lc, synth
 
 pytestmark = pytest.mark.gpu
@@ -29,25 +30,48 @@ class Box:
         self.u = O.canonical(box.pos, box.L)
         self.ref = O.forces_lc_fx(self.u, box.L, box.rc, self.g.nc)
 
-    def run(self, kind, mode, limit_ms=5000.0):
+    def run(self, kind, mode, limit_ms=5000.0, logged=False):
         s = lc.Schedule(self.g, kind)
+        A, B = s.tasks()
+        log = torch.full((2 * len(A),), -1, dtype=torch.int32, device=DEV) if logged else None
         self.ws.clear_status()
         F, ew = lc.compute_forces_dataflow(self.g, s, self.cs, self.coord, self.ws, mode,
-                                           limit_ms=limit_ms)
+                                           limit_ms=limit_ms, log=log)
         torch.cuda.synchronize()
         st = self.ws.status()
         s.close()
         Fh = F.cpu().numpy()
         out = np.empty_like(Fh)
         out[:, self.perm_h] = Fh
+        self.last = (A, B, log.cpu().numpy() if logged else None)
         return out, [int(x) for x in ew.cpu().numpy()], st
 
-    def check(self, kind, mode):
-        F, ew, st = self.run(kind, mode)
+    def check(self, kind, mode, logged=True):
+        F, ew, st = self.run(kind, mode, logged=logged)
         Fo, Eo, Wo, npo = self.ref
         assert st == 0, (kind, mode, st)
         assert (F == Fo).all(), (kind, mode)
         assert ew == [Eo, Wo, npo], (kind, mode)
+        if logged:
+            self.check_log(kind, mode)
+
+    def check_log(self, kind, mode):
+        """The executor honoured its strategy: every task ran once, and
+        ordered kept the creation order's dependences, mutex and nested kept
+        tasks sharing a cell apart (nested: each chain in order)."""
+        A, B, log = self.last
+        T = len(A)
+        assert D.check_complete(log, T) == 0, (kind, mode)
+        if mode == "ordered":
+            assert D.check_ordered(A, B, log) == 0, (kind, mode)
+        else:
+            assert D.check_exclusive(A, B, log) == 0, (kind, mode)
+        if mode == "nested":
+            assert D.check_chains(log, T, T // self.g.ncell) == 0, (kind, mode)
+        # the mutual-exclusion executors do not keep the creation order:
+        # report how often they ran a dependent task before its predecessor
+        if mode != "ordered":
+            _say("  out-of-order dependent pairs", D.check_ordered(A, B, log))
 
 
 _c1 = None
@@ -65,6 +89,16 @@ def c1():
 def test_dataflow_bit_exact_c1(kind, mode):
     _say("dataflow fcc4k", kind, mode)
     c1().check(kind, mode)
+
+
+def test_schedule_tasks_are_the_oracle_creation_order():
+    S = c1()
+    for kind, order in (("lex", O.ORDER3_LEX), ("opt", O.ORDER3_OPT), ("bad", O.ORDER3_BAD)):
+        s = lc.Schedule(S.g, kind)
+        A, B = s.tasks()
+        oa, ob = O.lc_tasks(S.g.nc, order)
+        assert (A == oa).all() and (B == ob).all(), kind
+        s.close()
 
 
 @pytest.mark.parametrize("mode", ["ordered", "mutex"])
