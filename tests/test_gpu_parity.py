@@ -98,6 +98,50 @@ def test_cell_build_reuses_workspace_counters():
         assert (O.cell_ids(u, g.nc)[perm.cpu().numpy()] == slot_cell).all()
 
 
+def _check_build(box, g, cs, perm, coord):
+    u = O.canonical(box.pos, box.L)
+    csh = cs.cpu().numpy()
+    assert (csh == O.cell_start(u, g.nc)).all()
+    ph = perm.cpu().numpy()
+    assert np.array_equal(np.sort(ph), np.arange(box.n))
+    slot_cell = np.repeat(np.arange(g.ncell), np.diff(csh))
+    assert (O.cell_ids(u, g.nc)[ph] == slot_cell).all()
+    assert (coord.cpu().numpy().view(np.uint32) == u[:, ph]).all()
+
+
+def test_cell_build_sizes_and_orders():
+    """The cell build gives the oracle's cell table, a permutation with the
+    oracle's cell membership and the matching box fractions: ragged sizes,
+    one particle, a shuffled order, 256k in lattice order, and builds that
+    alternate sizes on one workspace (counters and the bin pass's completion
+    counter reset)."""
+    cases = [synth.fcc(1, 0.8, rc=2.5, seed=61), synth.fcc(1234, 0.8, rc=2.5, seed=62),
+             synth.fcc(4000, 0.8, rc=2.5, seed=63), synth.fcc(256000, 0.8, rc=2.5, seed=1002)]
+    cases[0].L = np.array([8.0, 8.0, 8.0])  # one particle in a 3^3 grid
+    sh = synth.fcc(70001, 0.7, rc=2.5, seed=64)
+    sh.pos = np.ascontiguousarray(sh.pos[:, np.random.default_rng(5).permutation(sh.n)])
+    cases.append(sh)
+    grids = [lc.Grid(b.L, b.rc) for b in cases]
+    ws = lc.Workspace(max(b.n for b in cases), max(g.ncell for g in grids))
+    for b, g in list(zip(cases, grids)) + list(zip(cases, grids))[::-1]:
+        _say("cell build", b.n, g.nc)
+        cs, perm, coord = lc.build_cells(g, torch.from_numpy(b.pos).to(DEV), ws)
+        _check_build(b, g, cs, perm, coord)
+    assert ws.status() == 0
+
+
+def test_cell_build_two_million():
+    """The 2M slab (dense and dilute cells, 64^3 = 262,144 cells: the
+    three-pass scan)."""
+    box = synth.workload("slab2m")
+    g = lc.Grid(box.L, box.rc)
+    ws = lc.Workspace(box.n, g.ncell)
+    _say("cell build slab2m", g.nc)
+    cs, perm, coord = lc.build_cells(g, torch.from_numpy(box.pos).to(DEV), ws)
+    _check_build(box, g, cs, perm, coord)
+    assert ws.status() == 0
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_forces_bit_exact_c1(kind):
     S = c1()
