@@ -628,9 +628,16 @@ struct SweepArgs {
 // 2^-32, so its one rounding takes v to the nearest multiple of 2^-32 (ties
 // to even), and that multiple's count sits in the low mantissa bits:
 // bits = bits(1.5 * 2^20) + round(v * 2^32).
-__device__ __forceinline__ long long q32_magic(float v) {
+constexpr long long kQ32Bias = 0x4138000000000000LL;  // bits of 1.5 * 2^20
+// The quantised value plus kQ32Bias (modulo 2^64): a sum of n such terms
+// is the sum of the quantised values plus n kQ32Bias, so sums can skip the
+// per-term subtraction and remove n kQ32Bias once.
+__device__ __forceinline__ long long q32_biased(float v) {
     const double d = (double)v + 1572864.0;  // 1.5 * 2^20
-    return (long long)__double_as_longlong(d) - 0x4138000000000000LL;
+    return (long long)__double_as_longlong(d);
+}
+__device__ __forceinline__ long long q32_magic(float v) {
+    return q32_biased(v) - kQ32Bias;
 }
 
 // IEEE (correctly rounded) 1/x for x in [kRcpLo, kRcpHi): the hardware
@@ -675,7 +682,9 @@ __device__ __forceinline__ void lj_terms(float inv, float dx, float dy, float dz
 }
 
 // FP32 pair terms with the fast reciprocal and quantisation; same values as
-// pair_terms<false>.
+// pair_terms<false>.  BIASED: qe and qw come with kQ32Bias added (modulo
+// 2^64), for sums that remove the bias once per pair counted.
+template <bool BIASED = false>
 __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, const PairParams &p,
                                                 long long &qx, long long &qy, long long &qz,
                                                 long long &qe, long long &qw, uint32_t &ovf) {
@@ -691,8 +700,8 @@ __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, 
         qx = q32_magic(fx);
         qy = q32_magic(fy);
         qz = q32_magic(fz);
-        qe = q32_magic(e);
-        qw = q32_magic(w);
+        qe = BIASED ? q32_biased(e) : q32_magic(e);
+        qw = BIASED ? q32_biased(w) : q32_magic(w);
     } else {
         lj_terms(1.0f / r2, dx, dy, dz, r2, p.ecut, fx, fy, fz, e, w);
         qx = q32f(fx, ovf);
@@ -700,6 +709,10 @@ __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, 
         qz = q32f(fz, ovf);
         qe = q32f(e, ovf);
         qw = q32f(w, ovf);
+        if constexpr (BIASED) {
+            qe = (long long)((unsigned long long)qe + (unsigned long long)kQ32Bias);
+            qw = (long long)((unsigned long long)qw + (unsigned long long)kQ32Bias);
+        }
     }
     return true;
 }
@@ -812,10 +825,11 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
         if constexpr (F64)
             in = pair_terms<true>(ui.x, ui.y, ui.z, uj.x, uj.y, uj.z, pp, qx, qy, qz, qe, qw, ovf);
         else
-            in = pair_terms_fast(ui, uj, pp, qx, qy, qz, qe, qw, ovf);
+            in = pair_terms_fast<true>(ui, uj, pp, qx, qy, qz, qe, qw, ovf);
         if (!in) return;
-        e_sum += qe;
-        w_sum += qw;
+        // (FP32: biased energy and virial terms, corrected below)
+        e_sum = (long long)((unsigned long long)e_sum + (unsigned long long)qe);
+        w_sum = (long long)((unsigned long long)w_sum + (unsigned long long)qw);
         p_cnt += 1;
         if constexpr (STAGED && WMODE != 2) {
             lds_sub64(&sh.acc[0][il], qx);  // ds_sub_u64: no negation
@@ -930,12 +944,18 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             // one candidate row: 16-bit differences wrap modulo the box (the
             // minimum image up to one unit per axis); r2 - bound is negative
             // (sign bit set) inside, and the sign bit is shifted into m
+            // The first dot product takes the bound from a register it does
+            // not overwrite (the three-operand form; the compiler would copy
+            // the bound into the accumulating two-operand form, one more
+            // instruction per row).
+            const int nthr = -pp.thr16;
             auto row = [&](const uint2 hi, uint32_t m) -> uint32_t {
                 const short2v dxy =
                     __builtin_bit_cast(short2v, hj.x) - __builtin_bit_cast(short2v, hi.x);
                 const short2v dz0 =
                     __builtin_bit_cast(short2v, hj.y) - __builtin_bit_cast(short2v, hi.y);
-                int t = __builtin_amdgcn_sdot2(dz0, dz0, -pp.thr16, false);
+                int t;
+                asm("v_dot2_i32_i16 %0, %1, %1, %2" : "=v"(t) : "v"(dz0), "v"(nthr));
                 t = __builtin_amdgcn_sdot2(dxy, dxy, t, false);
                 return __builtin_amdgcn_alignbit(m, (uint32_t)t, 31);
             };
@@ -944,11 +964,13 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
                 const uint2 *ha = &sh.h[a0 + k0];
                 uint32_t m = 0u;
                 int k = 0;
-                for (; k + 2 <= kr; k += 2) {  // two rows per LDS read
+                for (; k + 4 <= kr; k += 4) {  // four rows per address step
                     m = row(ha[k], m);
                     m = row(ha[k + 1], m);
+                    m = row(ha[k + 2], m);
+                    m = row(ha[k + 3], m);
                 }
-                if (k < kr) m = row(ha[k], m);
+                for (; k < kr; ++k) m = row(ha[k], m);
                 // row k sits at bit kr - 1 - k; keep rows k < lim - k0
                 const int nv = lim - k0;
                 m = nv <= 0 ? 0u : nv >= kr ? m : m & ~((1u << (kr - nv)) - 1u);
@@ -996,6 +1018,11 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     if (lane < qn) eval(load(q[lane]));
     if (lane + 64 < qn) eval(load(q[lane + 64]));
+    if constexpr (!F64) {  // remove the bias of the p_cnt energy and virial terms
+        const unsigned long long b = (unsigned long long)p_cnt * (unsigned long long)kQ32Bias;
+        e_sum = (long long)((unsigned long long)e_sum - b);
+        w_sum = (long long)((unsigned long long)w_sum - b);
+    }
 }
 
 // What a group's setup reads from global memory before its LDS work: the
