@@ -251,11 +251,13 @@ def main():
     err_energy = abs(int(ew32[0]) - int(ew64[0])) / abs(int(ew64[0]))
 
     # ---- dominant kernel: the sweep phases, HIP events around each launch
-    sweep_ms = []
+    sweep_ms, close_ms = [], []
     for _ in range(5):
         _, _, tot, per_phase = lc.compute_forces_profiled(g, sched, cs, coord, ws, "fp32", F, ew)
         sweep_ms.append(tot)
+        close_ms.append(per_phase[-1])
     sweep_ms = statistics.median(sweep_ms)
+    close_ms = statistics.median(close_ms)
     nphase = sched.info()["nphase"]
     ops = OPS_PER_CANDIDATE * ncand + OPS_PER_PAIR * pairs
     achieved_tops = ops / (sweep_ms * 1e-3) / 1e12
@@ -309,6 +311,19 @@ def main():
         },
         "wall_s_timed": wall,
     }
+
+    # ---- buffer + reduce: the gather that closes the evaluation is HBM-bound;
+    # per particle it reads its cell's R_c replica slots (24 B each) and the
+    # replica count (4 B) and writes the force (24 B)
+    if sched.info()["write_mode"] == 3:
+        nc_cells = np.diff(cs.cpu().numpy().astype(np.int64))
+        reps = sched.cell_footprints().astype(np.int64)
+        gbytes = int(np.sum(nc_cells * (24 * reps + 28)))
+        out["gather"] = {"kernel": "k_gather_partials", "ms": close_ms,
+                         "algorithmic_bytes": gbytes,
+                         "mean_replicas": float(np.sum(nc_cells * reps) / box.n),
+                         "GBps": gbytes / (close_ms * 1e-3) / 1e9,
+                         "hbm_frac": gbytes / (close_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     # ---- the cell build (a1) alone and the evaluation with it, candidate rate
     copy_gbs = copy_bandwidth_gbs()

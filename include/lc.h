@@ -258,6 +258,11 @@ int lc_schedule_info_get(const lc_schedule *s, lc_schedule_info *out);
  * cap < T. */
 int lc_schedule_tasks(const lc_schedule *s, int32_t *A, int32_t *B, int64_t cap,
                       int64_t *ntask);
+/* [host] For every cell, the number of work-group footprints (over all
+ * phases) that hold it: the replica slots its particles get under
+ * LC_SCHED_BUFFER, the write-backs they get under the tiled kinds.  count
+ * [host] int32 of cap >= ncell entries (x fastest). */
+int lc_schedule_cell_footprints(const lc_schedule *s, int32_t *count, int64_t cap);
 void lc_schedule_free(lc_schedule *s);
 
 /* Load-aware variant of lc_make_schedule_ex (the weighted tasks of the
@@ -363,10 +368,12 @@ int lc_compute_forces(const lc_grid *g, const lc_schedule *s,
                       lc_workspace *ws, void *stream);
 
 /* Profiling variant of lc_compute_forces: the same launches, each sweep
- * phase bracketed by HIP events on `stream`; synchronises and returns the
- * summed device time of the sweep kernels in *sweep_ms (the zero-fill of F
- * and ew is not included) and, if phase_ms is not NULL, the time of each
- * phase (host array of nphase doubles). */
+ * phase and the closing launch (the gather of LC_SCHED_BUFFER, else the
+ * energy sums) bracketed by HIP events on `stream`; synchronises and returns
+ * the summed device time of the sweep kernels in *sweep_ms (the zero-fill of
+ * F and ew is not included) and, if phase_ms is not NULL, the time of each
+ * phase followed by that of the closing launch (host array of nphase + 1
+ * doubles). */
 int lc_compute_forces_profiled(const lc_grid *g, const lc_schedule *s,
                                const int32_t *cell_start, const uint32_t *coord,
                                int64_t n, int64_t *F, int64_t *ew, int precision,

@@ -1987,16 +1987,18 @@ static int forces_run(const lc_grid *g, const lc_schedule *s, const int32_t *cel
         if (rc) return rc;
         if (ev) HIPCHK(hipEventRecord(ev[2 * p + 1], st));
     }
+    if (ev) HIPCHK(hipEventRecord(ev[2 * nphase], st));
     if (buffered && n > 0) {  // gather + the energy sums in one launch
         hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((n + 255) / 256 + 1)), dim3(256), 0,
                            st, (const long long *)sc.pbuf, (const int *)a.rcnt, n,
                            (long long *)F, sc.part, (long long *)ew);
         LAUNCHCHK("k_gather_partials");
-        return LC_OK;
+    } else {
+        hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, sc.part, 3,
+                           (long long *)ew, fullshell ? 1 : 0);
+        LAUNCHCHK("k_reduce_parts");
     }
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, sc.part, 3,
-                       (long long *)ew, fullshell ? 1 : 0);
-    LAUNCHCHK("k_reduce_parts");
+    if (ev) HIPCHK(hipEventRecord(ev[2 * nphase + 1], st));
     return LC_OK;
 }
 
@@ -2436,6 +2438,16 @@ extern "C" int lc_schedule_tasks(const lc_schedule *s, int32_t *A, int32_t *B, i
     return LC_OK;
 }
 
+extern "C" int lc_schedule_cell_footprints(const lc_schedule *s, int32_t *count, int64_t cap) {
+    if (!s || !count) return fail(LC_EINVAL, "lc_schedule_cell_footprints: null argument");
+    const int64_t ncell = (int64_t)s->nc[0] * s->nc[1] * s->nc[2];
+    if (cap < ncell)
+        return fail(LC_ECAPACITY, "lc_schedule_cell_footprints: need %lld entries", (long long)ncell);
+    std::fill(count, count + ncell, 0);
+    for (int32_t c : s->h.foot_cells) count[c]++;
+    return LC_OK;
+}
+
 extern "C" int lc_schedule_info_get(const lc_schedule *s, lc_schedule_info *out) {
     if (!s || !out) return fail(LC_EINVAL, "null argument");
     memset(out, 0, sizeof *out);
@@ -2797,7 +2809,7 @@ extern "C" int lc_compute_forces_profiled(const lc_grid *g, const lc_schedule *s
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     const int nphase = (int)s->h.phase_grp.size() - 1;
-    std::vector<hipEvent_t> ev((size_t)2 * nphase, nullptr);
+    std::vector<hipEvent_t> ev((size_t)2 * nphase + 2, nullptr);
     for (auto &e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
             for (auto &x : ev)
@@ -2817,6 +2829,12 @@ extern "C" int lc_compute_forces_profiled(const lc_grid *g, const lc_schedule *s
         }
         total += ms;
         if (phase_ms) phase_ms[p] = ms;
+    }
+    if (!rc && phase_ms) {  // the closing launch: gather (buffer + reduce) or the energy sums
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[2 * nphase], ev[2 * nphase + 1]) != hipSuccess)
+            rc = fail(LC_EHIP, "hipEventElapsedTime");
+        phase_ms[nphase] = ms;
     }
     for (auto &x : ev) (void)hipEventDestroy(x);
     if (!rc) *sweep_ms = total;

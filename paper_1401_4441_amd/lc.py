@@ -95,6 +95,7 @@ SYMBOLS = {
     "lc_compute_forces_dataflow_log": ([P, P, INT, P, P, I64, P, P, ctypes.c_double, P, P, P],
                                        INT),
     "lc_schedule_tasks": ([P, P, P, I64, P], INT),
+    "lc_schedule_cell_footprints": ([P, P, I64], INT),
     "lc_compute_forces_profiled": ([P, P, P, P, I64, P, P, INT, P, P, P, P], INT),
     "lc_compute_forces_noalloc": ([P, P, P, P, I64, P, P, INT, P, P], INT),
     "lc_verlet_step": ([P, P, P, P, P, I64, P, P, P, P, ctypes.c_double, INT,
@@ -311,6 +312,15 @@ class Schedule:
         _chk(lib().lc_schedule_info_get(self._h, ctypes.byref(i)))
         return {k: getattr(i, k) for k, _ in _SchedInfo._fields_ if k != "pad"}
 
+    def cell_footprints(self):
+        """int32 numpy array, per cell: how many work-group footprints hold
+        it (the replica slots of buffer + reduce)."""
+        import numpy as np
+        out = np.zeros(self.grid.ncell, dtype=np.int32)
+        _chk(lib().lc_schedule_cell_footprints(self._h, ctypes.c_void_p(out.ctypes.data),
+                                               self.grid.ncell))
+        return out
+
     def tasks(self):
         """(A, B) int32 numpy arrays: a creation-order schedule's tasks in
         creation order."""
@@ -455,8 +465,10 @@ def compute_forces_dataflow(grid: Grid, sched: Schedule, cell_start, coord, ws: 
 def compute_forces_profiled(grid: Grid, sched: Schedule, cell_start, coord,
                             ws: Workspace, precision: str = "fp32", F=None, ew=None,
                             stream=None):
-    """compute_forces with HIP events around every sweep phase (synchronises).
-    Returns (F, ew, sweep_ms, per-phase ms list)."""
+    """compute_forces with HIP events around every sweep phase and the
+    closing launch (synchronises).  Returns (F, ew, sweep_ms, per-phase ms
+    list); the list's extra last entry is the closing launch (the gather of
+    buffer + reduce, else the energy sums)."""
     import numpy as np
     n = coord.shape[1]
     dev = coord.device
@@ -465,13 +477,13 @@ def compute_forces_profiled(grid: Grid, sched: Schedule, cell_start, coord,
     if ew is None:
         ew = torch.empty(3, dtype=torch.int64, device=dev)
     nphase = sched.info()["nphase"]
-    ph = np.zeros(max(nphase, 1), dtype=np.float64)
+    ph = np.zeros(nphase + 1, dtype=np.float64)
     tot = ctypes.c_double(0.0)
     _chk(lib().lc_compute_forces_profiled(grid.ptr, sched.ptr, _p(cell_start), _p(coord), n,
                                           _p(F), _p(ew), PREC[precision], ws.ptr,
                                           _stream(stream), ctypes.byref(tot),
                                           ctypes.c_void_p(ph.ctypes.data)))
-    return F, ew, float(tot.value), ph[:nphase].tolist()
+    return F, ew, float(tot.value), ph.tolist()
 
 
 def verlet_step(grid: Grid, sched: Schedule, pos, vel, ids, ws: Workspace,

@@ -141,4 +141,8 @@ def test_expired_wait_abandons_the_evaluation():
     _say("dataflow forced abort")
     _, _, st = S.run("lex", "ordered", limit_ms=0.0)
     assert st & lc.FLAG_ABORT
+    with pytest.raises(lc.LCError) as e:  # the flag as a status code
+        S.ws.check()
+    assert e.value.code == -8
     S.check("lex", "ordered")
+    S.ws.check()

@@ -169,6 +169,20 @@ def test_fp64_variant_and_fp32_error_c1():
     assert ew32[0] / lc.SCALE == pytest.approx(U, rel=1e-5)
 
 
+def test_footprint_counts_and_profiled_phases_c1():
+    """Per-cell footprint counts of buffer + reduce are its replica slots (at
+    least one per cell, at most max_replicas), and the profiled evaluation
+    times every phase and the closing gather."""
+    S = c1()
+    s = lc.Schedule(S.g, "buffer")
+    fp = s.cell_footprints()
+    assert fp.shape == (S.g.ncell,) and fp.min() >= 1
+    assert fp.max() == s.info()["max_replicas"]
+    F, ew, tot, ph = lc.compute_forces_profiled(S.g, s, S.cs, S.coord, S.ws)
+    assert len(ph) == s.info()["nphase"] + 1 and tot > 0 and ph[-1] > 0
+    assert (S.unsort(F) == O.forces_lc_fx(S.u, S.box.L, S.box.rc, S.g.nc)[0]).all()
+
+
 def test_momentum_exact_c1():
     S = c1()
     F, _, _ = S.forces("block8")

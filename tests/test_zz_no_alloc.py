@@ -23,26 +23,27 @@ def _system(n, seed):
     return g, ws, cs, coord
 
 
-@pytest.mark.parametrize("kind", ["buffer", "block8", "atomic_tile"])
-def test_noalloc_matches_workspace_path(kind):
+@pytest.mark.parametrize("kind,prec", [("buffer", "fp32"), ("block8", "fp32"),
+                                       ("atomic_tile", "fp32"), ("buffer", "fp64")])
+def test_noalloc_matches_workspace_path(kind, prec):
     # the larger system first, then a smaller one: the second call reuses the
     # scratch the first left behind
     for n, seed in ((32000, 71), (4000, 72)):
-        print(f"noalloc {kind} n={n} seed={seed}", flush=True)
+        print(f"noalloc {kind} {prec} n={n} seed={seed}", flush=True)
         g, ws, cs, coord = _system(n, seed)
         s = lc.Schedule(g, kind)
-        F0, ew0 = lc.compute_forces(g, s, cs, coord, ws)
+        F0, ew0 = lc.compute_forces(g, s, cs, coord, ws, prec)
         F1 = torch.full((3, coord.shape[1]), 7, dtype=torch.int64, device=DEV)
         ew1 = torch.full((3,), 7, dtype=torch.int64, device=DEV)
         flags = torch.zeros(1, dtype=torch.int32, device=DEV)
-        lc.compute_forces_noalloc(g, s, cs, coord, F1, ew1, flags=flags)
+        lc.compute_forces_noalloc(g, s, cs, coord, F1, ew1, prec, flags=flags)
         torch.cuda.synchronize()
         assert torch.equal(F0, F1), (kind, n)
         assert torch.equal(ew0, ew1), (kind, n, ew0.tolist(), ew1.tolist())
         assert int(flags.item()) & lc.FLAG_OVERFLOW == 0
         # again without a flags word (status bits go to the scratch)
         F1.fill_(-1)
-        lc.compute_forces_noalloc(g, s, cs, coord, F1, ew1)
+        lc.compute_forces_noalloc(g, s, cs, coord, F1, ew1, prec)
         torch.cuda.synchronize()
         assert torch.equal(F0, F1) and torch.equal(ew0, ew1), (kind, n)
 
