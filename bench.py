@@ -423,6 +423,20 @@ def main():
             "value": npo / t, "unit": "pairs/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(times)} full serial fixed-point link-cell evaluations of the "
                       f"same {box.n}-particle box (median {t:.3f} s each)"}
+        # the headline's FP32 forces against the FP64 serial link-cell oracle
+        # (FP64 arithmetic and the FP64 cutoff test, cells from the same box
+        # fractions); pairs within an FP32 ulp of the cutoff may be in one
+        # pair set and not the other
+        F64o, U64o, W64o, np64o = O.forces_lc_f64(box.pos, u, box.L, box.rc,
+                                                  O.grid_dims(box.L, box.rc))
+        Fin = np.empty((3, box.n))
+        Fin[:, perm.cpu().numpy()] = F32.double().cpu().numpy() / 2.0 ** 32
+        out["cpu_baseline"]["fp64_oracle_check"] = {
+            "force_normwise_rel_err": float(np.linalg.norm(Fin - F64o) / np.linalg.norm(F64o)),
+            "energy_rel_err": abs(int(ew32[0]) / 2.0 ** 32 - U64o) / abs(U64o),
+            "virial_rel_err": abs(int(ew32[1]) / 2.0 ** 32 - W64o) / abs(W64o),
+            "pairs_fp32_cutoff": int(ew32[2]), "pairs_fp64_cutoff": np64o,
+            "gate": 1e-5}
         # the paper's own CPU scheme beside it: the same sweep in the
         # loop-exchange order with two-strided colouring, parallel over each
         # colour's cells with OpenMP on the host's threads (even cell counts)
