@@ -140,8 +140,9 @@ void lc_workspace_destroy(lc_workspace *ws);
 int lc_workspace_set_tile_hint(lc_workspace *ws, int32_t max_per_cell);
 
 /* Clear the device status flags (async on stream).  It also re-zeroes the
- * workspace's energy partial slots, which every call otherwise leaves zero
- * for the next (a call that failed part-way may not have). */
+ * workspace's energy partial slots, cell counters and scan status words,
+ * which every call otherwise leaves zero for the next (a call that failed
+ * part-way may not have). */
 int lc_workspace_clear_status(lc_workspace *ws, void *stream);
 /* Synchronise `stream` and return the device status flags (LC_FLAG_*). */
 int lc_workspace_status(lc_workspace *ws, void *stream, uint32_t *flags);

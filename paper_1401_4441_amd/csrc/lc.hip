@@ -5,8 +5,8 @@
 //                           whole path can sit inside a captured graph)
 //   k_bin                   cell of each particle + its rank in the cell (one
 //                           counter atomic per cell and wave)
-//   k_scan_one / k_scan_*   exclusive scan of per-cell counts -> cell_start
-//                           (one work-group up to 65,536 cells, else 3 passes)
+//   k_scan_lb               exclusive scan of per-cell counts -> cell_start
+//                           (one pass, decoupled look-back between tiles)
 //   k_scatter               counting-sort scatter: perm + sorted box fractions
 //   k_sweep<CAP,WMODE,F64,FF>  one phase of cell-cell tasks (Sec. IV): per
 //                           work-group a group of tasks whose footprint cells
@@ -82,7 +82,6 @@ struct lc_workspace {
     int32_t *cid = nullptr;      // N: cell of particle
     int32_t *rank = nullptr;     // N: rank inside its cell
     int32_t *counts = nullptr;   // max_cells: per-cell counters
-    int32_t *partial = nullptr;  // scan block totals
     uint32_t *flags = nullptr;   // device status flags
     int64_t *ew = nullptr;       // 3: energy, virial, pairs
     int64_t *part = nullptr;     // kPartSlots x 3 spread partial sums
@@ -96,6 +95,9 @@ struct lc_workspace {
     int32_t *df_sync = nullptr;  // dataflow: per-cell counter or lock
     int32_t *df_ctl = nullptr;   // dataflow: ticket, abort
     int live_graphs = 0;         // graphs captured with this workspace, not yet freed
+    unsigned long long *lb_status = nullptr;  // single-pass scan: tile status words
+    int32_t *lb_done = nullptr;               // single-pass scan: tiles finished
+    int64_t lb_tiles = 0;
 };
 
 struct lc_schedule {
@@ -422,130 +424,113 @@ __global__ __launch_bounds__(256) void k_bin(const double *__restrict__ pos, int
     if (act) rank[i] = r;
 }
 
-constexpr int kScanBS = 256, kScanIPT = 4, kScanTile = kScanBS * kScanIPT;
+// ---- single-pass scan (decoupled look-back) ------------------------------
+//
+// Work-group b scans tile b of kLbTile counters and publishes the tile's
+// total in status[b]; it then looks back over the lower tiles (64 at a time,
+// one per lane of its first wave), adding their totals until it meets one
+// that has published its inclusive prefix (tile 0 does so at once), and
+// publishes its own.  Status words are 64-bit: flag (1 = tile total, 2 =
+// inclusive prefix) << 62 | value, read and written with device-scope atomics
+// (coherent across the XCDs' caches).  A tile only waits for lower tiles,
+// which the hardware dispatches first, and every wait is bounded (abort
+// flag).  The last work-group to finish clears the status words for the next
+// scan.  The counters are cleared as they are read.
+constexpr int kLbBS = 1024, kLbIPT = 4, kLbTile = kLbBS * kLbIPT;
+constexpr unsigned long long kLbAgg = 1ull << 62, kLbPre = 2ull << 62;
 
-__global__ __launch_bounds__(kScanBS) void k_scan_reduce(const int *__restrict__ in, int64_t m,
-                                                         int *__restrict__ partial) {
-    __shared__ int s_w[kScanBS / 64 + 1];
-    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanIPT;
-    int v = 0;
-    for (int k = 0; k < kScanIPT; ++k)
-        if (base + k < m) v += in[base + k];
-    int total;
-    block_scan_excl<kScanBS>(v, s_w, total);
-    if (threadIdx.x == 0) partial[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(kScanBS) void k_scan_top(int *__restrict__ partial, int nb) {
-    __shared__ int s_w[kScanBS / 64 + 1];
-    int carry = 0;
-    for (int b0 = 0; b0 < nb; b0 += kScanBS) {
-        int k = b0 + threadIdx.x;
-        int v = k < nb ? partial[k] : 0;
-        int total;
-        int e = block_scan_excl<kScanBS>(v, s_w, total);
-        if (k < nb) partial[k] = e + carry;
-        carry += total;
+__global__ __launch_bounds__(kLbBS) void k_scan_lb(int *__restrict__ counts, int64_t m,
+                                                   int *__restrict__ out,
+                                                   unsigned long long *__restrict__ status,
+                                                   int *__restrict__ done,
+                                                   uint32_t *__restrict__ flags,
+                                                   unsigned long long limit) {
+    __shared__ int s_w[kLbBS / 64 + 1];
+    __shared__ int s_excl, s_last;
+    const int b = (int)blockIdx.x, tid = (int)threadIdx.x, lane = tid & 63;
+    const int64_t base = (int64_t)b * kLbTile + (int64_t)tid * kLbIPT;
+    int v[kLbIPT];
+    if (base + kLbIPT <= m) {  // 16-byte aligned: counts come from hipMalloc
+        const int4 q = *reinterpret_cast<const int4 *>(counts + base);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kLbIPT; ++k) v[k] = base + k < m ? counts[base + k] : 0;
     }
-}
-
-// (the last pass over the cell counters: it also clears them for the next
-// build, so no separate fill is needed)
-__global__ __launch_bounds__(kScanBS) void k_scan_final(int *__restrict__ in, int64_t m,
-                                                        const int *__restrict__ partial,
-                                                        int *__restrict__ out) {
-    __shared__ int s_w[kScanBS / 64 + 1];
-    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanIPT;
-    int v[kScanIPT];
-    int sum = 0;
-    for (int k = 0; k < kScanIPT; ++k) {
-        v[k] = base + k < m ? in[base + k] : 0;
-        sum += v[k];
-    }
-    for (int k = 0; k < kScanIPT; ++k)
-        if (base + k < m) in[base + k] = 0;
-    int total;
-    int e = block_scan_excl<kScanBS>(sum, s_w, total) + partial[blockIdx.x];
-    for (int k = 0; k < kScanIPT; ++k) {
-        if (base + k < m) out[base + k] = e;
-        e += v[k];
-    }
-    // the end marker: total particle count
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[m] = partial[blockIdx.x] + total;
-}
-
-// Exclusive scan of up to kScanOneMax cell counters by one work-group, with
-// the end marker, clearing the counters as it goes.  Thread t owns one run of
-// `per4` int4 words; all its loads are issued before the one work-group
-// scan, so a small grid costs one memory round trip and one launch instead
-// of three.  Needs a 16-byte aligned output.
-constexpr int kScanOneBS = 1024, kScanOneVec = 16;
-constexpr int kScanOneMax = kScanOneBS * kScanOneVec * 4;
-
-__global__ __launch_bounds__(kScanOneBS) void k_scan_one(int *__restrict__ counts, int m,
-                                                         int *__restrict__ out) {
-    __shared__ int s_w[kScanOneBS / 64 + 1];
-    const int per4 = (m + 4 * kScanOneBS - 1) / (4 * kScanOneBS);
-    const int b4 = (int)threadIdx.x * per4, m4 = m >> 2;
-    int4 *c4 = reinterpret_cast<int4 *>(counts);  // hipMalloc: 256-B aligned
-    int4 *o4 = reinterpret_cast<int4 *>(out);
-    int4 v[kScanOneVec];
     int sum = 0;
 #pragma unroll
-    for (int j = 0; j < kScanOneVec; ++j) {
-        const int q = b4 + j;
-        v[j] = make_int4(0, 0, 0, 0);
-        if (j < per4) {
-            if (q < m4) {
-                v[j] = c4[q];
-            } else if (q == m4) {  // the ragged last word
-                const int e = 4 * q;
-                v[j].x = e < m ? counts[e] : 0;
-                v[j].y = e + 1 < m ? counts[e + 1] : 0;
-                v[j].z = e + 2 < m ? counts[e + 2] : 0;
-            }
-        }
-        sum += v[j].x + v[j].y + v[j].z + v[j].w;
-    }
+    for (int k = 0; k < kLbIPT; ++k) sum += v[k];
     int total;
-    int run = block_scan_excl<kScanOneBS>(sum, s_w, total);
-#pragma unroll
-    for (int j = 0; j < kScanOneVec; ++j) {
-        const int q = b4 + j;
-        if (j < per4) {
-            const int4 o = make_int4(run, run + v[j].x, run + v[j].x + v[j].y,
-                                     run + v[j].x + v[j].y + v[j].z);
-            if (q < m4) {
-                o4[q] = o;
-                c4[q] = make_int4(0, 0, 0, 0);
-            } else if (q == m4) {
-                const int e = 4 * q;
-                if (e < m) { out[e] = o.x; counts[e] = 0; }
-                if (e + 1 < m) { out[e + 1] = o.y; counts[e + 1] = 0; }
-                if (e + 2 < m) { out[e + 2] = o.z; counts[e + 2] = 0; }
+    int run = block_scan_excl<kLbBS>(sum, s_w, total);
+    if (tid == 0)
+        __hip_atomic_store(&status[b], (b == 0 ? kLbPre : kLbAgg) | (uint32_t)total,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid < 64) {  // look-back by the first wave
+        int excl = 0;
+        bool ok = true;
+        const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+        for (int w = b - 1; w >= 0 && ok; w -= 64) {
+            const int q = w - lane;  // lane 0: the nearest lower tile
+            unsigned long long sv = 0ull;
+            if (q >= 0) {
+                for (;;) {
+                    sv = __hip_atomic_load(&status[q], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (sv >> 62) break;
+                    if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+                        atomicOr(flags, (uint32_t)LC_FLAG_ABORT);
+                        sv = kLbPre;  // give up: the output is wrong, the wait ends
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
             }
+            // the nearest tile with an inclusive prefix ends the walk
+            const unsigned long long pre = __ballot(q >= 0 && (sv >> 62) == 2ull);
+            const int stop = pre ? (int)__builtin_ctzll(pre) : 64;
+            int val = (q >= 0 && lane <= stop) ? (int)(uint32_t)sv : 0;
+            excl += wave_sum64((long long)val);  // wave-uniform
+            if (pre) ok = false;
         }
-        run += v[j].x + v[j].y + v[j].z + v[j].w;
+        if (tid == 0) {
+            s_excl = excl;
+            if (b > 0)
+                __hip_atomic_store(&status[b], kLbPre | (uint32_t)(excl + total),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
-    if (threadIdx.x == 0) out[m] = total;
+    __syncthreads();
+    run += s_excl;
+#pragma unroll
+    for (int k = 0; k < kLbIPT; ++k) {
+        if (base + k < m) {
+            out[base + k] = run;
+            counts[base + k] = 0;
+            run += v[k];
+        }
+    }
+    if (b == (int)gridDim.x - 1 && tid == 0) out[m] = s_excl + total;
+    // the last work-group out clears the status words
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(done, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (s_last) {
+        for (int q = tid; q < (int)gridDim.x; q += kLbBS) status[q] = 0ull;
+        if (tid == 0) *done = 0;
+    }
 }
 
 // cell_start from the cell counters (which are left cleared).
 static int scan_counts(lc_workspace *ws, int64_t m, int32_t *cell_start, hipStream_t st) {
-    if (m <= kScanOneMax && ((uintptr_t)cell_start & 15u) == 0) {
-        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kScanOneBS), 0, st, ws->counts, (int)m,
-                           cell_start);
-        LAUNCHCHK("k_scan_one");
-        return LC_OK;
-    }
-    const int nb = (int)((m + kScanTile - 1) / kScanTile);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBS), 0, st, ws->counts, m, ws->partial);
-    LAUNCHCHK("k_scan_reduce");
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBS), 0, st, ws->partial, nb);
-    LAUNCHCHK("k_scan_top");
-    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanBS), 0, st, ws->counts, m, ws->partial,
-                       cell_start);
-    LAUNCHCHK("k_scan_final");
+    const int64_t nt = (m + kLbTile - 1) / kLbTile;
+    if (nt < 1 || nt > ws->lb_tiles) return fail(LC_ECAPACITY, "scan: %lld cells", (long long)m);
+    hipLaunchKernelGGL(k_scan_lb, dim3((unsigned)nt), dim3(kLbBS), 0, st, ws->counts, m, cell_start,
+                       ws->lb_status, ws->lb_done, ws->flags,
+                       100000000ull /* 1 s of s_memrealtime */);
+    LAUNCHCHK("k_scan_lb");
     return LC_OK;
 }
 
@@ -2165,7 +2150,6 @@ extern "C" void lc_workspace_destroy(lc_workspace *ws) {
     (void)hipFree(ws->cid);
     (void)hipFree(ws->rank);
     (void)hipFree(ws->counts);
-    (void)hipFree(ws->partial);
     (void)hipFree(ws->flags);
     (void)hipFree(ws->ew);
     (void)hipFree(ws->part);
@@ -2176,6 +2160,8 @@ extern "C" void lc_workspace_destroy(lc_workspace *ws) {
     (void)hipFree(ws->df_sync);
     (void)hipFree(ws->df_ctl);
     (void)hipFree(ws->pbuf);
+    (void)hipFree(ws->lb_status);
+    (void)hipFree(ws->lb_done);
     (void)hipSetDevice(cur);
     delete ws;
 }
@@ -2187,20 +2173,26 @@ extern "C" int lc_workspace_create(int64_t max_n, int64_t max_cells, lc_workspac
     HIPCHK(hipGetDevice(&ws->device));
     ws->max_n = max_n;
     ws->max_cells = max_cells;
+    ws->lb_tiles = (max_cells + kLbTile - 1) / kLbTile;
     int rc = 0;
-    const int64_t nb = (max_cells + kScanTile - 1) / kScanTile;
     if ((rc = dalloc(&ws->cid, max_n)) || (rc = dalloc(&ws->rank, max_n)) ||
-        (rc = dalloc(&ws->counts, max_cells)) || (rc = dalloc(&ws->partial, nb + 1)) ||
+        (rc = dalloc(&ws->counts, max_cells)) ||
         (rc = dalloc(&ws->flags, 1)) || (rc = dalloc(&ws->ew, 3)) ||
         (rc = dalloc(&ws->part, 3 * kPartSlots)) || (rc = dalloc(&ws->ke, 1)) ||
         (rc = dalloc(&ws->xref, 3 * max_n)) || (rc = dalloc(&ws->tmp3, 3 * max_n)) ||
-        (rc = dalloc(&ws->tmpi, max_n))) {
+        (rc = dalloc(&ws->tmpi, max_n)) ||
+        (rc = dalloc(&ws->lb_status, (max_cells + kLbTile - 1) / kLbTile)) ||
+        (rc = dalloc(&ws->lb_done, 1))) {
         lc_workspace_destroy(ws);
         return rc;
     }
     if (hipMemset(ws->flags, 0, sizeof(uint32_t)) != hipSuccess ||
         hipMemset(ws->part, 0, 3 * kPartSlots * sizeof(int64_t)) != hipSuccess ||
         hipMemset(ws->counts, 0, (size_t)max_cells * sizeof(int)) != hipSuccess ||
+        hipMemset(ws->lb_status, 0,
+                  (size_t)((max_cells + kLbTile - 1) / kLbTile) * sizeof(unsigned long long)) !=
+            hipSuccess ||
+        hipMemset(ws->lb_done, 0, sizeof(int32_t)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         lc_workspace_destroy(ws);
         return fail(LC_EHIP, "lc_workspace_create: clearing the workspace");
@@ -2217,9 +2209,16 @@ extern "C" int lc_workspace_set_tile_hint(lc_workspace *ws, int32_t max_per_cell
 
 extern "C" int lc_workspace_clear_status(lc_workspace *ws, void *stream) {
     if (!ws) return fail(LC_EINVAL, "null workspace");
-    // also the energy slots, which a failed evaluation may have left dirty
-    int rc = fill64((long long *)ws->part, 3 * kPartSlots, (hipStream_t)stream);
-    return rc ? rc : fill32((int *)ws->flags, 1, (hipStream_t)stream);
+    // also the energy slots, which a failed evaluation may have left dirty,
+    // and the cell build's counters and scan status words, which an
+    // abandoned scan may have left set
+    hipStream_t st = (hipStream_t)stream;
+    int rc = fill64((long long *)ws->part, 3 * kPartSlots, st);
+    if (!rc) rc = fill32((int *)ws->flags, 1, st);
+    if (!rc) rc = fill32(ws->counts, ws->max_cells, st);
+    if (!rc) rc = fill64((long long *)ws->lb_status, ws->lb_tiles, st);
+    if (!rc) rc = fill32(ws->lb_done, 1, st);
+    return rc;
 }
 
 extern "C" int lc_workspace_status(lc_workspace *ws, void *stream, uint32_t *flags) {

@@ -78,8 +78,8 @@ def test_batch_build_cells_matches_oracle():
 
 
 def test_batch_many_cells_three_pass_scan():
-    """Dilute boxes whose cells total more than 65,536, so the batched cell
-    build takes the three-pass scan: cell tables and forces bit-exact per box,
+    """Dilute boxes whose cells total more than 65,536 (many scan tiles
+    looking back over each other): cell tables and forces bit-exact per box,
     twice on one workspace (the counters are left cleared between builds)."""
     boxes = synth.boxes(30, 1500, 3000, 0.04, 0.08, rc=2.5, seed=13)
     grids = [lc.Grid(b.L, b.rc) for b in boxes]

@@ -79,10 +79,10 @@ def test_build_cells_c1():
 
 
 def test_cell_build_reuses_workspace_counters():
-    """Each scan leaves the per-cell counters cleared for the next build:
-    builds on one workspace that alternate a grid scanned by one work-group
-    (6^3 cells) and one scanned in three passes (41^3 = 68,921 cells, above
-    the one-work-group limit of 65,536) all match the oracle's cell table."""
+    """Each scan leaves the per-cell counters and its tile status words
+    cleared for the next build: builds on one workspace that alternate a
+    grid of one scan tile (6^3 cells) and one of 17 tiles (41^3 = 68,921
+    cells) all match the oracle's cell table."""
     small = synth.fcc(4000, 0.8, rc=2.5, seed=51)
     big = synth.fcc(20000, 0.0185, rc=2.5, seed=52)
     gs, gb = lc.Grid(small.L, small.rc), lc.Grid(big.L, big.rc)
@@ -132,7 +132,7 @@ def test_cell_build_sizes_and_orders():
 
 def test_cell_build_two_million():
     """The 2M slab (dense and dilute cells, 64^3 = 262,144 cells: the
-    three-pass scan)."""
+    64 scan tiles)."""
     box = synth.workload("slab2m")
     g = lc.Grid(box.L, box.rc)
     ws = lc.Workspace(box.n, g.ncell)
