@@ -1442,8 +1442,10 @@ __global__ __launch_bounds__(256) void k_gather_partials(
 // take work units in creation order (Sec. VI strategy 2, and the mutual
 // exclusion Sec. VII asks for).
 // ---------------------------------------------------------------------------
-constexpr int kDfCell = 256;  // largest cell a runner stages (LDS)
-constexpr int kDfPre = kDfCell / 64;  // particles of cell A per lane
+// Largest cell a runner stages (LDS): CELL = 64 when the workspace's tile
+// hint allows it (15 KB of LDS per runner at 256, under 4 KB at 64, so
+// about three times as many runners fit a compute unit), else 256.
+constexpr int kDfCell = 256;
 
 struct DfArgs {
     const int32_t *ta, *tb;      // tasks in creation order: cells A, B
@@ -1539,13 +1541,16 @@ __device__ __forceinline__ bool df_wait2(const DfArgs &a, int A, int B, int qa, 
 // critical path): the two cells, their particle ranges, cell A's box
 // fractions (particle lane + 64 r in register r) and the box fraction of
 // cell B's particle `lane`.
+template <int CELL>
 struct DfPre {
+    static constexpr int kPer = CELL / 64;  // particles of cell A per lane
     int A, B, sA, na, sB, nb;
-    uint32_t ax[kDfPre], ay[kDfPre], az[kDfPre];
+    uint32_t ax[kPer], ay[kPer], az[kPer];
     uint4 ub;
 };
 
-__device__ __forceinline__ void df_load(const DfArgs &a, int64_t t, DfPre &p) {
+template <int CELL>
+__device__ __forceinline__ void df_load(const DfArgs &a, int64_t t, DfPre<CELL> &p) {
     const int lane = threadIdx.x;
     const int64_t n = a.n;
     p.A = a.ta[t];
@@ -1555,7 +1560,7 @@ __device__ __forceinline__ void df_load(const DfArgs &a, int64_t t, DfPre &p) {
     p.sB = a.cell_start[p.B];
     p.nb = a.cell_start[p.B + 1] - p.sB;
 #pragma unroll
-    for (int r = 0; r < kDfPre; ++r) {
+    for (int r = 0; r < DfPre<CELL>::kPer; ++r) {
         const int k = lane + 64 * r;
         if (k < p.na) {
             p.ax[r] = a.coord[p.sA + k];
@@ -1580,20 +1585,21 @@ __device__ __forceinline__ void df_load(const DfArgs &a, int64_t t, DfPre &p) {
 // of several L2 caches (one per XCD) writes back and invalidates a whole L2
 // each time; integer adds commute, so the result is the same.  The caller
 // waits for the adds to complete before it releases the cells.
-__device__ __forceinline__ void df_task(const DfArgs &a, const DfPre &p, uint32_t (*su)[kDfCell],
-                                        long long (*acc)[kDfCell], long long (*accb)[kDfCell],
+template <int CELL>
+__device__ __forceinline__ void df_task(const DfArgs &a, const DfPre<CELL> &p, uint32_t (*su)[CELL],
+                                        long long (*acc)[CELL], long long (*accb)[CELL],
                                         long long &e_sum, long long &w_sum, long long &p_cnt,
                                         uint32_t &ovf) {
     const int lane = threadIdx.x;
     const int64_t n = a.n;
     const int na = p.na, nb = p.nb, sA = p.sA, sB = p.sB;
-    if (na > kDfCell || nb > kDfCell) {  // the host checks the tile hint first
+    if (na > CELL || nb > CELL) {  // the host checks the tile hint first
         if (lane == 0) atomicOr(a.flags, (uint32_t)LC_FLAG_OVERFLOW);
         return;
     }
     const bool intra = p.A == p.B;
 #pragma unroll
-    for (int r = 0; r < kDfPre; ++r) {
+    for (int r = 0; r < DfPre<CELL>::kPer; ++r) {
         const int k = lane + 64 * r;
         if (k < na) {
             su[0][k] = p.ax[r];
@@ -1605,7 +1611,7 @@ __device__ __forceinline__ void df_task(const DfArgs &a, const DfPre &p, uint32_
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    long long(*accj)[kDfCell] = intra ? acc : accb;
+    long long(*accj)[CELL] = intra ? acc : accb;
     const int parts = (nb > 0 && nb <= 64) ? 64 / nb : 1;
     for (int j0 = 0; j0 < nb; j0 += 64) {
         const int jr = parts > 1 ? lane % nb : lane;  // B particle within this chunk
@@ -1676,12 +1682,13 @@ __device__ __forceinline__ void df_ticket(const DfArgs &a, int64_t at) {
 }
 
 // MODE 0: ordered (sequence counters), 1: mutual exclusion per task,
-// 2: nested (a chain per unit, mutual exclusion per task).
-template <int MODE>
+// 2: nested (a chain per unit, mutual exclusion per task).  CELL: the
+// largest cell staged (64 or 256 particles).
+template <int MODE, int CELL>
 __global__ __launch_bounds__(64) void k_dataflow(DfArgs a) {
-    __shared__ uint32_t su[3][kDfCell];
-    __shared__ long long acc[3][kDfCell];
-    __shared__ long long accb[3][kDfCell];
+    __shared__ uint32_t su[3][CELL];
+    __shared__ long long acc[3][CELL];
+    __shared__ long long accb[3][CELL];
     const int lane = threadIdx.x;
     long long e_sum = 0, w_sum = 0, p_cnt = 0;
     uint32_t ovf = 0;
@@ -1709,8 +1716,8 @@ __global__ __launch_bounds__(64) void k_dataflow(DfArgs a) {
         const int64_t t1 = MODE == 2 ? t0 + a.chain : t0 + 1;
         ++unit;
         for (int64_t t = t0; t < t1; ++t) {
-            DfPre p;
-            df_load(a, t, p);  // in flight while the cells are awaited
+            DfPre<CELL> p;
+            df_load<CELL>(a, t, p);  // in flight while the cells are awaited
             const int A = p.A, B = p.B;
             const int lo = A < B ? A : B, hi = A < B ? B : A;
             if constexpr (MODE == 0) {
@@ -1732,7 +1739,7 @@ __global__ __launch_bounds__(64) void k_dataflow(DfArgs a) {
                 }
             }
             df_ticket(a, t);
-            df_task(a, p, su, acc, accb, e_sum, w_sum, p_cnt, ovf);
+            df_task<CELL>(a, p, su, acc, accb, e_sum, w_sum, p_cnt, ovf);
             // the task has finished when its force adds have completed:
             // wait for them (the whole wave's memory operations) before the
             // end ticket and the release
@@ -2700,22 +2707,25 @@ extern "C" int lc_selftest_recip(uint32_t lo_bits, uint32_t hi_bits, uint64_t *m
     return LC_OK;
 }
 
-template <int MODE>
+template <int MODE, int CELL>
 static int launch_dataflow(const DfArgs &a, int ncu, hipStream_t st) {
     static int per_cu = 0;
     int res = per_cu;
     if (res == 0) {
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &nb, reinterpret_cast<const void *>(&k_dataflow<MODE>), 64, 0) == hipSuccess &&
+                &nb, reinterpret_cast<const void *>(&k_dataflow<MODE, CELL>), 64, 0) ==
+                hipSuccess &&
             nb >= 1)
             per_cu = res = nb;
         else
             res = 1;
     }
-    const int64_t grid = std::min<int64_t>(a.nunit, (int64_t)res * ncu);
+    // at most 10 runners per compute unit (what the 256-particle tiles allow):
+    // more only add contention on the unit counter and the cell locks
+    const int64_t grid = std::min<int64_t>(a.nunit, (int64_t)std::min(res, 10) * ncu);
     if (grid > 0) {
-        hipLaunchKernelGGL(k_dataflow<MODE>, dim3((unsigned)grid), dim3(64), 0, st, a);
+        hipLaunchKernelGGL((k_dataflow<MODE, CELL>), dim3((unsigned)grid), dim3(64), 0, st, a);
         LAUNCHCHK("k_dataflow");
     }
     return LC_OK;
@@ -2779,12 +2789,15 @@ extern "C" int lc_compute_forces_dataflow_log(const lc_grid *g, const lc_schedul
     a.flags = ws->flags;
     a.pp = pair_params(g);
     a.limit = (unsigned long long)(limit_ms * 1.0e5);  // s_memrealtime: 100 MHz
+    // small cells (the tile hint, set by the cell build) take the runner
+    // with 64-particle tiles: more runners per compute unit
+    const bool small = ws->max_per_cell > 0 && ws->max_per_cell <= 64;
     if (mode == LC_DF_ORDERED)
-        rc = launch_dataflow<0>(a, s->ncu, st);
+        rc = small ? launch_dataflow<0, 64>(a, s->ncu, st) : launch_dataflow<0, 256>(a, s->ncu, st);
     else if (mode == LC_DF_MUTEX)
-        rc = launch_dataflow<1>(a, s->ncu, st);
+        rc = small ? launch_dataflow<1, 64>(a, s->ncu, st) : launch_dataflow<1, 256>(a, s->ncu, st);
     else
-        rc = launch_dataflow<2>(a, s->ncu, st);
+        rc = small ? launch_dataflow<2, 64>(a, s->ncu, st) : launch_dataflow<2, 256>(a, s->ncu, st);
     if (rc) return rc;
     hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (long long *)ws->part, 3,
                        (long long *)ew, 0);
