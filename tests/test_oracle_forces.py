@@ -284,3 +284,34 @@ def test_subset_brute_force_matches_sweep():
     Fs, nn = O.forces_subset_fx(u, b.L, b.rc, idx)
     assert (Fs == Fq[:, idx]).all()
     assert nn.sum() <= 2 * npairs
+
+
+def test_fp32_error_within_derived_bound():
+    """The canonical FP32 pair arithmetic against FP64, per particle and
+    component, within a bound derived from its rounding steps (unit
+    u = 2^-24, first order, factor 2 of margin): the separation carries 3u
+    (int-to-float, scale, the rounded box scale), r^2 9u, 1/r^2 10u, s6 32u,
+    (24/r^2) s6 44u; 2 s6 - 1 cancels near the force zero, so its error is
+    taken against 2 s6 + 1, which gives per pair
+    |delta f_x| <= u (24 s6 / r^2) (164 s6 + 50) |d_x|, plus 2^-33 of
+    rounding to the fixed-point grid per pair."""
+    b = _tiny(500, 0.85, seed=31)
+    u = O.canonical(b.pos, b.L)
+    Fq, _, _, _ = O.forces_brute_fx(u, b.L, b.rc)
+    F64, _, _, _, npairs = O.forces_brute_f64(b.pos, b.L, b.rc, u=u)
+    L = np.asarray(b.L)[:, None, None]
+    d = b.pos[:, None, :] - b.pos[:, :, None]   # d[:, i, j] = r_j - r_i
+    d -= L * np.round(d / L)
+    r2 = (d ** 2).sum(axis=0)
+    np.fill_diagonal(r2, np.inf)
+    inside = r2 < (b.rc * (1 + 1e-6)) ** 2       # a superset of the FP32 pair set
+    s6 = np.where(inside, r2 ** -3.0, 0.0)
+    amp = np.where(inside, 24.0 * s6 / r2 * (164.0 * s6 + 50.0), 0.0)
+    uu = 2.0 ** -24
+    bound = 2.0 * (uu * (amp[None] * np.abs(d)).sum(axis=2)
+                   + inside.sum(axis=1)[None] * 2.0 ** -33)
+    err = np.abs(Fq / S - F64)
+    assert npairs > 10000
+    assert (err <= bound).all(), float((err / bound).max())
+    # and the bound is not vacuous: the errors reach a fair share of it
+    assert float((err / bound).max()) > 0.01
