@@ -327,3 +327,68 @@ def test_new_entry_points_reject_bad_arguments():
     g = lc.Grid((17.0998,) * 3, 2.5)
     with pytest.raises(lc.LCError):  # wrong number of cell counts
         lc.Schedule(g, "buffer", cell_counts=np.zeros(g.ncell - 1, dtype=np.int32))
+
+
+def _concurrent_rmw(ncell, phases):
+    """Run phases of groups the way a plain read-modify-write kernel does
+    when its work-groups run at once: every group reads its cells at the
+    start of the phase, adds its tasks' contributions (one unit per cell a
+    task writes) and stores the cells back, later groups over earlier ones."""
+    F = np.zeros(ncell, dtype=np.int64)
+    for groups in phases:
+        snap = F.copy()
+        for tasks in groups:
+            cells = sorted({c for t in tasks for c in set(t)})
+            acc = {c: int(snap[c]) for c in cells}
+            for t in tasks:
+                for c in set(t):
+                    acc[c] += 1
+            for c in cells:
+                F[c] = acc[c]
+    return F
+
+
+def _as_phase_arrays(phases):
+    pg, gf, fc = [0], [0], []
+    for groups in phases:
+        for tasks in groups:
+            fc.extend(sorted({c for t in tasks for c in set(t)}))
+            gf.append(len(fc))
+        pg.append(len(gf) - 1)
+    return pg, gf, fc
+
+
+def test_race_canary():
+    """The loop-exchange phases of Sec. VI (for every stencil offset, the
+    cells of one parity class, one task per group) pass the validator and a
+    concurrent plain read-modify-write gives the sequential sums; merging two
+    parity classes into one phase is rejected by the validator (LC_ESCHED),
+    and run anyway it loses updates (the race canary)."""
+    dims = (4, 4, 4)
+    nx, ny, nz = dims
+    ncell = nx * ny * nz
+    cid = lambda x, y, z: (x % nx) + nx * ((y % ny) + ny * (z % nz))
+    offsets = [(0, 0, 0)] + [tuple(d) for d in O.H3]
+    seq = np.zeros(ncell, dtype=np.int64)
+    good, bad = [], []
+    for d in offsets:
+        classes = []
+        for par in itertools.product((0, 1), repeat=3):
+            tasks = []
+            for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
+                if (x % 2, y % 2, z % 2) == par:
+                    t = (cid(x, y, z), cid(x + d[0], y + d[1], z + d[2]))
+                    tasks.append(t)
+                    for c in set(t):
+                        seq[c] += 1
+            classes.append([[t] for t in tasks])
+        good.extend(classes)
+        # two classes one cell apart along x in one phase
+        bad.extend([classes[0] + classes[1]] + classes[2:])
+    lc.validate_phases(ncell, *_as_phase_arrays(good))
+    assert (_concurrent_rmw(ncell, good) == seq).all()
+    with pytest.raises(lc.LCError) as e:
+        lc.validate_phases(ncell, *_as_phase_arrays(bad))
+    assert e.value.code == -4
+    lost = seq - _concurrent_rmw(ncell, bad)
+    assert (lost >= 0).all() and lost.sum() > 0
