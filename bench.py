@@ -549,12 +549,13 @@ def _time_evals(fn, steps, warmup):
 # algorithmic bytes of the cell build: read the positions (3 x f64), write
 # the permutation (int32) and the box fractions (3 x u32) of every particle,
 # and cell_start (int32) of every cell.  The counting sort as built moves
-# 84 B per particle: the bin pass reads the positions and writes cell and
-# rank (32 B), the scatter pass reads them again with cell and rank and the
-# cell's start and writes the permutation and box fractions (52 B).
+# 64 B per particle: the count pass reads the positions (24 B) and stores
+# nothing per particle; the scatter pass reads them again and writes the
+# permutation and box fractions (40 B).  The per-cell counters and starts
+# stay in the L2 caches.
 BUILD_BYTES_PER_PARTICLE = 24 + 4 + 12
 BUILD_BYTES_PER_CELL = 4
-BUILD_BYTES_MOVED_PER_PARTICLE = 84
+BUILD_BYTES_MOVED_PER_PARTICLE = 64
 
 
 def copy_bandwidth_gbs(nbytes=256 * 2 ** 20):

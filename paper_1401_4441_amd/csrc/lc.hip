@@ -3,11 +3,13 @@
 // Kernels
 //   k_fill64 / k_fill32     zero-fill (used instead of hipMemsetAsync so the
 //                           whole path can sit inside a captured graph)
-//   k_bin                   cell of each particle + its rank in the cell (one
-//                           counter atomic per cell and wave)
+//   k_bin                   count pass: particles per cell (one counter
+//                           atomic per cell and wave)
 //   k_scan_lb               exclusive scan of per-cell counts -> cell_start
 //                           (one pass, decoupled look-back between tiles)
-//   k_scatter               counting-sort scatter: perm + sorted box fractions
+//   k_scatter               counting-sort scatter: the cell again, a rank
+//                           claimed from the counter, perm + sorted box
+//                           fractions
 //   k_sweep<CAP,WMODE,F64,FF>  one phase of cell-cell tasks (Sec. IV): per
 //                           work-group a group of tasks whose footprint cells
 //                           are staged in LDS; lanes own j particles, loop over
@@ -79,8 +81,6 @@ extern "C" const char *lc_last_error(void) { return g_err.c_str(); }
 struct lc_workspace {
     int device = 0;
     int64_t max_n = 0, max_cells = 0;
-    int32_t *cid = nullptr;      // N: cell of particle
-    int32_t *rank = nullptr;     // N: rank inside its cell
     int32_t *counts = nullptr;   // max_cells: per-cell counters
     uint32_t *flags = nullptr;   // device status flags
     int64_t *ew = nullptr;       // 3: energy, virial, pairs
@@ -381,17 +381,14 @@ struct GridArgs {
     int nc[3];
 };
 
-// Rank of this lane's particle among the particles of its cell cc (act:
-// the lane holds a particle), from the cell counters.  The lanes of a wave
-// that fall into one cell share a single atomic: the lowest of them adds the
-// group's size and every lane takes the group's base plus its place in the
-// group.  Particles stored near each other (a lattice, or an array already
-// sorted by cell) then cost one counter update per cell and wave instead of
-// one per particle, all of them on the same address.
-__device__ __forceinline__ int wave_cell_rank(bool act, int cc, int *__restrict__ counts) {
-    const int lane = threadIdx.x & 63;
+// The lanes of a wave that fall into one cell share a single atomic on the
+// cell's counter.  Returns this lane's mask of the active lanes in its cell
+// (0 for an inactive lane).  Particles stored near each other (a lattice, or
+// an array already sorted by cell) then cost one counter update per cell and
+// wave instead of one per particle, all of them on the same address.
+__device__ __forceinline__ unsigned long long wave_cell_group(bool act, int cc) {
     if (!act) cc = -1;
-    // group the active lanes by cell (one pass per distinct cell, at most 64)
+    // one pass per distinct cell among the active lanes (at most 64)
     unsigned long long todo = __ballot(act), mine = 0ull;
     while (todo) {
         const int lead = (int)__builtin_ctzll(todo);
@@ -400,28 +397,50 @@ __device__ __forceinline__ int wave_cell_rank(bool act, int cc, int *__restrict_
         if (cc == lcell) mine = same;
         todo &= ~same;
     }
-    const unsigned long long below = mine & ((1ull << lane) - 1ull);
-    int base = 0;
-    if (act && below == 0ull) base = atomicAdd(&counts[cc], __popcll(mine));
-    base = __shfl(base, act ? (int)__builtin_ctzll(mine) : lane);
-    return base + __popcll(below);
+    return act ? mine : 0ull;
 }
 
-// Cell of every particle and its rank in the cell.
+// Cell of a particle from its coordinates; its box fractions in u.
+__device__ __forceinline__ int cell_and_fractions(const double *__restrict__ pos, int64_t n,
+                                                  int64_t i, const double *inv, const int *nc,
+                                                  uint32_t u[3]) {
+    int c[3];
+    for (int d = 0; d < 3; ++d) {
+        u[d] = canon(pos[d * n + i], inv[d]);
+        c[d] = cell_of(u[d], nc[d]);
+    }
+    return c[0] + nc[0] * (c[1] + nc[1] * c[2]);
+}
+
+// Count pass: every particle adds one to its cell's counter.  Nothing is
+// stored per particle; the scatter pass computes the cell again.
 __global__ __launch_bounds__(256) void k_bin(const double *__restrict__ pos, int64_t n,
-                                             GridArgs ga, int *__restrict__ cid,
-                                             int *__restrict__ rank, int *__restrict__ counts) {
+                                             GridArgs ga, int *__restrict__ counts) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool act = i < n;
     int cc = 0;
-    if (act) {
-        int c[3];
-        for (int d = 0; d < 3; ++d) c[d] = cell_of(canon(pos[d * n + i], ga.inv[d]), ga.nc[d]);
-        cc = c[0] + ga.nc[0] * (c[1] + ga.nc[1] * c[2]);
-        cid[i] = cc;
-    }
-    const int r = wave_cell_rank(act, cc, counts);
-    if (act) rank[i] = r;
+    uint32_t u[3];
+    if (act) cc = cell_and_fractions(pos, n, i, ga.inv, ga.nc, u);
+    const unsigned long long mine = wave_cell_group(act, cc);
+    const int lane = threadIdx.x & 63;
+    if (mine && !(mine & ((1ull << lane) - 1ull))) atomicAdd(&counts[cc], __popcll(mine));
+}
+
+// Rank of a particle in its cell, claimed in the scatter pass: the cell's
+// counter still holds the cell's size after the scan, and every wave group
+// takes its ranks by subtracting its size, so the counters end cleared for
+// the next build.  Ranks inside a cell follow the order of the claims (the
+// order of particles within a cell is not fixed; every reader treats a cell
+// as a set).
+__device__ __forceinline__ int wave_cell_claim(bool act, int cc, int *__restrict__ counts) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long mine = wave_cell_group(act, cc);
+    const unsigned long long below = mine & ((1ull << lane) - 1ull);
+    const int k = __popcll(mine);
+    int top = 0;
+    if (mine && !below) top = atomicSub(&counts[cc], k);
+    top = __shfl(top, mine ? (int)__builtin_ctzll(mine) : lane);
+    return top - k + __popcll(below);
 }
 
 // ---- single-pass scan (decoupled look-back) ------------------------------
@@ -435,11 +454,12 @@ __global__ __launch_bounds__(256) void k_bin(const double *__restrict__ pos, int
 // (coherent across the XCDs' caches).  A tile only waits for lower tiles,
 // which the hardware dispatches first, and every wait is bounded (abort
 // flag).  The last work-group to finish clears the status words for the next
-// scan.  The counters are cleared as they are read.
+// scan.  The counters are left as they are: the scatter pass claims its
+// ranks from them and leaves them cleared.
 constexpr int kLbBS = 1024, kLbIPT = 4, kLbTile = kLbBS * kLbIPT;
 constexpr unsigned long long kLbAgg = 1ull << 62, kLbPre = 2ull << 62;
 
-__global__ __launch_bounds__(kLbBS) void k_scan_lb(int *__restrict__ counts, int64_t m,
+__global__ __launch_bounds__(kLbBS) void k_scan_lb(const int *__restrict__ counts, int64_t m,
                                                    int *__restrict__ out,
                                                    unsigned long long *__restrict__ status,
                                                    int *__restrict__ done,
@@ -508,7 +528,6 @@ __global__ __launch_bounds__(kLbBS) void k_scan_lb(int *__restrict__ counts, int
     for (int k = 0; k < kLbIPT; ++k) {
         if (base + k < m) {
             out[base + k] = run;
-            counts[base + k] = 0;
             run += v[k];
         }
     }
@@ -523,7 +542,7 @@ __global__ __launch_bounds__(kLbBS) void k_scan_lb(int *__restrict__ counts, int
     }
 }
 
-// cell_start from the cell counters (which are left cleared).
+// cell_start from the cell counters (left as they are).
 static int scan_counts(lc_workspace *ws, int64_t m, int32_t *cell_start, hipStream_t st) {
     const int64_t nt = (m + kLbTile - 1) / kLbTile;
     if (nt < 1 || nt > ws->lb_tiles) return fail(LC_ECAPACITY, "scan: %lld cells", (long long)m);
@@ -534,15 +553,20 @@ static int scan_counts(lc_workspace *ws, int64_t m, int32_t *cell_start, hipStre
     return LC_OK;
 }
 
-__global__ void k_scatter(const double *__restrict__ pos, int64_t n, GridArgs ga,
-                          const int *__restrict__ cid, const int *__restrict__ rank,
-                          const int *__restrict__ cell_start, int *__restrict__ perm,
-                          uint32_t *__restrict__ coord) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int64_t dst = (int64_t)cell_start[cid[i]] + rank[i];
+__global__ __launch_bounds__(256) void k_scatter(const double *__restrict__ pos, int64_t n,
+                                                 GridArgs ga, const int *__restrict__ cell_start,
+                                                 int *__restrict__ counts, int *__restrict__ perm,
+                                                 uint32_t *__restrict__ coord) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = i < n;
+    int cc = 0;
+    uint32_t u[3] = {0u, 0u, 0u};
+    if (act) cc = cell_and_fractions(pos, n, i, ga.inv, ga.nc, u);
+    const int r = wave_cell_claim(act, cc, counts);
+    if (!act) return;
+    const int64_t dst = (int64_t)cell_start[cc] + r;
     perm[dst] = (int)i;
-    for (int d = 0; d < 3; ++d) coord[d * n + dst] = canon(pos[d * n + i], ga.inv[d]);
+    for (int d = 0; d < 3; ++d) coord[d * n + dst] = u[d];
 }
 
 static int build_cells_impl(const lc_grid *g, const double *pos, int64_t n, int32_t *cell_start,
@@ -553,18 +577,18 @@ static int build_cells_impl(const lc_grid *g, const double *pos, int64_t n, int3
         ga.inv[d] = g->inv_box[d];
         ga.nc[d] = g->nc[d];
     }
-    // the cell counters are clear: the workspace starts so and every scan
-    // leaves them so
+    // the cell counters are clear: the workspace starts so and every scatter
+    // pass leaves them so
     if (n > 0) {
         hipLaunchKernelGGL(k_bin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n, ga,
-                           ws->cid, ws->rank, ws->counts);
+                           ws->counts);
         LAUNCHCHK("k_bin");
     }
     int rc = scan_counts(ws, m, cell_start, st);
     if (rc) return rc;
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n,
-                           ga, ws->cid, ws->rank, cell_start, perm, coord);
+                           ga, cell_start, ws->counts, perm, coord);
         LAUNCHCHK("k_scatter");
     }
     return LC_OK;
@@ -2154,8 +2178,6 @@ extern "C" void lc_workspace_destroy(lc_workspace *ws) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(ws->device);
-    (void)hipFree(ws->cid);
-    (void)hipFree(ws->rank);
     (void)hipFree(ws->counts);
     (void)hipFree(ws->flags);
     (void)hipFree(ws->ew);
@@ -2182,8 +2204,7 @@ extern "C" int lc_workspace_create(int64_t max_n, int64_t max_cells, lc_workspac
     ws->max_cells = max_cells;
     ws->lb_tiles = (max_cells + kLbTile - 1) / kLbTile;
     int rc = 0;
-    if ((rc = dalloc(&ws->cid, max_n)) || (rc = dalloc(&ws->rank, max_n)) ||
-        (rc = dalloc(&ws->counts, max_cells)) ||
+    if ((rc = dalloc(&ws->counts, max_cells)) ||
         (rc = dalloc(&ws->flags, 1)) || (rc = dalloc(&ws->ew, 3)) ||
         (rc = dalloc(&ws->part, 3 * kPartSlots)) || (rc = dalloc(&ws->ke, 1)) ||
         (rc = dalloc(&ws->xref, 3 * max_n)) || (rc = dalloc(&ws->tmp3, 3 * max_n)) ||
@@ -2957,33 +2978,37 @@ __device__ __forceinline__ int box_of(const int64_t *__restrict__ pstart, int nb
 __global__ __launch_bounds__(256) void k_bin_batch(const double *__restrict__ pos, int64_t ntot,
                                                    const int64_t *__restrict__ pstart, int nbox,
                                                    const BoxGeo *__restrict__ geo,
-                                                   int *__restrict__ cid, int *__restrict__ rank,
                                                    int *__restrict__ counts) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool act = i < ntot;
     int cc = 0;
+    uint32_t u[3];
     if (act) {
         const BoxGeo gb = geo[box_of(pstart, nbox, i)];
-        int c[3];
-        for (int d = 0; d < 3; ++d) c[d] = cell_of(canon(pos[d * ntot + i], gb.inv[d]), gb.nc[d]);
-        cc = gb.cstart + c[0] + gb.nc[0] * (c[1] + gb.nc[1] * c[2]);
-        cid[i] = cc;
+        cc = gb.cstart + cell_and_fractions(pos, ntot, i, gb.inv, gb.nc, u);
     }
-    const int r = wave_cell_rank(act, cc, counts);
-    if (act) rank[i] = r;
+    const unsigned long long mine = wave_cell_group(act, cc);
+    const int lane = threadIdx.x & 63;
+    if (mine && !(mine & ((1ull << lane) - 1ull))) atomicAdd(&counts[cc], __popcll(mine));
 }
 
-__global__ void k_scatter_batch(const double *__restrict__ pos, int64_t ntot,
-                                const int64_t *__restrict__ pstart, int nbox,
-                                const BoxGeo *__restrict__ geo, const int *__restrict__ cid,
-                                const int *__restrict__ rank, const int *__restrict__ cell_start,
-                                int *__restrict__ perm, uint32_t *__restrict__ coord) {
+__global__ __launch_bounds__(256) void k_scatter_batch(
+    const double *__restrict__ pos, int64_t ntot, const int64_t *__restrict__ pstart, int nbox,
+    const BoxGeo *__restrict__ geo, const int *__restrict__ cell_start, int *__restrict__ counts,
+    int *__restrict__ perm, uint32_t *__restrict__ coord) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ntot) return;
-    const BoxGeo gb = geo[box_of(pstart, nbox, i)];
-    const int64_t dst = (int64_t)cell_start[cid[i]] + rank[i];
+    const bool act = i < ntot;
+    int cc = 0;
+    uint32_t u[3] = {0u, 0u, 0u};
+    if (act) {
+        const BoxGeo gb = geo[box_of(pstart, nbox, i)];
+        cc = gb.cstart + cell_and_fractions(pos, ntot, i, gb.inv, gb.nc, u);
+    }
+    const int r = wave_cell_claim(act, cc, counts);
+    if (!act) return;
+    const int64_t dst = (int64_t)cell_start[cc] + r;
     perm[dst] = (int)i;
-    for (int d = 0; d < 3; ++d) coord[d * ntot + dst] = canon(pos[d * ntot + i], gb.inv[d]);
+    for (int d = 0; d < 3; ++d) coord[d * ntot + dst] = u[d];
 }
 
 struct lc_batch {
@@ -3266,15 +3291,15 @@ extern "C" int lc_batch_build_cells(const lc_batch *b, const double *pos, int32_
     // the cell counters are clear (see build_cells_impl)
     if (n > 0) {
         hipLaunchKernelGGL(k_bin_batch, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n,
-                           (const int64_t *)b->d_pstart, b->nbox, (const BoxGeo *)b->d_geo, ws->cid,
-                           ws->rank, ws->counts);
+                           (const int64_t *)b->d_pstart, b->nbox, (const BoxGeo *)b->d_geo,
+                           ws->counts);
         LAUNCHCHK("k_bin_batch");
     }
     if ((rc = scan_counts(ws, m, cell_start, st))) return rc;
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter_batch, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos,
                            n, (const int64_t *)b->d_pstart, b->nbox, (const BoxGeo *)b->d_geo,
-                           ws->cid, ws->rank, cell_start, perm, coord);
+                           cell_start, ws->counts, perm, coord);
         LAUNCHCHK("k_scatter_batch");
     }
     return LC_OK;
