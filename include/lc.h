@@ -188,10 +188,14 @@ int lc_gather(const int32_t *perm, int64_t n, const double *in3, double *out3,
 #define LC_SCHED_LOOPEX 4       /* loop exchange + 2-strided colouring
                                    (offset-major, 2x2x2 colours; needs even
                                    cell counts); run as DAG levels (27)     */
-#define LC_SCHED_BLOCK8 5       /* 2x2x2-coloured blocks of 2-3 cells per
-                                   axis: 8 conflict-free phases, one work-
-                                   group per block, LDS accumulation, plain
-                                   read-modify-write                        */
+#define LC_SCHED_BLOCK8 5       /* 2x2x2-coloured blocks of cells: 8
+                                   conflict-free phases, one work-group per
+                                   block, LDS accumulation, plain read-
+                                   modify-write.  A task joins the block of
+                                   its lower corner cell (per axis the
+                                   smaller coordinate of its two cells), so
+                                   a block's footprint is the block grown by
+                                   the stencil's reach towards +x, +y, +z */
 #define LC_SCHED_ATOMIC_TILE 6  /* BLOCK8's groups in ONE phase with global
                                    int64 atomic write-back                  */
 #define LC_SCHED_ATOMIC_PAIR 7  /* one phase, one group per home cell, every
@@ -241,14 +245,17 @@ int lc_make_schedule(const lc_grid *g, int kind, const int8_t *offsets, int n,
                      lc_schedule **out);
 /* As lc_make_schedule, with the block shape of the block kinds: block_min
  * [host] 3 x int32.  LC_SCHED_BLOCK8: the smallest block per axis, at least
- * {1, 2, 2} -- the stencil reaches one cell along +x and one cell each way
- * along y and z, so same-coloured blocks stay a whole block apart -- with an
- * even block count per axis.  LC_SCHED_ATOMIC_TILE / BUFFER / FULLSHELL (uncoloured):
- * the largest block per axis, at least {1, 1, 1}; each axis is cut into
- * ceil(n / size) near-equal blocks.  NULL = the BLOCK8 partition with
- * {1, 2, 2} for all three.  Larger blocks mean fewer, bigger work-groups and
- * less halo write-back per particle; smaller ones fit denser boxes into the
- * LDS tile.  The autotuner picks the shape. */
+ * the stencil's reach (1; 2 on grids of cells of side rc/2) -- a footprint
+ * reaches that far past its block towards +x, +y and +z, so same-coloured
+ * blocks stay a whole block apart -- with an even block count per axis.
+ * LC_SCHED_ATOMIC_TILE / BUFFER / FULLSHELL (uncoloured): the largest block
+ * per axis, at least {1, 1, 1}; each axis is cut into ceil(n / size)
+ * near-equal blocks.  NULL = the BLOCK8 partition with {1, 2, 2} for all
+ * three (blocks of at most {1, 2, 2} for the uncoloured kinds on rc/2
+ * grids).  Larger blocks mean fewer, bigger work-groups and less halo
+ * write-back per particle; smaller ones fit denser boxes into the LDS tile.
+ * A work-group holds at most 512 tasks and 128 footprint cells
+ * (LC_ECAPACITY otherwise).  The autotuner picks the shape. */
 int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *offsets,
                         int n, const int32_t *block_min, lc_schedule **out);
 int lc_schedule_info_get(const lc_schedule *s, lc_schedule_info *out);

@@ -28,24 +28,29 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1401_4441
 
 BOX_KINDS_CONFLICT_FREE = ("block8", "buffer")
 # BLOCK8: lower bounds per axis (even block counts); uncoloured kinds: upper
-# bounds.  Shapes whose footprint outgrows the LDS tile lose on their own
-# (one work-group per compute unit), so they need no pruning here.
-BLOCKS = {"block8": ((1, 2, 2), (2, 2, 2), (1, 3, 3), (2, 3, 3)),
+# bounds.  Tasks join the block of their lower corner cell, so a block's
+# footprint is (bx + r)(by + r)(bz + r) cells at stencil reach r.  Shapes
+# whose footprint outgrows the LDS tile lose on their own (fewer work-groups
+# per compute unit), so they need no pruning here.
+BLOCKS = {"block8": ((1, 1, 1), (1, 1, 2), (1, 2, 2), (2, 2, 2), (1, 3, 3), (2, 3, 3)),
           "uncoloured": ((1, 2, 2), (1, 2, 3), (1, 3, 3), (2, 2, 2), (2, 2, 3), (1, 3, 4),
                          (1, 4, 4), (2, 3, 3)),
-          # cells of side rc/2: the reach-2 footprint of a block (bx + 2) x
-          # (by + 4) x (bz + 4) must stay within 128 cells
-          "uncoloured_half": ((1, 1, 1), (1, 1, 2), (2, 1, 1), (1, 2, 2), (1, 2, 3)),
-          # flat (2D) grids: one cell along z; a block's footprint is about
-          # (bx + 1) x (by + 2) cells
-          "flat": ((2, 4, 1), (4, 4, 1), (4, 8, 1), (8, 8, 1), (6, 12, 1), (8, 12, 1))}
+          # cells of side rc/2 (reach 2): at most 8 cells per block (63
+          # tasks per cell, 512 per work-group), footprints within 128 cells
+          "uncoloured_half": ((1, 1, 1), (1, 1, 2), (1, 2, 2), (1, 2, 3), (2, 2, 2),
+                              (1, 2, 4)),
+          "block8_half": ((2, 2, 2),),
+          # flat (2D) grids: one cell along z; a block's footprint is
+          # (bx + 1) x (by + 1) cells
+          "flat": ((2, 4, 1), (4, 4, 1), (4, 8, 1), (8, 8, 1), (6, 12, 1), (8, 12, 1),
+                   (10, 10, 1))}
 
 
 def shapes_for(kind: str, half: bool = False, flat: bool = False):
     if flat:
         return BLOCKS["flat"]
     if kind == "block8":
-        return BLOCKS["block8"]
+        return BLOCKS["block8_half"] if half else BLOCKS["block8"]
     return BLOCKS["uncoloured_half"] if half else BLOCKS["uncoloured"]
 GRIDS = ({"extra": 0.0, "even": True}, {"extra": 0.0, "even": False},
          {"extra": 0.15, "even": True}, {"extra": 0.0, "even": False, "half": True})

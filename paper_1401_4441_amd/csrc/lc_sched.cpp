@@ -309,16 +309,9 @@ bool add_group(HostSchedule &hs, const std::vector<int32_t> &A,
     return true;
 }
 
-// Partition n cells along an axis into an even number of blocks, each at
-// least `minsize` cells, sizes differing by at most one; a single block when
-// two blocks of minsize do not fit.  With an even count the blocks 2-colour
-// under the periodic wrap; same-coloured blocks are then separated by a
-// whole block, which keeps their write footprints apart when that block is
-// at least as wide as the stencil reaches on that side (minsize: 1 along x,
-// where the half stencil is one-sided, 2 along y and z).  Returns block start
-// offsets with n appended.
 // n cells cut into ceil(n / maxsize) near-equal blocks of at most maxsize
-// (the uncoloured block kinds: no parity or spacing constraint).
+// (the uncoloured block kinds: no parity or spacing constraint).  Returns
+// block start offsets with n appended.
 std::vector<int> axis_blocks_max(int n, int maxsize) {
     const int m = (n + maxsize - 1) / maxsize;
     const int base = n / m, extra = n % m;
@@ -331,6 +324,13 @@ std::vector<int> axis_blocks_max(int n, int maxsize) {
     return s;
 }
 
+// Partition n cells along an axis into an even number of blocks, each at
+// least `minsize` cells, sizes differing by at most one; a single block when
+// two blocks of minsize do not fit.  With an even count the blocks 2-colour
+// under the periodic wrap; same-coloured blocks are then separated by a
+// whole block, which keeps their write footprints apart when that block is
+// at least as wide as the footprint reaches past a block (the stencil's
+// reach, towards + only under corner grouping).
 std::vector<int> axis_blocks(int n, int minsize) {
     if (n < 2 * minsize) return {0, n};
     int m = n / minsize;
@@ -351,18 +351,38 @@ std::vector<int> axis_blocks(int n, int minsize) {
 // so the 64 lanes of a wave, which cover about five consecutive tasks, spread
 // their force additions over several cells' particles instead of piling them
 // onto one cell A.
+//
+// corner = false: the block's cells are the tasks' cells A (the stencil task
+// of cell A with offset o couples A and A + o); the footprint is the block
+// grown by the reach towards +x and both ways along y and z.
+// corner = true: a task joins the block that holds its lower corner, the
+// cell C = A + min(o, 0) (per axis the smaller of the two cells' coordinates,
+// the periodic wrap taken on the side the pair reaches across).  For a block
+// cell C and offset o the task couples C + max(-o, 0) and C + max(o, 0): the
+// stencil task of cell A = C + max(-o, 0), the same (A, B) pair, so the task
+// set is the stencil's and each pair is kept once.  Both cells lie in C +
+// {0..reach}^3, so the footprint is the block grown by the reach towards +x,
+// +y and +z only -- (bx + r)(by + r)(bz + r) cells against about
+// (bx + r)(by + 2r)(bz + 2r).
 void block_tasks(const int32_t nc[3], const std::vector<int> bs[3], int bx, int by, int bz,
                  const std::vector<Offset> &offs, std::vector<int32_t> &A,
-                 std::vector<int32_t> &B) {
-    for (const Offset &o : offs)
+                 std::vector<int32_t> &B, bool corner = false) {
+    auto cell = [&](int x, int y, int z) -> int32_t {
+        return (int32_t)(wrap(x, nc[0]) + nc[0] * (wrap(y, nc[1]) + nc[1] * wrap(z, nc[2])));
+    };
+    for (const Offset &o : offs) {
+        int sa[3], sb[3];  // cell A and cell B relative to the block cell
+        for (int d = 0; d < 3; ++d) {
+            sa[d] = corner ? std::max(-(int)o.d[d], 0) : 0;
+            sb[d] = sa[d] + o.d[d];
+        }
         for (int z = bs[2][bz]; z < bs[2][bz + 1]; ++z)
             for (int y = bs[1][by]; y < bs[1][by + 1]; ++y)
                 for (int x = bs[0][bx]; x < bs[0][bx + 1]; ++x) {
-                    A.push_back(x + nc[0] * (y + nc[1] * z));
-                    B.push_back((int32_t)(wrap(x + o.d[0], nc[0]) +
-                                          nc[0] * (wrap(y + o.d[1], nc[1]) +
-                                                   nc[1] * wrap(z + o.d[2], nc[2]))));
+                    A.push_back(cell(x + sa[0], y + sa[1], z + sa[2]));
+                    B.push_back(cell(x + sb[0], y + sb[1], z + sb[2]));
                 }
+    }
 }
 
 }  // namespace
@@ -380,10 +400,6 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
         err = "flat grids take the reach-1 2D stencil";
         return LC_EINVAL;
     }
-    if (reach == 2 && kind == LC_SCHED_BLOCK8) {
-        err = "no 2x2x2 block colouring at reach 2 (use buffer, atomic_tile or loopex)";
-        return LC_EINVAL;
-    }
     if (kind == LC_SCHED_CUSTOM && order_reach(offsets, n) != reach) {
         err = "custom offsets must reach as far as the grid's stencil";
         return LC_EINVAL;
@@ -391,15 +407,21 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
     // BLOCK8 colours its blocks, so their sizes are lower bounds (the
     // stencil reach) with an even block count per axis; the uncoloured kinds
     // take explicit sizes as upper bounds.
+    // (The tiled Newton-3 kinds group tasks by their lower corner cell, so
+    // a block's footprint grows by the reach towards +x, +y and +z only:
+    // same-coloured blocks stay apart when every block spans at least the
+    // reach along every axis.)
     const bool coloured = kind == LC_SCHED_BLOCK8;  // FULLSHELL: uncoloured
     int32_t bmin[3] = {1, 2, 2};
+    if (reach == 2 && coloured) bmin[0] = bmin[1] = bmin[2] = 2;
     if (block_min) {
         for (int d = 0; d < 3; ++d) bmin[d] = block_min[d];
-        const int lo_yz = coloured ? 2 : 1;
-        const int lo_z = flat ? 1 : lo_yz;  // a flat grid's z axis is one cell
-        if (bmin[0] < 1 || bmin[1] < lo_yz || bmin[2] < lo_z || bmin[0] > 64 ||
-            bmin[1] > 64 || bmin[2] > 64) {
-            err = coloured ? "block sizes must be >= {1, 2, 2} (the stencil reach) and <= 64"
+        const int lo = coloured ? reach : 1;
+        const int lo_z = flat ? 1 : lo;  // a flat grid's z axis is one cell
+        if (bmin[0] < lo || bmin[1] < lo || bmin[2] < lo_z || bmin[0] > 64 || bmin[1] > 64 ||
+            bmin[2] > 64) {
+            err = coloured ? (reach == 2 ? "block sizes must be >= 2 (the stencil reach) and <= 64"
+                                         : "block sizes must be >= 1 and <= 64")
                            : "block sizes must be >= 1 and <= 64";
             return LC_EINVAL;
         }
@@ -468,12 +490,12 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
         const int ncol[3] = {nb[0] > 1 ? 2 : 1, nb[1] > 1 ? 2 : 1, nb[2] > 1 ? 2 : 1};
         {
             // footprint extent per axis: the largest block plus the stencil
-            // reach (reach cells along +x, reach on each side along y and z)
+            // reach (corner grouping: towards + only)
             hs.compact = true;
             for (int d = 0; d < 3; ++d) {
                 int big = 0;
                 for (int b = 0; b < nb[d]; ++b) big = std::max(big, bs[d][b + 1] - bs[d][b]);
-                const int extent = big + (d == 0 ? reach : 2 * reach);
+                const int extent = big + reach;
                 if (2 * extent >= nc[d]) hs.compact = false;
             }
         }
@@ -492,7 +514,7 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
                             (bz % ncol[2]) != col[2])
                             continue;
                         std::vector<int32_t> A, B;
-                        block_tasks(nc, bs, bx, by, bz, order, A, B);
+                        block_tasks(nc, bs, bx, by, bz, order, A, B, true);
                         groups.emplace_back(std::move(A), std::move(B));
                     }
             std::stable_sort(groups.begin(), groups.end(), [](const auto &x, const auto &y) {

@@ -318,6 +318,22 @@ def test_block_shapes_bit_exact(kind):
         assert (F == Fo).all() and ew == [Eo, Wo, npo], (kind, block)
 
 
+def test_block8_corner_colourings_bit_exact():
+    """BLOCK8 over the shapes corner grouping admits: single cells (each
+    colour class a 2 x 2 x 2 stride of cells, the paper's colouring with
+    each cell's 14 tasks in one work-group) and 1 x 1 x 2 and 2 x 2 x 2
+    blocks, on the 6^3 grid of 4,000 particles and an 8^3 grid."""
+    for n, seed in ((4000, 1001), (9000, 7)):
+        box = synth.fcc(n, 0.8, rc=2.5, seed=seed)
+        S = Setup(box)
+        Fo, Eo, Wo, npo = O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
+        for block in ((1, 1, 1), (1, 1, 2), (2, 2, 2)):
+            _say("block8 corner", n, block, S.g.nc)
+            F, ew, st = S.forces("block8", block=block)
+            assert st & lc.FLAG_OVERFLOW == 0
+            assert (F == Fo).all() and ew == [Eo, Wo, npo], (n, block)
+
+
 def test_fast_reciprocal_is_ieee_on_its_range():
     """The FP32 sweep takes 1/r^2 for 0.3 <= r^2 < 128 from the hardware
     estimate plus one Newton-Raphson step; it must equal IEEE division for
@@ -439,7 +455,8 @@ def test_half_cells_bit_exact():
 
 def test_half_cells_loopex_27_colours():
     """Loop exchange at reach 2 colours cells with stride 3 (27 colours): a
-    12^3 half-cell grid, level by level, bit-exact."""
+    12^3 half-cell grid, level by level, bit-exact; BLOCK8, buffer + reduce
+    and tile atomics with 2 x 2 x 2 blocks on the same grid."""
     box = synth.fcc(3000, 0.8, rc=2.5, seed=42)
     S = Setup(box, half=True)
     assert S.g.nc == (12, 12, 12)
@@ -447,6 +464,12 @@ def test_half_cells_loopex_27_colours():
     F, ew, st = S.forces("loopex")
     assert st & lc.FLAG_OVERFLOW == 0
     assert (F == Fo).all() and ew == [Eo, Wo, npo]
+    # 2-cell blocks colour at reach 2 (footprints grow two cells towards +)
+    for kind in ("block8", "buffer", "atomic_tile"):
+        _say("half 2x2x2", kind)
+        F, ew, st = S.forces(kind, block=(2, 2, 2))
+        assert st & lc.FLAG_OVERFLOW == 0
+        assert (F == Fo).all() and ew == [Eo, Wo, npo], kind
 
 
 def test_flat_2d_bit_exact():

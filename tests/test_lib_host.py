@@ -145,19 +145,22 @@ def test_block8_on_odd_and_small_grids():
 def test_uncoloured_block_sizes_are_upper_bounds(kind):
     """Uncoloured block kinds cut each axis into ceil(n / size) near-equal
     blocks of at most `size` cells (down to single cells); every task is
-    kept and the footprint of a single-cell block is the cell and its 13
-    half-shell neighbours."""
+    kept.  Tasks join the block of their lower corner cell (per axis the
+    smaller coordinate of the two cells), so the footprint of a single-cell
+    block is the 2 x 2 x 2 cube above it: 8 cells, and every cell lies in 8
+    single-cell footprints."""
     g = lc.Grid((7 * 2.6,) * 3, 2.5)  # 7 cells per axis
     assert tuple(g.nc) == (7, 7, 7)
     one = lc.schedule_plan(g, kind, block=(1, 1, 1))
     assert one["ngroup"] == 343 and one["ntask"] == 14 * 343
-    assert one["max_group_cells"] == 14 and one["max_group_tasks"] == 14
+    assert one["max_group_cells"] == 8 and one["max_group_tasks"] == 14
     two = lc.schedule_plan(g, kind, block=(1, 1, 2))
     assert two["ngroup"] == 7 * 7 * 4 and two["ntask"] == 14 * 343
     big = lc.schedule_plan(g, kind, block=(2, 3, 3))
     assert big["ngroup"] == 4 * 3 * 3 and big["ntask"] == 14 * 343
-    if kind == "buffer":  # a cell is in 14 single-cell footprints
-        assert one["max_replicas"] == 14
+    assert big["max_group_cells"] == 3 * 4 * 4  # (2 + 1)(3 + 1)(3 + 1)
+    if kind == "buffer":
+        assert one["max_replicas"] == 8
 
 
 def test_fullshell_plan():
@@ -175,11 +178,24 @@ def test_fullshell_plan():
 
 
 def test_block8_sizes_are_lower_bounds():
-    g = lc.Grid((7 * 2.6,) * 3, 2.5)
+    """BLOCK8 block sizes are lower bounds of at least the stencil's reach:
+    corner grouping grows a footprint by the reach towards +x, +y and +z
+    only, so single cells colour at reach 1 (the 2 x 2 x 2 cube above each
+    cell of a colour class) and blocks of two cells at reach 2."""
+    g = lc.Grid((8 * 2.6,) * 3, 2.5)
     with pytest.raises(lc.LCError):
-        lc.schedule_plan(g, "block8", block=(1, 1, 2))
-    info = lc.schedule_plan(g, "block8", block=(1, 2, 2))
-    assert info["nphase"] == 8 and info["ntask"] == 14 * 343
+        lc.schedule_plan(g, "block8", block=(0, 1, 1))
+    for blk in ((1, 1, 1), (1, 1, 2), (1, 2, 2)):
+        info = lc.schedule_plan(g, "block8", block=blk)
+        assert info["nphase"] == 8 and info["ntask"] == 14 * 512, blk
+    one = lc.schedule_plan(g, "block8", block=(1, 1, 1))
+    assert one["ngroup"] == 512 and one["max_group_cells"] == 8
+    h = lc.Grid((8 * 2.6,) * 3, 2.5, half=True)  # 16 cells per axis, reach 2
+    with pytest.raises(lc.LCError):
+        lc.schedule_plan(h, "block8", block=(1, 2, 2))
+    info = lc.schedule_plan(h, "block8", block=(2, 2, 2))
+    assert info["nphase"] == 8 and info["ntask"] == 63 * 16 ** 3
+    assert info["max_group_cells"] == 4 ** 3 and info["max_group_tasks"] == 63 * 8
 
 
 def test_validator_rejects_shared_write():
@@ -301,11 +317,11 @@ def test_flat_grid_plans_follow_the_2d_closed_forms():
     for kind in ("buffer", "atomic_tile", "atomic_pair"):
         assert lc.schedule_plan(g, kind)["ntask"] == 5 * g.ncell, kind
     assert lc.schedule_plan(g, "fullshell")["ntask"] == 9 * g.ncell
-    # blocks of at most 8 x 12: 26 = 7+7+6+6 along x, 9+9+8 along y; the
-    # largest, 7 x 9, reaches (7 + 1) x (9 + 2) cells but one corner (no
-    # (0, +1) offset in the half stencil)
+    # blocks of at most 8 x 12: 26 = 7+7+6+6 along x, 9+9+8 along y; tasks
+    # join the block of their lower corner cell, so the largest, 7 x 9,
+    # reaches (7 + 1) x (9 + 1) cells
     info = lc.schedule_plan(g, "buffer", block=(8, 12, 1))
-    assert info["max_group_cells"] == 8 * 11 - 1 and info["max_group_tasks"] == 5 * 7 * 9
+    assert info["max_group_cells"] == 8 * 10 and info["max_group_tasks"] == 5 * 7 * 9
     with pytest.raises(lc.LCError):
         lc.Grid((65.465, 65.465, 10.0), 2.5, half=True, flat=True)
 
