@@ -1437,20 +1437,31 @@ __global__ __launch_bounds__(256) void k_reduce_parts(long long *__restrict__ pa
 }
 
 // Buffer + reduce: F of every particle = sum of its cell's replica slots.
-// With part != NULL one extra work-group (the last) sums the energy slots
-// instead, which saves a launch.
+// With part != NULL one extra work-group (the first, dispatched before the
+// others, so its serial sums do not trail the launch) sums the energy slots
+// instead, which saves a launch.  The replicas are read two at a time, so
+// that each thread has six loads in flight.
 __global__ __launch_bounds__(256) void k_gather_partials(
     const long long *__restrict__ pbuf, const int *__restrict__ rcnt, int64_t n,
     long long *__restrict__ F, long long *__restrict__ part, long long *__restrict__ ew) {
-    if (part && blockIdx.x == gridDim.x - 1) {
+    if (part && blockIdx.x == 0) {
         reduce_parts_wg(part, 3, ew);
         return;
     }
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = (int64_t)(blockIdx.x - (part ? 1 : 0)) * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int R = rcnt[p];  // replicas of p's cell, recorded by the sweep
     long long fx = 0, fy = 0, fz = 0;
-    for (int r = 0; r < R; ++r) {
+    int r = 0;
+    for (; r + 2 <= R; r += 2) {
+        const long long *P = pbuf + (int64_t)r * 3 * n, *Q = P + 3 * n;
+        const long long a0 = P[p], a1 = P[n + p], a2 = P[2 * n + p];
+        const long long b0 = Q[p], b1 = Q[n + p], b2 = Q[2 * n + p];
+        fx += a0 + b0;
+        fy += a1 + b1;
+        fz += a2 + b2;
+    }
+    if (r < R) {
         const long long *P = pbuf + (int64_t)r * 3 * n;
         fx += P[p];
         fy += P[n + p];
