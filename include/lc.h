@@ -300,6 +300,18 @@ int lc_schedule_plan(const lc_grid *g, int kind, const int8_t *offsets, int n,
 int lc_schedule_plan_ex(const lc_grid *g, int kind, const int8_t *offsets, int n,
                         const int32_t *block_min, lc_schedule_info *out);
 
+/* [host only] The tasks of the schedule lc_schedule_plan_ex builds, in
+ * launch order: task t couples cells A[t] and B[t] (A == B for an intra
+ * task), runs in work-group grp[t] (groups numbered in launch order over
+ * all phases) and phase phase[t].  A, B, grp, phase: host int32 arrays of
+ * cap >= T entries, each may be NULL to skip it; *ntask = T (set also when
+ * cap < T, which returns LC_ECAPACITY).  Lets a caller check a schedule
+ * without a device: that every stencil pair is kept once, what each work-
+ * group's footprint is, and that a phase's groups touch disjoint cells. */
+int lc_schedule_plan_tasks(const lc_grid *g, int kind, const int8_t *offsets, int n,
+                           const int32_t *block_min, int32_t *A, int32_t *B, int32_t *grp,
+                           int32_t *phase, int64_t cap, int64_t *ntask);
+
 /* [host only] The schedule validator on an explicit phase list: phase p runs
  * work-groups phase_grp[p] .. phase_grp[p+1]-1, group k writes the cells
  * foot_cells[grp_foot[k] .. grp_foot[k+1]-1].  Returns LC_OK when every

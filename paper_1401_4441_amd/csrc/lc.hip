@@ -2505,6 +2505,37 @@ extern "C" int lc_schedule_plan(const lc_grid *g, int kind, const int8_t *offset
     return lc_schedule_plan_ex(g, kind, offsets, n, nullptr, out);
 }
 
+extern "C" int lc_schedule_plan_tasks(const lc_grid *g, int kind, const int8_t *offsets, int n,
+                                      const int32_t *block_min, int32_t *A, int32_t *B,
+                                      int32_t *grp, int32_t *phase, int64_t cap,
+                                      int64_t *ntask) {
+    if (!g || !ntask) return fail(LC_EINVAL, "lc_schedule_plan_tasks: null argument");
+    if (kind < 0 || kind >= LC_SCHED_COUNT) return fail(LC_EINVAL, "unknown schedule kind %d", kind);
+    lcs::HostSchedule h;
+    std::string err;
+    int rc = lcs::build_schedule(g->nc, kind, offsets, n, h, err, block_min, grid_reach(g));
+    if (rc) return fail(rc, "lc_schedule_plan_tasks: %s", err.c_str());
+    if (!lcs::validate(h, g->ncell, err))
+        return fail(LC_ESCHED, "lc_schedule_plan_tasks: %s", err.c_str());
+    *ntask = (int64_t)h.task_ab.size();
+    if (cap < *ntask)
+        return fail(LC_ECAPACITY, "lc_schedule_plan_tasks: need %lld entries", (long long)*ntask);
+    const int ngrp = (int)h.grp_task.size() - 1;
+    int p = 0;
+    for (int k = 0; k < ngrp; ++k) {
+        while (p + 1 < (int)h.phase_grp.size() && h.phase_grp[p + 1] <= k) ++p;
+        const int32_t *fc = h.foot_cells.data() + h.grp_foot[k];
+        for (int t = h.grp_task[k]; t < h.grp_task[k + 1]; ++t) {
+            const uint32_t ab = h.task_ab[(size_t)t];
+            if (A) A[t] = fc[ab & 0xffffu];
+            if (B) B[t] = fc[ab >> 16];
+            if (grp) grp[t] = k;
+            if (phase) phase[t] = p;
+        }
+    }
+    return LC_OK;
+}
+
 extern "C" int lc_schedule_plan_ex(const lc_grid *g, int kind, const int8_t *offsets, int n,
                                    const int32_t *block_min, lc_schedule_info *out) {
     if (!g || !out) return fail(LC_EINVAL, "lc_schedule_plan: null argument");

@@ -87,6 +87,7 @@ SYMBOLS = {
     "lc_schedule_free": ([P], None),
     "lc_schedule_plan": ([P, INT, P, INT, P], INT),
     "lc_schedule_plan_ex": ([P, INT, P, INT, P, P], INT),
+    "lc_schedule_plan_tasks": ([P, INT, P, INT, P, P, P, P, P, I64, P], INT),
     "lc_validate_phases": ([I64, ctypes.c_int32, P, P, P], INT),
     "lc_serialization_degree": ([P, INT, P, INT, P, I64, P], INT),
     "lc_serialization_degree_weighted": ([P, INT, P, INT, P, P], INT),
@@ -366,6 +367,33 @@ def schedule_plan(grid: Grid, kind, offsets=None, block=None) -> dict:
     i = _SchedInfo()
     _chk(lib().lc_schedule_plan_ex(grid.ptr, int(kind), op, int(n), bp, ctypes.byref(i)))
     return {k: getattr(i, k) for k, _ in _SchedInfo._fields_ if k != "pad"}
+
+
+def schedule_plan_tasks(grid: Grid, kind, offsets=None, block=None):
+    """Host-only: the tasks of the schedule schedule_plan describes, in
+    launch order, as int32 numpy arrays (A, B, group, phase)."""
+    import numpy as np
+    if isinstance(kind, str):
+        kind = KINDS[kind]
+    if offsets is not None:
+        arr = np.ascontiguousarray(np.asarray(offsets, dtype=np.int8).reshape(-1, 3))
+        op, n = ctypes.c_void_p(arr.ctypes.data), arr.shape[0]
+    else:
+        op, n = None, 0
+    bp = None
+    if block is not None:
+        barr = np.ascontiguousarray(np.asarray(block, dtype=np.int32).reshape(3))
+        bp = ctypes.c_void_p(barr.ctypes.data)
+    nt = ctypes.c_int64(0)
+    rc = lib().lc_schedule_plan_tasks(grid.ptr, int(kind), op, int(n), bp, None, None, None,
+                                      None, 0, ctypes.byref(nt))
+    if rc not in (0, -7):  # LC_ECAPACITY: the count is set
+        _chk(rc)
+    out = [np.zeros(nt.value, dtype=np.int32) for _ in range(4)]
+    _chk(lib().lc_schedule_plan_tasks(grid.ptr, int(kind), op, int(n), bp,
+                                      *[ctypes.c_void_p(a.ctypes.data) for a in out],
+                                      nt.value, ctypes.byref(nt)))
+    return tuple(out)
 
 
 def validate_phases(ncell: int, phase_grp, grp_foot, foot_cells) -> None:

@@ -408,3 +408,82 @@ def test_race_canary():
     assert e.value.code == -4
     lost = seq - _concurrent_rmw(ncell, bad)
     assert (lost >= 0).all() and lost.sum() > 0
+
+
+def _stencil_tasks(nc, offsets):
+    """Every (A, A + o) of the half stencil plus the intra task, by definition."""
+    nx, ny, nz = nc
+    out = []
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                a = x + nx * (y + ny * z)
+                for o in [(0, 0, 0)] + list(offsets):
+                    b = ((x + o[0]) % nx) + nx * (((y + o[1]) % ny) + ny * ((z + o[2]) % nz))
+                    out.append((a, b))
+    return sorted(out)
+
+
+def _half_shell(reach):
+    r = range(-reach, reach + 1)
+    return [(dx, dy, dz) for dz in r for dy in r for dx in r
+            if dx > 0 or (dx == 0 and dz > 0) or (dx == 0 and dz == 0 and dy < 0)]
+
+
+def _coords(c, nc):
+    return np.stack([c % nc[0], (c // nc[0]) % nc[1], c // (nc[0] * nc[1])], axis=-1)
+
+
+@pytest.mark.parametrize("ncell_axis,reach,kind,block", [
+    (7, 1, "buffer", (2, 2, 3)), (7, 1, "atomic_tile", (1, 1, 1)), (8, 1, "block8", (1, 1, 1)),
+    (8, 1, "block8", (1, 2, 2)), (9, 1, "buffer", (3, 3, 3)), (12, 2, "buffer", (2, 2, 2)),
+    (12, 2, "block8", (2, 2, 2)), (13, 2, "atomic_tile", (1, 2, 3))])
+def test_tile_tasks_by_corner_cell(ncell_axis, reach, kind, block):
+    """The tile kinds keep the stencil's tasks exactly (each (A, A + o) once,
+    compared with the stencil written out here), and a task runs in the
+    work-group of its lower corner cell C (per axis A + min(o, 0)): every
+    cell is the corner of all its tasks in one group, a group's corners form
+    a box of at most the block's size, its footprint lies in the box grown
+    by the reach towards +, and the groups of one phase touch disjoint
+    cells."""
+    side = 2.6 if reach == 1 else 1.3
+    g = lc.Grid((ncell_axis * side,) * 3, 2.5, half=reach == 2)
+    nc = g.nc
+    assert nc == (ncell_axis,) * 3 and g.reach == reach
+    A, B, G, P = lc.schedule_plan_tasks(g, kind, block=block)
+    offs = O.H3 if reach == 1 else _half_shell(2)
+    assert len(offs) == (13 if reach == 1 else 62)
+    assert sorted(zip(A.tolist(), B.tolist())) == _stencil_tasks(nc, offs)
+    n = np.array(nc)
+    a, b = _coords(A, nc), _coords(B, nc)
+    d = (b - a + reach) % n - reach  # the offset, in [-reach, reach]
+    corner = (a + np.minimum(d, 0)) % n
+    cid = corner[:, 0] + nc[0] * (corner[:, 1] + nc[1] * corner[:, 2])
+    owner = {}
+    for c, gg in zip(cid.tolist(), G.tolist()):
+        assert owner.setdefault(c, gg) == gg  # one group per corner cell
+    assert len(owner) == g.ncell
+    for gg in np.unique(G):
+        sel = G == gg
+        cs = np.unique(cid[sel])
+        cc = _coords(cs, nc)
+        ext = []
+        for ax in range(3):
+            vals = sorted(set(cc[:, ax].tolist()))
+            # a cyclic interval: the gaps between consecutive values are 1
+            # except one wrap-around gap
+            gaps = [(vals[(k + 1) % len(vals)] - vals[k]) % nc[ax] for k in range(len(vals))]
+            assert len(vals) == nc[ax] or sum(x != 1 for x in gaps) <= 1
+            ext.append(len(vals))
+        assert len(cs) == ext[0] * ext[1] * ext[2]  # a box
+        lim = block if kind != "block8" else tuple(2 * x + 1 for x in block)
+        assert all(e <= m for e, m in zip(ext, lim)), (ext, block)
+        foot = np.unique(np.concatenate([A[sel], B[sel]]))
+        assert len(foot) <= np.prod([e + reach for e in ext])
+    if kind == "block8":
+        for p in np.unique(P):
+            seen = {}
+            for gg in np.unique(G[P == p]):
+                sel = G == gg
+                for c in np.unique(np.concatenate([A[sel], B[sel]])).tolist():
+                    assert seen.setdefault(c, gg) == gg, (p, c)
