@@ -554,8 +554,9 @@ typedef struct lc_batch_opts {
     int32_t tile;       /* LDS tile (particles) a split box's block shape is
                            sized for: the largest blocks of {2,3,3}, {1,3,3},
                            {1,2,2}, {1,1,2}, {1,1,1} whose footprint is
-                           expected (box density + 35%) to fit; 768 (0 =
-                           default, three work-groups per CU), 1024 or 2048 */
+                           expected (box density + 35%) to fit; 512 (four
+                           work-groups per CU), 768 (0 = default, three),
+                           1024 or 2048                                     */
     int32_t write_mode; /* LC_BATCH_WRITE_*                                 */
 } lc_batch_opts;
 /* lc_batch_create with options (NULL = defaults); LC_EINVAL on other tile

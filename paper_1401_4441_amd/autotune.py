@@ -220,7 +220,7 @@ def tune_shape(grid, pos: torch.Tensor, kinds=BOX_KINDS_CONFLICT_FREE, reps: int
     return out
 
 
-BATCH_TILES = (768, 1024, 2048)
+BATCH_TILES = (512, 768, 1024, 2048)
 
 
 def tune_batch(grids, ns, pos_all: torch.Tensor, reps: int = 5, grid_sets=None,

@@ -1347,13 +1347,17 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
 //        atomics; 3 = accumulate in LDS, plain stores into the group's
 //        replica slots (buffer + reduce); 4 = full shell: only the i side
 //        accumulates, plain stores of the group's home particles.
-// Occupancy: a 768-particle tile leaves LDS for three work-groups per
-// compute unit, which also needs at most 80 VGPRs (six waves per SIMD); the
-// register allocator then spills a few values outside the pair loops, which
-// costs far less than the latency the third work-group hides.  Larger tiles
-// are held to two work-groups by LDS anyway.
+// Occupancy: a 512-particle tile (40 KB of LDS) leaves room for four
+// work-groups per compute unit, which then need at most 64 VGPRs (eight
+// waves per SIMD); a 768-particle tile for three at 80 VGPRs (six waves).
+// The register allocator spills a few dozen values, mostly outside the pair
+// loops, which costs less than the group setup latency the extra
+// work-group hides (measured at 256k: 2x2x3 blocks 62.5 -> 60.3 us per
+// evaluation, 1x2x3 73.8 -> 68.5 us).  Larger tiles are held to two
+// work-groups by LDS anyway.
 template <int CAP, int WMODE, bool F64, bool FF>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CAP <= 768 ? 6 : 1)))
+__global__ __launch_bounds__(kWG)
+__attribute__((amdgpu_waves_per_eu(CAP <= 512 ? 8 : CAP <= 768 ? 6 : 1)))
 void k_sweep(SweepArgs a) {
     __shared__ SweepLDS<CAP, WMODE, FF> sh;
     __shared__ int s_tk[1];
@@ -1838,11 +1842,12 @@ static int launch_sweep_t(SweepArgs a, int ngroups, int ncu, int *ticket, hipStr
     return LC_OK;
 }
 
-// LDS tile capacities (particles): with the float filter tile {768, 1024,
+// LDS tile capacities (particles): with the integer filter {512, 768, 1024,
 // 2048}, without {1024, 2048, 3072}.
 template <int WMODE, bool F64, bool FF>
 static int launch_sweep_c(int cap, const SweepArgs &a, int ng, int ncu, int *tk, hipStream_t st) {
     if constexpr (FF) {
+        if (cap <= 512) return launch_sweep_t<512, WMODE, F64, true>(a, ng, ncu, tk, st);
         if (cap <= 768) return launch_sweep_t<768, WMODE, F64, true>(a, ng, ncu, tk, st);
         if (cap <= 1024) return launch_sweep_t<1024, WMODE, F64, true>(a, ng, ncu, tk, st);
         return launch_sweep_t<2048, WMODE, F64, true>(a, ng, ncu, tk, st);
@@ -1999,7 +2004,7 @@ static int forces_run(const lc_grid *g, const lc_schedule *s, const int32_t *cel
                                  : mean * s->h.max_cells * 1.35;
     int cap;
     if (ff)
-        cap = need <= 768 ? 768 : (need <= 1024 ? 1024 : 2048);
+        cap = need <= 512 ? 512 : need <= 768 ? 768 : (need <= 1024 ? 1024 : 2048);
     else
         cap = need <= 1024 ? 1024 : (need <= 2048 ? 2048 : 3072);
     for (int p = 0; p < nphase; ++p) {
@@ -3121,8 +3126,8 @@ extern "C" int lc_batch_create_ex(const lc_box_desc *boxes, int nbox, const int3
     if (!boxes || nbox < 1 || !out) return fail(LC_EINVAL, "lc_batch_create: bad arguments");
     const int tile = opts && opts->tile ? opts->tile : 768;
     const int wm = opts ? opts->write_mode : LC_BATCH_WRITE_BUFFER;
-    if (tile != 768 && tile != 1024 && tile != 2048)
-        return fail(LC_EINVAL, "lc_batch_create_ex: tile %d (768, 1024 or 2048)", tile);
+    if (tile != 512 && tile != 768 && tile != 1024 && tile != 2048)
+        return fail(LC_EINVAL, "lc_batch_create_ex: tile %d (512, 768, 1024 or 2048)", tile);
     if (wm != LC_BATCH_WRITE_BUFFER && wm != LC_BATCH_WRITE_ATOMIC)
         return fail(LC_EINVAL, "lc_batch_create_ex: write mode %d", wm);
     lc_batch *b = new lc_batch();
@@ -3272,6 +3277,7 @@ extern "C" int lc_batch_create_ex(const lc_box_desc *boxes, int nbox, const int3
     for (int32_t r : cell_rep) h.rmax = std::max(h.rmax, r);
     const double need = est_max;
     b->cap = need <= 768 ? 768 : need <= 1024 ? 1024 : (need <= 2048 ? 2048 : 3072);
+    if (filt && need <= 512) b->cap = 512;  // the filtered kernel has a 512 tile
     b->ff = filt && b->cap <= 2048;
 
     int rc = 0;

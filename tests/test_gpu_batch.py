@@ -198,7 +198,8 @@ def test_batch_atomic_write_and_tiles_same_bits():
     boxes, grids, pos = _batch_inputs(10, 500, 6000, seed=21)
     want = _oracle(boxes, grids)
     posd = torch.from_numpy(pos).to(DEV)
-    for tile, write in ((768, "atomic"), (1024, "buffer"), (2048, "buffer"), (2048, "atomic")):
+    for tile, write in ((512, "buffer"), (768, "atomic"), (1024, "buffer"), (2048, "buffer"),
+                        (2048, "atomic")):
         print("batch tile", tile, write, flush=True)
         batch = lc.Batch(grids, [b.n for b in boxes], tile=tile, write=write)
         info = batch.info()

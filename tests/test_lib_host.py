@@ -71,7 +71,7 @@ def test_cp_loopex_matches_oracle():
 
 def test_batch_options_rejected_on_host():
     g = lc.Grid((17.1, 17.1, 17.1), 2.5)
-    for kw in ({"tile": 999}, {"tile": 512}):
+    for kw in ({"tile": 999}, {"tile": 256}):
         with pytest.raises(lc.LCError) as e:
             lc.Batch([g], [100], **kw)
         assert e.value.code == -1
