@@ -280,7 +280,10 @@ void lc_schedule_free(lc_schedule *s);
  * so heavy groups start first and a launch ends on light ones.  cell_counts
  * [host] int32 per cell (e.g. the differences of cell_start); LC_EINVAL if
  * NULL or negative.  The schedule stays valid for any later particle
- * distribution; only its launch order was chosen for this one. */
+ * distribution; only its launch order, and the LDS tile (sized to hold its
+ * largest footprint under these counts; a work-group whose footprint
+ * outgrows it later takes the exact global-memory path and sets
+ * LC_FLAG_FALLBACK), were chosen for this one. */
 int lc_make_schedule_weighted(const lc_grid *g, int kind, const int8_t *offsets,
                               int n, const int32_t *block_min,
                               const int32_t *cell_counts, lc_schedule **out);

@@ -115,6 +115,9 @@ struct lc_schedule {
     // creation-order kinds: tasks in creation order and, per task, how many
     // earlier tasks touch its cells A and B (dataflow executors)
     int32_t *df_a = nullptr, *df_b = nullptr, *df_seqa = nullptr, *df_seqb = nullptr;
+    // load-aware schedules: the largest footprint in particles under the
+    // counts they were built from (0: unknown); sizes the LDS tile
+    int64_t foot_max = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -2000,8 +2003,11 @@ static int forces_run(const lc_grid *g, const lc_schedule *s, const int32_t *cel
     const int32_t hint = sc.max_per_cell;
     const bool dense = hint > 0 ? hint > kFFCell : mean > 0.5 * kFFCell;
     const bool ff = a.pp.thr16 > 0 && precision == LC_PREC_FP32 && s->h.write_mode != 2 && !dense;
-    const double need = hint > 0 ? (double)hint * s->h.max_cells * 0.8
-                                 : mean * s->h.max_cells * 1.35;
+    // (a load-aware schedule knows its largest footprint exactly for the
+    // counts it was built from: a tile that holds it, no larger)
+    const double need = s->foot_max > 0 ? (double)s->foot_max
+                        : hint > 0      ? (double)hint * s->h.max_cells * 0.8
+                                        : mean * s->h.max_cells * 1.35;
     int cap;
     if (ff)
         cap = need <= 512 ? 512 : need <= 768 ? 768 : (need <= 1024 ? 1024 : 2048);
@@ -2340,6 +2346,13 @@ static int make_schedule_impl(const lc_grid *g, int kind, const int8_t *offsets,
                             (long long)c);
             }
         lcs::order_groups_by_work(s->h, cell_counts);
+        const int ngrp = (int)s->h.grp_foot.size() - 1;
+        for (int k = 0; k < ngrp; ++k) {
+            int64_t np = 0;
+            for (int f = s->h.grp_foot[k]; f < s->h.grp_foot[k + 1]; ++f)
+                np += cell_counts[s->h.foot_cells[(size_t)f]];
+            s->foot_max = std::max(s->foot_max, np);
+        }
     }
     if (!lcs::validate(s->h, g->ncell, err)) {
         delete s;
