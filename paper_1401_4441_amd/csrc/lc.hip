@@ -2004,10 +2004,13 @@ static int forces_run(const lc_grid *g, const lc_schedule *s, const int32_t *cel
     const bool dense = hint > 0 ? hint > kFFCell : mean > 0.5 * kFFCell;
     const bool ff = a.pp.thr16 > 0 && precision == LC_PREC_FP32 && s->h.write_mode != 2 && !dense;
     // (a load-aware schedule knows its largest footprint exactly for the
-    // counts it was built from: a tile that holds it, no larger)
-    const double need = s->foot_max > 0 ? (double)s->foot_max
-                        : hint > 0      ? (double)hint * s->h.max_cells * 0.8
-                                        : mean * s->h.max_cells * 1.35;
+    // counts it was built from: a tile that holds it, no larger; otherwise
+    // 80% of the footprint's cells all at the largest cell, but at least
+    // the mean footprint with 15% to spare)
+    const double need =
+        s->foot_max > 0 ? (double)s->foot_max
+        : hint > 0 ? std::max((double)hint * s->h.max_cells * 0.8, mean * s->h.max_cells * 1.15)
+                   : mean * s->h.max_cells * 1.35;
     int cap;
     if (ff)
         cap = need <= 512 ? 512 : need <= 768 ? 768 : (need <= 1024 ? 1024 : 2048);
