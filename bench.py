@@ -351,12 +351,17 @@ def main():
                                           "(paper_strategies)"}
                 continue
             try:
-                s, kms, _ = time_sched(kind, st, wu, kb)
+                # the tile kinds launch their groups in the headline's order
+                # (fixed or heaviest first), so that only the write-back and
+                # the phase count differ
+                tiled = kind in ("block8", "buffer", "atomic_tile", "fullshell", "atomic_pair")
+                s, kms, _ = time_sched(kind, st, wu, kb, weighted=bool(load_aware) and tiled)
             except lc.LCError as e:  # loop exchange needs even cell counts
                 extra[kind] = {"skipped": str(e)}
                 continue
             extra[kind] = {"ms_per_step": kms, "pairs_per_s": pairs / (kms * 1e-3),
                            "phases": s.info()["nphase"], "block": list(kb) if kb else None,
+                           "load_aware": bool(load_aware) and tiled,
                            "time_vs_headline": kms / ms,
                            # every schedule must give the headline's bits
                            # (forces, energy, virial, pair count)
@@ -635,7 +640,10 @@ def bench_md(args, emit=True):
                            cell_counts=lc.cell_counts_of(cs))
     order_ms = {}
     sched_at = lc.Schedule(g, "atomic_tile", block=tune_at["block"])
-    for name, sc in (("fixed", sched), ("load_aware", sched_la), ("atomic_tile", sched_at)):
+    sched_at_la = lc.Schedule(g, "atomic_tile", block=tune_at["block"],
+                              cell_counts=lc.cell_counts_of(cs))
+    for name, sc in (("fixed", sched), ("load_aware", sched_la), ("atomic_tile", sched_at),
+                     ("atomic_tile_load_aware", sched_at_la)):
         p_, v_, i_ = pos.clone(), vel.clone(), ids.clone()
         lc.verlet_step(g, sc, p_, v_, i_, ws, 0.005, 2, 10)
         torch.cuda.synchronize()
@@ -650,7 +658,9 @@ def bench_md(args, emit=True):
     load_aware = order_ms["load_aware"] < order_ms["fixed"]
     if load_aware:
         sched = sched_la
-    at_ms = order_ms.pop("atomic_tile")
+    # the tile-atomics baseline in the same launch order as the headline
+    at_fixed, at_la = order_ms.pop("atomic_tile"), order_ms.pop("atomic_tile_load_aware")
+    at_ms = at_la if load_aware else at_fixed
     nsteps = 100 if args.steps >= 10 else args.steps
     ws.clear_status()
     torch.cuda.synchronize()
@@ -686,7 +696,8 @@ def bench_md(args, emit=True):
           dtype="f32 pairs, int64 forces, f64 positions/velocities/energies",
           emit=emit,
           atomic_tile={"ms_per_step": at_ms, "block": tune_at["block"], "steps": 20,
-                       "time_vs_headline": at_ms / ms},
+                       "load_aware": load_aware, "fixed_order_ms_per_step": at_fixed,
+                       "load_aware_ms_per_step": at_la, "time_vs_headline": at_ms / ms},
           cell_build=build,
           energy={"E0_per_particle": etot[0] / box.n,
                   "drift_per_particle": (etot[-1] - etot[0]) / box.n,
@@ -733,7 +744,7 @@ def bench_slab(args, emit=True):
     # load-aware launch order (groups heaviest first by n_A n_B) for the
     # conflict-free kinds: the dense slab's groups start first
     cc = lc.cell_counts_of(cs)
-    for kind in ("buffer", "block8"):
+    for kind in ("buffer", "block8", "atomic_tile"):
         if "ms" not in res[kind]:
             continue
         blk = tuple(res[kind]["block"]) if res[kind]["block"] else None
@@ -745,6 +756,8 @@ def bench_slab(args, emit=True):
         s.close()
     best = min((k for k in ("buffer", "block8", "buffer_load_aware", "block8_load_aware")
                 if k in res and "ms" in res[k]), key=lambda k: res[k]["ms"])
+    # the tile-atomics baseline in the headline's launch order
+    at_key = "atomic_tile_load_aware" if best.endswith("_load_aware") else "atomic_tile"
     # cell side rc against rc/2 (the reach-2 stencil: fewer candidate pairs,
     # smaller and more numerous tasks), fastest trial of each kind per grid
     variants = {}
@@ -773,11 +786,13 @@ def bench_slab(args, emit=True):
           {"workload": "LJ slab N=2000000, rho 0.75 middle third / 0.02 gas, rc=3.0",
            "cells": list(g.nc), "schedule": best, "block": res[best]["block"],
            "pairs_in_cutoff": pairs, "grid_choice": pick["grid"], "cell_size_variants": variants,
+           "autotune_trials": [[t["kind"], t["nc"][0], t["block"], round(t["ms"], 4),
+                                t["fallback"]] for t in tune["trials"]],
            "cell_occupancy": {"max": int(counts.max()), "mean": float(counts.mean()),
                               "empty_frac": float((counts == 0).mean())}},
           emit=emit,
-          speedup_over_atomic_tile=res["atomic_tile"]["ms"] / res[best]["ms"]
-          if "ms" in res.get("atomic_tile", {}) else None,
+          speedup_over_atomic_tile=res[at_key]["ms"] / res[best]["ms"]
+          if "ms" in res.get(at_key, {}) else None,
           status_flags=int(np.bitwise_or.reduce([v.get("status_flags", 0) for v in res.values()])),
           schedules={k: (dict(v, pairs_per_s=pairs / (v["ms"] * 1e-3)) if "ms" in v else v)
                      for k, v in res.items()})
@@ -815,7 +830,7 @@ def bench_2d(args):
     pairs = int(ew[2].item())
     # the conflict-free kinds with their groups launched heaviest first
     cc = lc.cell_counts_of(cs)
-    for kind in ("buffer", "block8"):
+    for kind in ("buffer", "block8", "atomic_tile"):
         blk = tuple(res[kind]["block"]) if res[kind]["block"] else None
         s = lc.Schedule(g, kind, block=blk, cell_counts=cc)
         ws.clear_status()
@@ -848,6 +863,9 @@ def bench_2d(args):
           schedules={k: dict(v, pairs_per_s=pairs / (v["ms"] * 1e-3)) for k, v in res.items()},
           conflict_free_vs_atomics={
               "speedup_over_atomic_pair": res["atomic_pair"]["ms"] / res[best]["ms"],
+              # tile atomics in the headline's launch order
+              "speedup_over_atomic_tile": res["atomic_tile_load_aware" if best.endswith(
+                  "_load_aware") else "atomic_tile"]["ms"] / res[best]["ms"],
               "speedup_over_full_shell": res["fullshell"]["ms"] / res[best]["ms"]},
           paper_orders_2d={"n": small.n, "cells": list(gs.nc), "orders": orders})
 

@@ -135,7 +135,7 @@ def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
     if kinds is None:
         kinds = BOX_KINDS_CONFLICT_FREE + (("atomic_tile",) if allow_atomics else ())
     kinds = tuple(kinds)
-    key = box_key(n, L, rc) + "|" + ",".join(kinds) + "|v4"
+    key = box_key(n, L, rc) + "|" + ",".join(kinds) + "|v5"
     cache = _load_cache() if use_cache else {}
     if key in cache:
         return cache[key]
@@ -149,6 +149,9 @@ def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
             continue
         ws = lc.Workspace(n, grid.ncell)
         cs, perm, coord = lc.build_cells(grid, pos, ws)
+        # trials launch their groups heaviest first, as the final schedule
+        # does, which also sizes each trial's LDS tile to its footprints
+        cc = lc.cell_counts_of(cs)
         if not warmed:  # bring the clocks up before the first trial counts
             s0 = _first_schedule(grid, kinds)
             t_end = time.perf_counter() + 0.3
@@ -159,7 +162,7 @@ def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
         for kind in kinds:
             for block in shapes_for(kind, grid.reach == 2, grid.nc[2] == 1):
                 try:
-                    sched = lc.Schedule(grid, kind, block=block)
+                    sched = lc.Schedule(grid, kind, block=block, cell_counts=cc)
                 except lc.LCError:
                     continue
                 ws.clear_status()
@@ -191,6 +194,7 @@ def tune_shape(grid, pos: torch.Tensor, kinds=BOX_KINDS_CONFLICT_FREE, reps: int
     n = pos.shape[1]
     ws = lc.Workspace(n, grid.ncell)
     cs, perm, coord = lc.build_cells(grid, pos, ws)
+    cc = lc.cell_counts_of(cs)  # load-aware trials (see tune_box)
     s0 = _first_schedule(grid, kinds)
     t_end = time.perf_counter() + 0.3
     while time.perf_counter() < t_end:  # clocks up before the trials count
@@ -200,7 +204,7 @@ def tune_shape(grid, pos: torch.Tensor, kinds=BOX_KINDS_CONFLICT_FREE, reps: int
     for kind in kinds:
         for block in shapes_for(kind, grid.reach == 2, grid.nc[2] == 1):
             try:
-                sched = lc.Schedule(grid, kind, block=block)
+                sched = lc.Schedule(grid, kind, block=block, cell_counts=cc)
             except lc.LCError:
                 continue
             ws.clear_status()
