@@ -244,18 +244,19 @@ typedef struct lc_schedule_info {
 int lc_make_schedule(const lc_grid *g, int kind, const int8_t *offsets, int n,
                      lc_schedule **out);
 /* As lc_make_schedule, with the block shape of the block kinds: block_min
- * [host] 3 x int32.  LC_SCHED_BLOCK8: the smallest block per axis, at least
- * the stencil's reach (1; 2 on grids of cells of side rc/2) -- a footprint
- * reaches that far past its block towards +x, +y and +z, so same-coloured
- * blocks stay a whole block apart -- with an even block count per axis.
- * LC_SCHED_ATOMIC_TILE / BUFFER / FULLSHELL (uncoloured): the largest block
- * per axis, at least {1, 1, 1}; each axis is cut into ceil(n / size)
- * near-equal blocks.  NULL = the BLOCK8 partition with {1, 2, 2} for all
- * three (blocks of at most {1, 2, 2} for the uncoloured kinds on rc/2
- * grids).  Larger blocks mean fewer, bigger work-groups and less halo
- * write-back per particle; smaller ones fit denser boxes into the LDS tile.
- * A work-group holds at most 512 tasks and 128 footprint cells
- * (LC_ECAPACITY otherwise).  The autotuner picks the shape. */
+ * [host] 3 x int32, the largest block per axis (>= 1, <= 64).  The
+ * uncoloured kinds (LC_SCHED_ATOMIC_TILE / BUFFER / FULLSHELL) cut each axis
+ * into ceil(n / size) near-equal blocks.  LC_SCHED_BLOCK8 rounds that count
+ * up to even (the 2-colouring), then down by twos while a block would be
+ * narrower than the stencil's reach (1; 2 on grids of cells of side rc/2):
+ * a footprint reaches that far past its block towards +x, +y and +z, so
+ * same-coloured blocks stay a whole block apart.  NULL = the BLOCK8
+ * partition with at most {1, 3, 3} for all three ({2, 2, 2} for BLOCK8 and
+ * {1, 2, 2} for the uncoloured kinds on rc/2 grids).  Larger blocks mean
+ * fewer, bigger work-groups and less halo write-back per particle; smaller
+ * ones fit denser boxes into the LDS tile.  A work-group holds at most 512
+ * tasks and 128 footprint cells (LC_ECAPACITY otherwise).  The autotuner
+ * picks the shape. */
 int lc_make_schedule_ex(const lc_grid *g, int kind, const int8_t *offsets,
                         int n, const int32_t *block_min, lc_schedule **out);
 int lc_schedule_info_get(const lc_schedule *s, lc_schedule_info *out);

@@ -27,8 +27,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1401_4441
                              "tune.json")
 
 BOX_KINDS_CONFLICT_FREE = ("block8", "buffer")
-# BLOCK8: lower bounds per axis (even block counts); uncoloured kinds: upper
-# bounds.  Tasks join the block of their lower corner cell, so a block's
+# Block sizes are upper bounds (BLOCK8: even block counts).  Tasks join the block of their lower corner cell, so a block's
 # footprint is (bx + r)(by + r)(bz + r) cells at stencil reach r.  Shapes
 # whose footprint outgrows the LDS tile lose on their own (fewer work-groups
 # per compute unit), so they need no pruning here.

@@ -324,17 +324,18 @@ std::vector<int> axis_blocks_max(int n, int maxsize) {
     return s;
 }
 
-// Partition n cells along an axis into an even number of blocks, each at
-// least `minsize` cells, sizes differing by at most one; a single block when
-// two blocks of minsize do not fit.  With an even count the blocks 2-colour
-// under the periodic wrap; same-coloured blocks are then separated by a
-// whole block, which keeps their write footprints apart when that block is
-// at least as wide as the footprint reaches past a block (the stencil's
-// reach, towards + only under corner grouping).
-std::vector<int> axis_blocks(int n, int minsize) {
-    if (n < 2 * minsize) return {0, n};
-    int m = n / minsize;
-    if (m & 1) m -= 1;
+// n cells cut into an even number m of near-equal blocks for the 2-colouring
+// of BLOCK8: m = ceil(n / maxsize) rounded up to even, then fewer by twos
+// while a block would be narrower than `reach`.  Same-coloured blocks are
+// then separated by a whole block, which keeps their write footprints apart
+// since a footprint reaches `reach` cells past its block (towards + only,
+// under corner grouping).  A single block when two do not fit.  Returns
+// block start offsets with n appended.
+std::vector<int> axis_blocks(int n, int maxsize, int reach) {
+    int m = (n + maxsize - 1) / maxsize;
+    if (m & 1) m += 1;
+    while (m >= 2 && n < m * reach) m -= 2;
+    if (m < 2) return {0, n};
     const int base = n / m, extra = n % m;
     std::vector<int> s(1, 0);
     int pos = 0;
@@ -404,25 +405,24 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
         err = "custom offsets must reach as far as the grid's stencil";
         return LC_EINVAL;
     }
-    // BLOCK8 colours its blocks, so their sizes are lower bounds (the
-    // stencil reach) with an even block count per axis; the uncoloured kinds
-    // take explicit sizes as upper bounds.
-    // (The tiled Newton-3 kinds group tasks by their lower corner cell, so
-    // a block's footprint grows by the reach towards +x, +y and +z only:
+    // Block sizes are upper bounds for every block kind.  (The tiled
+    // Newton-3 kinds group tasks by their lower corner cell, so a block's
+    // footprint grows by the reach towards +x, +y and +z only: BLOCK8's
     // same-coloured blocks stay apart when every block spans at least the
-    // reach along every axis.)
+    // reach, which its partition ensures.)
     const bool coloured = kind == LC_SCHED_BLOCK8;  // FULLSHELL: uncoloured
-    int32_t bmin[3] = {1, 2, 2};
-    if (reach == 2 && coloured) bmin[0] = bmin[1] = bmin[2] = 2;
+    // defaults: blocks of at most 1 x 3 x 3 cells; at reach 2, 2 x 2 x 2 for
+    // BLOCK8 and 1 x 2 x 2 for the uncoloured kinds (63 tasks per cell)
+    int32_t bmin[3] = {1, 3, 3};
+    if (reach == 2) {
+        bmin[0] = coloured ? 2 : 1;
+        bmin[1] = bmin[2] = 2;
+    }
     if (block_min) {
         for (int d = 0; d < 3; ++d) bmin[d] = block_min[d];
-        const int lo = coloured ? reach : 1;
-        const int lo_z = flat ? 1 : lo;  // a flat grid's z axis is one cell
-        if (bmin[0] < lo || bmin[1] < lo || bmin[2] < lo_z || bmin[0] > 64 || bmin[1] > 64 ||
+        if (bmin[0] < 1 || bmin[1] < 1 || bmin[2] < 1 || bmin[0] > 64 || bmin[1] > 64 ||
             bmin[2] > 64) {
-            err = coloured ? (reach == 2 ? "block sizes must be >= 2 (the stencil reach) and <= 64"
-                                         : "block sizes must be >= 1 and <= 64")
-                           : "block sizes must be >= 1 and <= 64";
+            err = "block sizes must be >= 1 and <= 64";
             return LC_EINVAL;
         }
     }
@@ -484,7 +484,7 @@ int build_schedule(const int32_t nc[3], int kind, const int8_t *offsets,
             // (uncoloured kinds at reach 2 default to blocks of at most
             // 1 x 2 x 2: their footprints stay inside the work-group limits)
             bs[d] = (!coloured && (block_min || reach == 2)) ? axis_blocks_max(nc[d], bmin[d])
-                                                             : axis_blocks(nc[d], bmin[d]);
+                                                             : axis_blocks(nc[d], bmin[d], reach);
         const int nb[3] = {(int)bs[0].size() - 1, (int)bs[1].size() - 1,
                            (int)bs[2].size() - 1};
         const int ncol[3] = {nb[0] > 1 ? 2 : 1, nb[1] > 1 ? 2 : 1, nb[2] > 1 ? 2 : 1};

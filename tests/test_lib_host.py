@@ -177,25 +177,32 @@ def test_fullshell_plan():
     assert big["ngroup"] == 4 * 4 * 4 and big["max_group_cells"] == 64
 
 
-def test_block8_sizes_are_lower_bounds():
-    """BLOCK8 block sizes are lower bounds of at least the stencil's reach:
-    corner grouping grows a footprint by the reach towards +x, +y and +z
-    only, so single cells colour at reach 1 (the 2 x 2 x 2 cube above each
-    cell of a colour class) and blocks of two cells at reach 2."""
-    g = lc.Grid((8 * 2.6,) * 3, 2.5)
+def test_block8_sizes_are_upper_bounds():
+    """BLOCK8 block sizes are upper bounds like the other block kinds: an
+    axis of n cells is cut into ceil(n / size) blocks rounded up to an even
+    count (the 2-colouring), fewer by twos while a block would be narrower
+    than the stencil's reach -- corner grouping grows a footprint by the
+    reach towards +x, +y and +z only, so single cells colour at reach 1 and
+    blocks of two cells at reach 2."""
+    g = lc.Grid((8 * 2.6,) * 3, 2.5)  # 8 cells per axis
+    assert g.nc == (8, 8, 8)
     with pytest.raises(lc.LCError):
         lc.schedule_plan(g, "block8", block=(0, 1, 1))
-    for blk in ((1, 1, 1), (1, 1, 2), (1, 2, 2)):
+    for blk, ngroup, cells in (((1, 1, 1), 512, 8), ((1, 2, 2), 8 * 4 * 4, 2 * 3 * 3),
+                               ((2, 3, 3), 4 * 4 * 4, 3 * 3 * 3)):
         info = lc.schedule_plan(g, "block8", block=blk)
         assert info["nphase"] == 8 and info["ntask"] == 14 * 512, blk
-    one = lc.schedule_plan(g, "block8", block=(1, 1, 1))
-    assert one["ngroup"] == 512 and one["max_group_cells"] == 8
+        assert info["ngroup"] == ngroup and info["max_group_cells"] == cells, blk
+    g7 = lc.Grid((7 * 2.6,) * 3, 2.5)  # 7 = 2+2+2+1: ceil(7/2) = 4 blocks, even
+    info = lc.schedule_plan(g7, "block8", block=(2, 2, 2))
+    assert info["ngroup"] == 4 ** 3 and info["max_group_cells"] == 3 ** 3
     h = lc.Grid((8 * 2.6,) * 3, 2.5, half=True)  # 16 cells per axis, reach 2
-    with pytest.raises(lc.LCError):
-        lc.schedule_plan(h, "block8", block=(1, 2, 2))
-    info = lc.schedule_plan(h, "block8", block=(2, 2, 2))
-    assert info["nphase"] == 8 and info["ntask"] == 63 * 16 ** 3
-    assert info["max_group_cells"] == 4 ** 3 and info["max_group_tasks"] == 63 * 8
+    assert h.nc == (16, 16, 16) and h.reach == 2
+    for blk in ((1, 1, 1), (2, 2, 2)):  # blocks of one cell would be too narrow
+        info = lc.schedule_plan(h, "block8", block=blk)
+        assert info["nphase"] == 8 and info["ntask"] == 63 * 16 ** 3
+        assert info["ngroup"] == 8 ** 3 and info["max_group_cells"] == 4 ** 3
+        assert info["max_group_tasks"] == 63 * 8
 
 
 def test_validator_rejects_shared_write():
