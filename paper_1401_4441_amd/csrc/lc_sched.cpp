@@ -329,10 +329,12 @@ std::vector<int> axis_blocks_max(int n, int maxsize) {
 // while a block would be narrower than `reach`.  Same-coloured blocks are
 // then separated by a whole block, which keeps their write footprints apart
 // since a footprint reaches `reach` cells past its block (towards + only,
-// under corner grouping).  A single block when two do not fit.  Returns
-// block start offsets with n appended.
+// under corner grouping).  A single block (no colours along this axis) when
+// maxsize covers the axis or two blocks do not fit.  Returns block start
+// offsets with n appended.
 std::vector<int> axis_blocks(int n, int maxsize, int reach) {
     int m = (n + maxsize - 1) / maxsize;
+    if (m <= 1) return {0, n};
     if (m & 1) m += 1;
     while (m >= 2 && n < m * reach) m -= 2;
     if (m < 2) return {0, n};

@@ -193,6 +193,10 @@ def test_block8_sizes_are_upper_bounds():
         info = lc.schedule_plan(g, "block8", block=blk)
         assert info["nphase"] == 8 and info["ntask"] == 14 * 512, blk
         assert info["ngroup"] == ngroup and info["max_group_cells"] == cells, blk
+    # a size covering an axis leaves one block there, and no colours along
+    # it: columns of 1 x 1 x 8 cells in 2 x 2 = 4 phases
+    cols = lc.schedule_plan(g, "block8", block=(1, 1, 8))
+    assert cols["nphase"] == 4 and cols["ngroup"] == 64 and cols["max_group_cells"] == 2 * 2 * 8
     g7 = lc.Grid((7 * 2.6,) * 3, 2.5)  # 7 = 2+2+2+1: ceil(7/2) = 4 blocks, even
     info = lc.schedule_plan(g7, "block8", block=(2, 2, 2))
     assert info["ngroup"] == 4 ** 3 and info["max_group_cells"] == 3 ** 3
@@ -443,7 +447,8 @@ def _coords(c, nc):
 
 @pytest.mark.parametrize("ncell_axis,reach,kind,block", [
     (7, 1, "buffer", (2, 2, 3)), (7, 1, "atomic_tile", (1, 1, 1)), (8, 1, "block8", (1, 1, 1)),
-    (8, 1, "block8", (1, 2, 2)), (9, 1, "buffer", (3, 3, 3)), (12, 2, "buffer", (2, 2, 2)),
+    (8, 1, "block8", (1, 2, 2)), (8, 1, "block8", (1, 1, 8)), (7, 1, "block8", (2, 2, 2)),
+    (9, 1, "buffer", (3, 3, 3)), (12, 2, "buffer", (2, 2, 2)),
     (12, 2, "block8", (2, 2, 2)), (13, 2, "atomic_tile", (1, 2, 3))])
 def test_tile_tasks_by_corner_cell(ncell_axis, reach, kind, block):
     """The tile kinds keep the stencil's tasks exactly (each (A, A + o) once,
