@@ -1415,32 +1415,52 @@ void k_sweep(SweepArgs a) {
     }
 }
 
-// Sum the spread partial slots into out[0..ncomp) in a fixed order (one
-// work-group of 256 threads), then clear the slots it read: every
-// evaluation leaves them zero for the next, so no clearing launch is
-// needed (the workspace zeroes them once when it is created).
-__device__ __forceinline__ void reduce_parts_wg(long long *__restrict__ part, int ncomp,
+// Sum the spread partial slots into out[0..NC) (one work-group of 256
+// threads; NC = 3 for {energy, virial, pairs}, 1 for the kinetic energy),
+// then clear the slots it read: every evaluation leaves them zero for the
+// next, so no clearing launch is needed (the workspace zeroes them once when
+// it is created).  Each thread issues all its loads before the sums, so the
+// work-group waits for one round trip.
+constexpr int kPartPer = kPartSlots / 256;
+static_assert(kPartSlots % 256 == 0, "partial slots per thread");
+
+template <int NC>
+__device__ __forceinline__ void reduce_parts_wg(long long *__restrict__ part,
                                                 long long *__restrict__ out, int half = 0) {
-    __shared__ long long s_w[4];
-    for (int c = 0; c < ncomp; ++c) {
-        long long v = 0;
-        for (int k = threadIdx.x; k < kPartSlots; k += 256) {
-            v += part[k * ncomp + c];
-            part[k * ncomp + c] = 0;
+    __shared__ long long s_w[4][NC];
+    long long x[kPartPer][NC];
+#pragma unroll
+    for (int r = 0; r < kPartPer; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[r][c] = part[(threadIdx.x + 256 * r) * NC + c];
+    long long v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = 0;
+#pragma unroll
+    for (int r = 0; r < kPartPer; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            v[c] += x[r][c];
+            part[(threadIdx.x + 256 * r) * NC + c] = 0;
         }
-        v = wave_sum64(v);
-        if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
-        __syncthreads();
-        // half: every pair was counted twice (full shell), so the sum is
-        // even and halves exactly
-        if (threadIdx.x == 0) out[c] = (s_w[0] + s_w[1] + s_w[2] + s_w[3]) >> half;
-        __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        v[c] = wave_sum64(v[c]);
+        if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6][c] = v[c];
+    }
+    __syncthreads();
+    // half: every pair was counted twice (full shell), so the sum is even
+    // and halves exactly
+    if (threadIdx.x < NC) {
+        const int c = threadIdx.x;
+        out[c] = (s_w[0][c] + s_w[1][c] + s_w[2][c] + s_w[3][c]) >> half;
     }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_parts(long long *__restrict__ part, int ncomp,
+template <int NC>
+__global__ __launch_bounds__(256) void k_reduce_parts(long long *__restrict__ part,
                                                       long long *__restrict__ out, int half) {
-    reduce_parts_wg(part, ncomp, out, half);
+    reduce_parts_wg<NC>(part, out, half);
 }
 
 // Buffer + reduce: F of every particle = sum of its cell's replica slots.
@@ -1452,7 +1472,7 @@ __global__ __launch_bounds__(256) void k_gather_partials(
     const long long *__restrict__ pbuf, const int *__restrict__ rcnt, int64_t n,
     long long *__restrict__ F, long long *__restrict__ part, long long *__restrict__ ew) {
     if (part && blockIdx.x == 0) {
-        reduce_parts_wg(part, 3, ew);
+        reduce_parts_wg<3>(part, ew);
         return;
     }
     const int64_t p = (int64_t)(blockIdx.x - (part ? 1 : 0)) * blockDim.x + threadIdx.x;
@@ -2035,7 +2055,7 @@ static int forces_run(const lc_grid *g, const lc_schedule *s, const int32_t *cel
                            (long long *)F, sc.part, (long long *)ew);
         LAUNCHCHK("k_gather_partials");
     } else {
-        hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, sc.part, 3,
+        hipLaunchKernelGGL(k_reduce_parts<3>, dim3(1), dim3(256), 0, st, sc.part,
                            (long long *)ew, fullshell ? 1 : 0);
         LAUNCHCHK("k_reduce_parts");
     }
@@ -2883,7 +2903,7 @@ extern "C" int lc_compute_forces_dataflow_log(const lc_grid *g, const lc_schedul
     else
         rc = small ? launch_dataflow<2, 64>(a, s->ncu, st) : launch_dataflow<2, 256>(a, s->ncu, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (long long *)ws->part, 3,
+    hipLaunchKernelGGL(k_reduce_parts<3>, dim3(1), dim3(256), 0, st, (long long *)ws->part,
                        (long long *)ew, 0);
     LAUNCHCHK("k_reduce_parts");
     return LC_OK;
@@ -2948,7 +2968,7 @@ extern "C" int lc_kinetic_energy(const double *vel, int64_t n, int64_t *ke, lc_w
                            (unsigned long long *)ws->part);
         LAUNCHCHK("k_kick_ke");
     }
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (long long *)ws->part, 1,
+    hipLaunchKernelGGL(k_reduce_parts<1>, dim3(1), dim3(256), 0, st, (long long *)ws->part,
                        (long long *)ke, 0);
     LAUNCHCHK("k_reduce_parts");
     return LC_OK;
@@ -3010,7 +3030,7 @@ extern "C" int lc_verlet_step(const lc_grid *g, const lc_schedule *s, double *po
                                hdt, step > 0 ? 1 : 0, (unsigned long long *)ws->part);
             LAUNCHCHK("k_kick_ke");
         }
-        hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, (long long *)ws->part, 1,
+        hipLaunchKernelGGL(k_reduce_parts<1>, dim3(1), dim3(256), 0, st, (long long *)ws->part,
                            row, 0);
         LAUNCHCHK("k_reduce_parts");
         hipLaunchKernelGGL(k_copy64, dim3(1), dim3(64), 0, st, (const long long *)ws->ew, row + 1, 1);
