@@ -604,6 +604,18 @@ int lc_batch_graph_create(const lc_batch *b, const int32_t *cell_start,
                           const uint32_t *coord, int64_t *F, int64_t *ew,
                           int persistent, lc_workspace *ws, void *stream,
                           lc_graph **out);
+/* HIP graph of one lc_compute_forces evaluation (Sec. IV's cell-pair tasks
+ * under schedule s: its phase launches and the closing gather or energy
+ * launch, in order) with fixed buffers, captured on `stream` (not the legacy
+ * null stream).  Replays recompute F and ew from the current contents of
+ * cell_start and coord, bit-identical to lc_compute_forces; replaying
+ * removes the per-launch host overhead between a schedule's launches.  The
+ * grid, s, ws and the buffers must outlive the graph; ws's replica buffer
+ * is pinned as for lc_batch_graph_create.  LC_EINVAL as lc_compute_forces,
+ * LC_EHIP when capture or instantiation fails. */
+int lc_forces_graph_create(const lc_grid *g, const lc_schedule *s, const int32_t *cell_start,
+                           const uint32_t *coord, int64_t n, int64_t *F, int64_t *ew,
+                           int precision, lc_workspace *ws, void *stream, lc_graph **out);
 int lc_graph_launch(lc_graph *gr, void *stream);
 void lc_graph_free(lc_graph *gr);
 

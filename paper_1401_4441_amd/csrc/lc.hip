@@ -3480,6 +3480,46 @@ extern "C" int lc_batch_graph_create(const lc_batch *b, const int32_t *cell_star
     return LC_OK;
 }
 
+// One force evaluation captured into a graph (the launches of
+// lc_compute_forces, in order).  Like the batch graph it pins the
+// workspace's replica buffer while it lives.
+extern "C" int lc_forces_graph_create(const lc_grid *g, const lc_schedule *s,
+                                      const int32_t *cell_start, const uint32_t *coord, int64_t n,
+                                      int64_t *F, int64_t *ew, int precision, lc_workspace *ws,
+                                      void *stream, lc_graph **out) {
+    if (!g || !s || !cell_start || !F || !ew || (n > 0 && !coord) || !out || !stream)
+        return fail(LC_EINVAL, "lc_forces_graph_create: bad arguments");
+    if (precision != LC_PREC_FP32 && precision != LC_PREC_FP64)
+        return fail(LC_EINVAL, "lc_forces_graph_create: precision");
+    if (s->nc[0] != g->nc[0] || s->nc[1] != g->nc[1] || s->nc[2] != g->nc[2])
+        return fail(LC_EINVAL, "lc_forces_graph_create: schedule built for another grid");
+    if (n < 0 || n >= 2147483647LL) return fail(LC_EINVAL, "lc_forces_graph_create: bad n");
+    int rc = check_ws(ws, 0, 0);
+    if (rc) return rc;
+    if (s->h.write_mode == 3 && (rc = ensure_pbuf(ws, pbuf_elems(s->h.rmax, n))))
+        return rc;  // outside capture
+    hipStream_t st = (hipStream_t)stream;
+    lc_graph *gr = new lc_graph();
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    rc = forces_impl(g, s, cell_start, coord, n, F, ew, precision, ws, st);
+    hipError_t e = hipStreamEndCapture(st, &gr->graph);
+    if (rc || e != hipSuccess) {
+        if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        delete gr;
+        return rc ? rc : fail(LC_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(gr->graph);
+        delete gr;
+        return fail(LC_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    gr->ws = ws;
+    ws->live_graphs++;
+    *out = gr;
+    return LC_OK;
+}
+
 extern "C" int lc_graph_launch(lc_graph *gr, void *stream) {
     if (!gr) return fail(LC_EINVAL, "null graph");
     HIPCHK(hipGraphLaunch(gr->exec, (hipStream_t)stream));

@@ -111,6 +111,7 @@ SYMBOLS = {
     "lc_batch_build_cells": ([P, P, P, P, P, P, P], INT),
     "lc_batch_forces": ([P, P, P, P, P, INT, P, P], INT),
     "lc_batch_graph_create": ([P, P, P, P, P, INT, P, P, P], INT),
+    "lc_forces_graph_create": ([P, P, P, P, I64, P, P, INT, P, P, P], INT),
     "lc_graph_launch": ([P, P], INT),
     "lc_graph_free": ([P], None),
 }
@@ -286,6 +287,7 @@ class Schedule:
             bp = None
         self.kind = int(kind)
         self.block = tuple(block) if block is not None else None
+        self._live_graphs = 0  # graphs captured with this schedule, alive
         if cell_counts is None:
             _chk(lib().lc_make_schedule_ex(grid.ptr, int(kind), op, int(n), bp,
                                            ctypes.byref(self._h)))
@@ -338,6 +340,8 @@ class Schedule:
         return A, B
 
     def close(self):
+        if self._live_graphs:
+            raise LCError(-7, "the schedule is held by a live graph: close the graph first")
         if self._h:
             lib().lc_schedule_free(self._h)
             self._h = ctypes.c_void_p()
@@ -452,6 +456,19 @@ def compute_forces(grid: Grid, sched: Schedule, cell_start, coord, ws: Workspace
                                  _p(F), _p(ew), PREC[precision], ws.ptr,
                                  _stream(stream)))
     return F, ew
+
+
+def forces_graph(grid: Grid, sched: Schedule, cell_start, coord, ws: Workspace, F, ew,
+                 stream, precision: str = "fp32") -> "Graph":
+    """Capture one compute_forces evaluation into a HIP graph on `stream`
+    (not the null stream); Graph.launch replays it (same buffers, current
+    contents)."""
+    n = coord.shape[1]
+    h = ctypes.c_void_p()
+    _chk(lib().lc_forces_graph_create(grid.ptr, sched.ptr, _p(cell_start), _p(coord), n,
+                                      _p(F), _p(ew), PREC[precision], ws.ptr,
+                                      _stream(stream), ctypes.byref(h)))
+    return Graph(h, sched, ws, (grid, cell_start, coord, F, ew))
 
 
 def compute_forces_noalloc(grid: Grid, sched: Schedule, cell_start, coord, F, ew,
@@ -624,9 +641,10 @@ class _BatchOpts(ctypes.Structure):
 
 
 class Graph:
-    """A captured HIP graph of one batched force evaluation.  It keeps the
-    batch, the workspace and the buffers it was captured with alive (the
-    graph holds their device addresses) until it is closed."""
+    """A captured HIP graph of one force evaluation (batched, or of one box
+    under a schedule).  It keeps the batch or schedule, the workspace and
+    the buffers it was captured with alive (the graph holds their device
+    addresses) until it is closed."""
 
     def __init__(self, handle, batch, ws, buffers):
         self._h = handle
