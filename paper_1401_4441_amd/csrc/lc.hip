@@ -733,7 +733,10 @@ __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, 
 // 16-bit coordinates of the candidate filter.
 template <int CAP, int WMODE, bool FF>
 struct SweepLDS {
-    uint4 u[CAP];                                           // box fractions
+    // box fractions, one array per axis (a random pair read is then three
+    // 4-byte reads, which conflict less in the LDS banks than one 12-byte
+    // read at a 16-byte stride)
+    uint32_t ux[CAP], uy[CAP], uz[CAP];
     // filter coordinates: the top 16 bits of the box fractions, x | y << 16
     // and z; the filter reads rows aoff .. aoff + kmax - 1 for every lane
     // (kmax: the wave's largest cell A), so it runs past the footprint by
@@ -808,7 +811,7 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
 
     auto load_u = [&](int l) -> uint4 {
         if constexpr (STAGED) {
-            return sh.u[l];
+            return make_uint4(sh.ux[l], sh.uy[l], sh.uz[l], 0u);
         } else {
             const int64_t gi = foot_gidx(sh, nf, l);
             return make_uint4(a.coord[gi], a.coord[n + gi], a.coord[2 * n + gi], 0u);
@@ -1248,7 +1251,9 @@ __device__ __forceinline__ void sweep_group(SweepLDS<CAP, WMODE, FF> &sh, const 
                     else if constexpr (WMODE == 1 || WMODE >= 3)
                         sh.acc[d][k] = 0;
                 }
-                sh.u[k] = make_uint4(ux, uy, uz, 0u);
+                sh.ux[k] = ux;
+                sh.uy[k] = uy;
+                sh.uz[k] = uz;
                 if constexpr (FF) sh.h[k] = make_uint2((ux >> 16) | (uy & 0xffff0000u), uz >> 16);
             }
         }
