@@ -23,7 +23,9 @@
 //   k_dataflow<MODE>        creation-order executors (ordered / mutex /
 //                           nested), one wave per task runner
 //   k_selftest_recip        the fast reciprocal against IEEE division
-//   k_kick_drift / k_kick_ke  velocity Verlet halves (FP64)
+//   k_kick_ke_drift / k_kick_ke  velocity Verlet halves (FP64): a step's
+//                           closing half kick with the kinetic energy, fused
+//                           with the next step's opening half kick and drift
 //   k_gather                reorder SoA rows by a permutation
 #include <hip/hip_runtime.h>
 
@@ -2089,29 +2091,6 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
 // a7: Verlet
 // ---------------------------------------------------------------------------
 
-__global__ void k_kick_drift(double *__restrict__ pos, double *__restrict__ vel,
-                             const long long *__restrict__ F, int64_t n, double hdt, double dt,
-                             const double *__restrict__ xref, double lim2, GridArgs ga,
-                             uint32_t *__restrict__ coord, uint32_t *__restrict__ flags) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double r2 = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        const int64_t k = d * n + i;
-        const double acc = (double)F[k] * (1.0 / 4294967296.0);
-        double v = vel[k];
-        v = v + hdt * acc;
-        double x = pos[k];
-        x = x + dt * v;
-        vel[k] = v;
-        pos[k] = x;
-        coord[k] = canon(x, ga.inv[d]);
-        const double dd = x - xref[k];
-        r2 += dd * dd;
-    }
-    if (r2 > lim2) atomicOr(flags, (uint32_t)LC_FLAG_DISP);
-}
-
 __global__ __launch_bounds__(256) void k_kick_ke(double *__restrict__ vel,
                                                  const long long *__restrict__ F, int64_t n,
                                                  double hdt, int kick,
@@ -2134,6 +2113,56 @@ __global__ __launch_bounds__(256) void k_kick_ke(double *__restrict__ vel,
         double s = v[0] * v[0] + v[1] * v[1];
         s = s + v[2] * v[2];
         q = (long long)rint((s * 0.5) * 4294967296.0);
+    }
+    q = wave_sum64(q);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) s_w[w] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        atomicAdd(&part[blockIdx.x % kPartSlots], (unsigned long long)t);
+    }
+}
+
+// The closing half kick of one step (with its kinetic energy, as k_kick_ke)
+// fused with the opening half kick and drift of the next:
+// both half kicks take the same forces, so one pass reads F, v, x and x_ref
+// once.  Per particle the arithmetic is the two kernels' own, in their
+// order, so the trajectory is bit-identical to running them one after the
+// other.
+__global__ __launch_bounds__(256) void k_kick_ke_drift(
+    double *__restrict__ pos, double *__restrict__ vel, const long long *__restrict__ F, int64_t n,
+    double hdt, double dt, int kick, const double *__restrict__ xref, double lim2, GridArgs ga,
+    uint32_t *__restrict__ coord, uint32_t *__restrict__ flags,
+    unsigned long long *__restrict__ part) {
+    __shared__ long long s_w[4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    long long q = 0;
+    if (i < n) {
+        double v[3], acc[3];
+        for (int d = 0; d < 3; ++d) {
+            const int64_t k = d * n + i;
+            acc[d] = (double)F[k] * (1.0 / 4294967296.0);
+            double x = vel[k];
+            if (kick) x = x + hdt * acc[d];
+            v[d] = x;
+        }
+        double s = v[0] * v[0] + v[1] * v[1];
+        s = s + v[2] * v[2];
+        q = (long long)rint((s * 0.5) * 4294967296.0);
+        double r2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const int64_t k = d * n + i;
+            const double w = v[d] + hdt * acc[d];
+            double x = pos[k];
+            x = x + dt * w;
+            vel[k] = w;
+            pos[k] = x;
+            coord[k] = canon(x, ga.inv[d]);
+            const double dd = x - xref[k];
+            r2 += dd * dd;
+        }
+        if (r2 > lim2) atomicOr(flags, (uint32_t)LC_FLAG_DISP);
     }
     q = wave_sum64(q);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -3016,21 +3045,24 @@ extern "C" int lc_verlet_step(const lc_grid *g, const lc_schedule *s, double *po
     // step 0: sort into cells at the current positions, forces, energies
     if ((rc = rebuild(g, pos, vel, ids, n, cell_start, perm, coord, ws, st))) return rc;
     if ((rc = forces_impl(g, s, cell_start, coord, n, F, ws->ew, LC_PREC_FP32, ws, st))) return rc;
+    // Step k: (rebuild), forces at x_k, the closing half kick to v_k with
+    // its kinetic energy, and -- fused into the same pass while another
+    // step follows -- the next step's opening half kick and drift to
+    // x_{k+1}.
     for (int step = 0; step <= nsteps; ++step) {
         if (step > 0) {
-            if (n > 0) {
-                hipLaunchKernelGGL(k_kick_drift, dim3(nbk), dim3(256), 0, st, pos, vel,
-                                   (const long long *)F, n, hdt, dt, ws->xref, lim2, ga, coord,
-                                   ws->flags);
-                LAUNCHCHK("k_kick_drift");
-            }
             if (step % rebuild_every == 0)
                 if ((rc = rebuild(g, pos, vel, ids, n, cell_start, perm, coord, ws, st))) return rc;
             if ((rc = forces_impl(g, s, cell_start, coord, n, F, ws->ew, LC_PREC_FP32, ws, st)))
                 return rc;
         }
         long long *row = (long long *)trace + 2 * step;
-        if (n > 0) {
+        if (n > 0 && step < nsteps) {
+            hipLaunchKernelGGL(k_kick_ke_drift, dim3(nbk), dim3(256), 0, st, pos, vel,
+                               (const long long *)F, n, hdt, dt, step > 0 ? 1 : 0, ws->xref,
+                               lim2, ga, coord, ws->flags, (unsigned long long *)ws->part);
+            LAUNCHCHK("k_kick_ke_drift");
+        } else if (n > 0) {
             hipLaunchKernelGGL(k_kick_ke, dim3(nbk), dim3(256), 0, st, vel, (const long long *)F, n,
                                hdt, step > 0 ? 1 : 0, (unsigned long long *)ws->part);
             LAUNCHCHK("k_kick_ke");
