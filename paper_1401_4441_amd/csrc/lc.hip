@@ -23,9 +23,11 @@
 //   k_dataflow<MODE>        creation-order executors (ordered / mutex /
 //                           nested), one wave per task runner
 //   k_selftest_recip        the fast reciprocal against IEEE division
-//   k_kick_ke_drift / k_kick_ke  velocity Verlet halves (FP64): a step's
-//                           closing half kick with the kinetic energy, fused
-//                           with the next step's opening half kick and drift
+//   k_kick_ke_drift / k_gather_kick_ke_drift / k_kick_ke
+//                           velocity Verlet halves (FP64): a step's closing
+//                           half kick with the kinetic energy, fused with the
+//                           next step's opening half kick and drift (and, for
+//                           buffer + reduce, with the replica gather)
 //   k_gather                reorder SoA rows by a permutation
 #include <hip/hip_runtime.h>
 
@@ -87,6 +89,7 @@ struct lc_workspace {
     uint32_t *flags = nullptr;   // device status flags
     int64_t *ew = nullptr;       // 3: energy, virial, pairs
     int64_t *part = nullptr;     // kPartSlots x 3 spread partial sums
+    int64_t *kpart = nullptr;    // kPartSlots spread kinetic-energy sums
     int64_t *ke = nullptr;       // 1
     double *xref = nullptr;      // 3N positions at the last rebuild
     double *tmp3 = nullptr;      // 3N staging for reorders
@@ -1989,9 +1992,13 @@ struct SweepScratch {
     int32_t max_per_cell;
 };
 
+// gather = false (buffer + reduce only): leave the replica slots and the
+// energy slots for the caller to sum (the Verlet loop folds both into its
+// kick pass); F and ew are not written.
 static int forces_run(const lc_grid *g, const lc_schedule *s, const int32_t *cell_start,
                       const uint32_t *coord, int64_t n, int64_t *F, int64_t *ew, int precision,
-                      const SweepScratch &sc, hipStream_t st, hipEvent_t *ev) {
+                      const SweepScratch &sc, hipStream_t st, hipEvent_t *ev,
+                      bool gather = true) {
     const bool buffered = s->h.write_mode == 3;
     const bool fullshell = s->h.write_mode == 4;  // writes every particle itself
     int rc = (buffered || fullshell) ? LC_OK : fill64((long long *)F, 3 * n, st);
@@ -2057,10 +2064,12 @@ static int forces_run(const lc_grid *g, const lc_schedule *s, const int32_t *cel
     }
     if (ev) HIPCHK(hipEventRecord(ev[2 * nphase], st));
     if (buffered && n > 0) {  // gather + the energy sums in one launch
-        hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((n + 255) / 256 + 1)), dim3(256), 0,
-                           st, (const long long *)sc.pbuf, (const int *)a.rcnt, n,
-                           (long long *)F, sc.part, (long long *)ew);
-        LAUNCHCHK("k_gather_partials");
+        if (gather) {
+            hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((n + 255) / 256 + 1)),
+                               dim3(256), 0, st, (const long long *)sc.pbuf,
+                               (const int *)a.rcnt, n, (long long *)F, sc.part, (long long *)ew);
+            LAUNCHCHK("k_gather_partials");
+        }
     } else {
         hipLaunchKernelGGL(k_reduce_parts<3>, dim3(1), dim3(256), 0, st, sc.part,
                            (long long *)ew, fullshell ? 1 : 0);
@@ -2074,7 +2083,8 @@ static int forces_run(const lc_grid *g, const lc_schedule *s, const int32_t *cel
 // the workspace's replica buffer on first use.
 static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *cell_start,
                        const uint32_t *coord, int64_t n, int64_t *F, int64_t *ew, int precision,
-                       lc_workspace *ws, hipStream_t st, hipEvent_t *ev = nullptr) {
+                       lc_workspace *ws, hipStream_t st, hipEvent_t *ev = nullptr,
+                       bool gather = true) {
     if (s->h.write_mode == 3) {
         int rc = ensure_pbuf(ws, pbuf_elems(s->h.rmax, n));
         if (rc) return rc;
@@ -2084,7 +2094,7 @@ static int forces_impl(const lc_grid *g, const lc_schedule *s, const int32_t *ce
     sc.flags = ws->flags;
     sc.pbuf = ws->pbuf;
     sc.max_per_cell = ws->max_per_cell;
-    return forces_run(g, s, cell_start, coord, n, F, ew, precision, sc, st, ev);
+    return forces_run(g, s, cell_start, coord, n, F, ew, precision, sc, st, ev, gather);
 }
 
 // ---------------------------------------------------------------------------
@@ -2171,6 +2181,69 @@ __global__ __launch_bounds__(256) void k_kick_ke_drift(
     if (threadIdx.x == 0) {
         const long long t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
         atomicAdd(&part[blockIdx.x % kPartSlots], (unsigned long long)t);
+    }
+}
+
+// k_kick_ke_drift for buffer + reduce schedules, with the gather folded in:
+// each particle's forces are the sum of its cell's replica slots (as
+// k_gather_partials sums them), read here instead of F, so the pass that
+// would write F and the read of it are gone.  The first work-group sums the
+// energy slots into ew (as the gather launch's extra work-group does); the
+// kinetic energy goes to its own slots.
+__global__ __launch_bounds__(256) void k_gather_kick_ke_drift(
+    const long long *__restrict__ pbuf, const int *__restrict__ rcnt, int64_t n,
+    double *__restrict__ pos, double *__restrict__ vel, double hdt, double dt, int kick,
+    const double *__restrict__ xref, double lim2, GridArgs ga, uint32_t *__restrict__ coord,
+    uint32_t *__restrict__ flags, unsigned long long *__restrict__ kpart,
+    long long *__restrict__ part, long long *__restrict__ ew) {
+    if (blockIdx.x == 0) {
+        reduce_parts_wg<3>(part, ew);
+        return;
+    }
+    __shared__ long long s_w[4];
+    const int64_t i = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
+    long long q = 0;
+    if (i < n) {
+        const int R = rcnt[i];
+        long long f[3] = {0, 0, 0};
+        for (int r = 0; r < R; ++r) {
+            const long long *P = pbuf + (int64_t)r * 3 * n;
+            f[0] += P[i];
+            f[1] += P[n + i];
+            f[2] += P[2 * n + i];
+        }
+        double v[3], acc[3];
+        for (int d = 0; d < 3; ++d) {
+            const int64_t k = d * n + i;
+            acc[d] = (double)f[d] * (1.0 / 4294967296.0);
+            double x = vel[k];
+            if (kick) x = x + hdt * acc[d];
+            v[d] = x;
+        }
+        double s = v[0] * v[0] + v[1] * v[1];
+        s = s + v[2] * v[2];
+        q = (long long)rint((s * 0.5) * 4294967296.0);
+        double r2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const int64_t k = d * n + i;
+            const double w = v[d] + hdt * acc[d];
+            double x = pos[k];
+            x = x + dt * w;
+            vel[k] = w;
+            pos[k] = x;
+            coord[k] = canon(x, ga.inv[d]);
+            const double dd = x - xref[k];
+            r2 += dd * dd;
+        }
+        if (r2 > lim2) atomicOr(flags, (uint32_t)LC_FLAG_DISP);
+    }
+    q = wave_sum64(q);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) s_w[w] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        atomicAdd(&kpart[(blockIdx.x - 1) % kPartSlots], (unsigned long long)t);
     }
 }
 
@@ -2261,6 +2334,7 @@ extern "C" void lc_workspace_destroy(lc_workspace *ws) {
     (void)hipFree(ws->flags);
     (void)hipFree(ws->ew);
     (void)hipFree(ws->part);
+    (void)hipFree(ws->kpart);
     (void)hipFree(ws->ke);
     (void)hipFree(ws->xref);
     (void)hipFree(ws->tmp3);
@@ -2285,7 +2359,8 @@ extern "C" int lc_workspace_create(int64_t max_n, int64_t max_cells, lc_workspac
     int rc = 0;
     if ((rc = dalloc(&ws->counts, max_cells)) ||
         (rc = dalloc(&ws->flags, 1)) || (rc = dalloc(&ws->ew, 3)) ||
-        (rc = dalloc(&ws->part, 3 * kPartSlots)) || (rc = dalloc(&ws->ke, 1)) ||
+        (rc = dalloc(&ws->part, 3 * kPartSlots)) || (rc = dalloc(&ws->kpart, kPartSlots)) ||
+        (rc = dalloc(&ws->ke, 1)) ||
         (rc = dalloc(&ws->xref, 3 * max_n)) || (rc = dalloc(&ws->tmp3, 3 * max_n)) ||
         (rc = dalloc(&ws->tmpi, max_n)) ||
         (rc = dalloc(&ws->lb_status, (max_cells + kLbTile - 1) / kLbTile)) ||
@@ -2295,6 +2370,7 @@ extern "C" int lc_workspace_create(int64_t max_n, int64_t max_cells, lc_workspac
     }
     if (hipMemset(ws->flags, 0, sizeof(uint32_t)) != hipSuccess ||
         hipMemset(ws->part, 0, 3 * kPartSlots * sizeof(int64_t)) != hipSuccess ||
+        hipMemset(ws->kpart, 0, kPartSlots * sizeof(int64_t)) != hipSuccess ||
         hipMemset(ws->counts, 0, (size_t)max_cells * sizeof(int)) != hipSuccess ||
         hipMemset(ws->lb_status, 0,
                   (size_t)((max_cells + kLbTile - 1) / kLbTile) * sizeof(unsigned long long)) !=
@@ -2321,6 +2397,7 @@ extern "C" int lc_workspace_clear_status(lc_workspace *ws, void *stream) {
     // abandoned scan may have left set
     hipStream_t st = (hipStream_t)stream;
     int rc = fill64((long long *)ws->part, 3 * kPartSlots, st);
+    if (!rc) rc = fill64((long long *)ws->kpart, kPartSlots, st);
     if (!rc) rc = fill32((int *)ws->flags, 1, st);
     if (!rc) rc = fill32(ws->counts, ws->max_cells, st);
     if (!rc) rc = fill64((long long *)ws->lb_status, ws->lb_tiles, st);
@@ -2999,10 +3076,10 @@ extern "C" int lc_kinetic_energy(const double *vel, int64_t n, int64_t *ke, lc_w
     if (n > 0) {
         hipLaunchKernelGGL(k_kick_ke, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                            (double *)vel, (const long long *)nullptr, n, 0.0, 0,
-                           (unsigned long long *)ws->part);
+                           (unsigned long long *)ws->kpart);
         LAUNCHCHK("k_kick_ke");
     }
-    hipLaunchKernelGGL(k_reduce_parts<1>, dim3(1), dim3(256), 0, st, (long long *)ws->part,
+    hipLaunchKernelGGL(k_reduce_parts<1>, dim3(1), dim3(256), 0, st, (long long *)ws->kpart,
                        (long long *)ke, 0);
     LAUNCHCHK("k_reduce_parts");
     return LC_OK;
@@ -3042,32 +3119,46 @@ extern "C" int lc_verlet_step(const lc_grid *g, const lc_schedule *s, double *po
     const double lim = 0.5 * g->skin;
     const double lim2 = lim * lim;
     const unsigned nbk = (unsigned)((n + 255) / 256);
-    // step 0: sort into cells at the current positions, forces, energies
-    if ((rc = rebuild(g, pos, vel, ids, n, cell_start, perm, coord, ws, st))) return rc;
-    if ((rc = forces_impl(g, s, cell_start, coord, n, F, ws->ew, LC_PREC_FP32, ws, st))) return rc;
     // Step k: (rebuild), forces at x_k, the closing half kick to v_k with
     // its kinetic energy, and -- fused into the same pass while another
     // step follows -- the next step's opening half kick and drift to
-    // x_{k+1}.
+    // x_{k+1}.  Buffer + reduce schedules sum their replica slots inside
+    // that pass (no gather launch, no F round trip) except at the last step,
+    // whose forces are returned in F.
+    const bool fold = s->h.write_mode == 3 && n > 0;
+    // step 0: sort into cells at the current positions, forces, energies
+    if ((rc = rebuild(g, pos, vel, ids, n, cell_start, perm, coord, ws, st))) return rc;
+    if ((rc = forces_impl(g, s, cell_start, coord, n, F, ws->ew, LC_PREC_FP32, ws, st, nullptr,
+                          !(fold && nsteps > 0))))
+        return rc;
     for (int step = 0; step <= nsteps; ++step) {
         if (step > 0) {
             if (step % rebuild_every == 0)
                 if ((rc = rebuild(g, pos, vel, ids, n, cell_start, perm, coord, ws, st))) return rc;
-            if ((rc = forces_impl(g, s, cell_start, coord, n, F, ws->ew, LC_PREC_FP32, ws, st)))
+            if ((rc = forces_impl(g, s, cell_start, coord, n, F, ws->ew, LC_PREC_FP32, ws, st,
+                                  nullptr, !(fold && step < nsteps))))
                 return rc;
         }
         long long *row = (long long *)trace + 2 * step;
-        if (n > 0 && step < nsteps) {
+        if (n > 0 && step < nsteps && fold) {
+            hipLaunchKernelGGL(k_gather_kick_ke_drift, dim3(nbk + 1), dim3(256), 0, st,
+                               (const long long *)ws->pbuf,
+                               (const int *)rcnt_of(ws, s->h.rmax, n), n, pos, vel, hdt, dt,
+                               step > 0 ? 1 : 0, ws->xref, lim2, ga, coord, ws->flags,
+                               (unsigned long long *)ws->kpart, (long long *)ws->part,
+                               (long long *)ws->ew);
+            LAUNCHCHK("k_gather_kick_ke_drift");
+        } else if (n > 0 && step < nsteps) {
             hipLaunchKernelGGL(k_kick_ke_drift, dim3(nbk), dim3(256), 0, st, pos, vel,
                                (const long long *)F, n, hdt, dt, step > 0 ? 1 : 0, ws->xref,
-                               lim2, ga, coord, ws->flags, (unsigned long long *)ws->part);
+                               lim2, ga, coord, ws->flags, (unsigned long long *)ws->kpart);
             LAUNCHCHK("k_kick_ke_drift");
         } else if (n > 0) {
             hipLaunchKernelGGL(k_kick_ke, dim3(nbk), dim3(256), 0, st, vel, (const long long *)F, n,
-                               hdt, step > 0 ? 1 : 0, (unsigned long long *)ws->part);
+                               hdt, step > 0 ? 1 : 0, (unsigned long long *)ws->kpart);
             LAUNCHCHK("k_kick_ke");
         }
-        hipLaunchKernelGGL(k_reduce_parts<1>, dim3(1), dim3(256), 0, st, (long long *)ws->part,
+        hipLaunchKernelGGL(k_reduce_parts<1>, dim3(1), dim3(256), 0, st, (long long *)ws->kpart,
                            row, 0);
         LAUNCHCHK("k_reduce_parts");
         hipLaunchKernelGGL(k_copy64, dim3(1), dim3(64), 0, st, (const long long *)ws->ew, row + 1, 1);

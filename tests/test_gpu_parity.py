@@ -361,10 +361,10 @@ def test_overflow_flag():
         O.forces_lc_fx(S.u, box.L, box.rc, S.g.nc)
 
 
-def _verlet_gpu(box, vel, dt, steps, rebuild, skin, chunks=(None,), check=False):
+def _verlet_gpu(box, vel, dt, steps, rebuild, skin, chunks=(None,), check=False, kind="block8"):
     g = lc.Grid(box.L, box.rc, skin)
     ws = lc.Workspace(box.n, g.ncell)
-    s = lc.Schedule(g, "block8")
+    s = lc.Schedule(g, kind)
     pos = torch.from_numpy(box.pos).to(DEV)
     v = torch.from_numpy(vel).to(DEV)
     ids = torch.arange(box.n, dtype=torch.int32, device=DEV)
@@ -378,6 +378,8 @@ def _verlet_gpu(box, vel, dt, steps, rebuild, skin, chunks=(None,), check=False)
     V = np.empty((3, box.n))
     P[:, idh] = pos.cpu().numpy()
     V[:, idh] = v.cpu().numpy()
+    _verlet_gpu.last_F = np.empty((3, box.n), dtype=np.int64)
+    _verlet_gpu.last_F[:, idh] = F.cpu().numpy()
     if check:
         try:
             ws.check()
@@ -387,25 +389,37 @@ def _verlet_gpu(box, vel, dt, steps, rebuild, skin, chunks=(None,), check=False)
     return P, V, traces, ws.status()
 
 
-def test_verlet_bit_exact_vs_oracle():
+_verlet_oracle = {}
+
+
+@pytest.mark.parametrize("kind", ["block8", "buffer", "atomic_tile"])
+def test_verlet_bit_exact_vs_oracle(kind):
     """Config 1 (4,000 particles) with thermal velocities: 100 kick-drift-kick
     steps at dt = 0.005, cells rebuilt every 10 steps (skin 0.6), bit-exact
-    positions, velocities and energy trace against the oracle."""
+    positions, velocities and energy trace against the oracle -- under
+    BLOCK8, under buffer + reduce (whose replica slots the kick pass sums
+    itself, without a gather launch) and under tile atomics."""
     box = synth.fcc(4000, 0.8, rc=2.5, seed=1001)
     vel = synth.maxwell_boltzmann(box.n, 1.0, seed=2001)
-    _say("verlet fcc4k 100 steps")
-    P, V, (tr,), st = _verlet_gpu(box, vel, 0.005, 100, 10, 0.6)
-    Po, Vo, Fo, tro = O.verlet_fx(box.pos, vel, box.L, box.rc, 0.005, 100)
+    _say("verlet fcc4k 100 steps", kind)
+    P, V, (tr,), st = _verlet_gpu(box, vel, 0.005, 100, 10, 0.6, kind=kind)
+    if "ref" not in _verlet_oracle:
+        _verlet_oracle["ref"] = O.verlet_fx(box.pos, vel, box.L, box.rc, 0.005, 100)
+    Po, Vo, Fo, tro = _verlet_oracle["ref"]
     assert st & lc.FLAG_DISP == 0
     assert (P == Po).all() and (V == Vo).all()
     assert (tr == tro).all()
+    assert (_verlet_gpu.last_F == Fo).all()  # the forces returned for the last step
 
 
-def test_verlet_resume_is_bit_exact():
+@pytest.mark.parametrize("kind", ["block8", "buffer"])
+def test_verlet_resume_is_bit_exact(kind):
+    """Twice 10 steps give the bits of 20 (and with buffer + reduce the
+    returned forces of the last step are the gathered ones)."""
     box = synth.fcc(2048, 0.8, rc=2.5, seed=12)
     vel = synth.maxwell_boltzmann(box.n, 1.0, seed=13)
-    P1, V1, _, _ = _verlet_gpu(box, vel, 0.005, 20, 10, 0.6)
-    P2, V2, trs, _ = _verlet_gpu(box, vel, 0.005, 20, 10, 0.6, chunks=(10, 10))
+    P1, V1, _, _ = _verlet_gpu(box, vel, 0.005, 20, 10, 0.6, kind=kind)
+    P2, V2, trs, _ = _verlet_gpu(box, vel, 0.005, 20, 10, 0.6, chunks=(10, 10), kind=kind)
     assert (P1 == P2).all() and (V1 == V2).all()
 
 
