@@ -556,11 +556,11 @@ int lc_batch_create(const lc_box_desc *boxes, int nbox, const int32_t *modes,
                                    tile-atomics baseline)                    */
 typedef struct lc_batch_opts {
     int32_t tile;       /* LDS tile (particles) a split box's block shape is
-                           sized for: the largest blocks of {2,3,3}, {1,3,3},
-                           {1,2,2}, {1,1,2}, {1,1,1} whose footprint is
-                           expected (box density + 35%) to fit; 512 (four
-                           work-groups per CU), 768 (0 = default, three),
-                           1024 or 2048                                     */
+                           sized for: the first of {3,3,3}, {2,3,3},
+                           {2,2,3}, {1,3,3}, {1,2,2}, {1,1,2}, {1,1,1}
+                           whose footprint is expected (box density + 35%)
+                           to fit; 512 (four work-groups per CU), 768 (0 =
+                           default, three), 1024 or 2048                    */
     int32_t write_mode; /* LC_BATCH_WRITE_*                                 */
 } lc_batch_opts;
 /* lc_batch_create with options (NULL = defaults); LC_EINVAL on other tile

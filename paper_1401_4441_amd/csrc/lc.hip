@@ -3363,9 +3363,10 @@ extern "C" int lc_batch_create_ex(const lc_box_desc *boxes, int nbox, const int3
             // the largest blocks whose footprint is expected (box density,
             // 35% headroom) to fit the tile (768 particles by default, which
             // runs three work-groups per CU); dense boxes take smaller blocks
-            // (more replicas)
-            static const int32_t kShapes[][3] = {{2, 3, 3}, {1, 3, 3}, {1, 2, 2}, {1, 1, 2},
-                                                 {1, 1, 1}};
+            // (more replicas).  Footprints (corner grouping): 64, 48, 36, 32,
+            // 18, 12 and 8 cells.
+            static const int32_t kShapes[][3] = {{3, 3, 3}, {2, 3, 3}, {2, 2, 3}, {1, 3, 3},
+                                                 {1, 2, 2}, {1, 1, 2}, {1, 1, 1}};
             lcs::HostSchedule hb;
             std::string err;
             int rc = 0;
