@@ -700,11 +700,15 @@ __device__ __forceinline__ void lj_terms(float inv, float dx, float dy, float dz
 
 // FP32 pair terms with the fast reciprocal and quantisation; same values as
 // pair_terms<false>.  BIASED: qe and qw come with kQ32Bias added (modulo
-// 2^64), for sums that remove the bias once per pair counted.
+// 2^64), for sums that remove the bias once per pair counted.  With a
+// non-null `flags`, the slow path raises LC_FLAG_OVERFLOW there itself and
+// `ovf` is scratch: a caller then carries no overflow state through its
+// loop (the fast path cannot overflow).
 template <bool BIASED = false>
 __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, const PairParams &p,
                                                 long long &qx, long long &qy, long long &qz,
-                                                long long &qe, long long &qw, uint32_t &ovf) {
+                                                long long &qe, long long &qw, uint32_t &ovf,
+                                                uint32_t *flags = nullptr) {
     float dx = canon_d(uj.x, ui.x, p.s[0]);
     float dy = canon_d(uj.y, ui.y, p.s[1]);
     float dz = canon_d(uj.z, ui.z, p.s[2]);
@@ -730,6 +734,7 @@ __device__ __forceinline__ bool pair_terms_fast(const uint4 ui, const uint4 uj, 
             qe = (long long)((unsigned long long)qe + (unsigned long long)kQ32Bias);
             qw = (long long)((unsigned long long)qw + (unsigned long long)kQ32Bias);
         }
+        if (flags && ovf) atomicOr(flags, (uint32_t)LC_FLAG_OVERFLOW);
     }
     return true;
 }
@@ -802,7 +807,10 @@ __device__ __forceinline__ int foot_cell(const L &sh, int nf, int l) {
 // group's tasks) and loop over the i particles of their task's cell A;
 // pairs inside the cutoff are compacted into a per-wave queue and evaluated
 // 128 at a time (two full-wave batches), so the Lennard-Jones arithmetic
-// runs on full waves.
+// runs on full waves.  A staged queue entry holds the byte offsets of the
+// pair's two rows in a 4-byte per-particle array, 4 i | 4 j << 16 (the LDS
+// reads take them as addresses as they are; i, j < CAP <= 2048); unstaged,
+// it holds i | j << 16 (up to 65535 footprint particles).
 template <int CAP, int WMODE, bool F64, bool STAGED, bool FF>
 __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const SweepArgs &a,
                                             const PairParams &pp, int f0, int nf, int nt,
@@ -813,12 +821,19 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
     const int64_t n = a.n;
     uint32_t *q = sh.q[wave];
     int qn = 0;  // wave-uniform queue length
+    constexpr uint32_t kEs = STAGED ? 2u : 0u;  // entry scale: i << kEs | j << (16 + kEs)
+    static_assert(!STAGED || CAP <= 16384, "staged entries hold 4 i in 16 bits");
 
-    auto load_u = [&](int l) -> uint4 {
+    // box fractions of the particle of entry field b (staged: the byte
+    // offset of its 4-byte rows; unstaged: its local index)
+    auto load_u = [&](uint32_t b) -> uint4 {
         if constexpr (STAGED) {
-            return make_uint4(sh.ux[l], sh.uy[l], sh.uz[l], 0u);
+            auto row = [&](const uint32_t *arr) {
+                return *(const uint32_t *)((const char *)arr + b);
+            };
+            return make_uint4(row(sh.ux), row(sh.uy), row(sh.uz), 0u);
         } else {
-            const int64_t gi = foot_gidx(sh, nf, l);
+            const int64_t gi = foot_gidx(sh, nf, (int)b);
             return make_uint4(a.coord[gi], a.coord[n + gi], a.coord[2 * n + gi], 0u);
         }
     };
@@ -827,38 +842,45 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
     // loads of two batches are in flight together, then evaluated (eval)
     struct PairIn {
         uint4 ui, uj;
-        int il, jl;
+        uint32_t bi, bj;  // the entry's two fields (see kEs)
     };
     auto load = [&](uint32_t ent) -> PairIn {
         PairIn r;
-        r.il = (int)(ent & 0xffffu);
-        r.jl = (int)(ent >> 16);
-        r.ui = load_u(r.il);
-        r.uj = load_u(r.jl);
+        r.bi = ent & 0xffffu;
+        r.bj = ent >> 16;
+        r.ui = load_u(r.bi);
+        r.uj = load_u(r.bj);
         return r;
     };
+    // int64 accumulator k of the staged particle whose 4-byte rows start at
+    // byte b
+    auto acc_at = [&](int k, uint32_t b) -> long long * {
+        return (long long *)((char *)&sh.acc[k][0] + 2 * b);
+    };
     auto eval = [&](const PairIn &pin) {
-        const int il = pin.il, jl = pin.jl;
+        const int il = (int)(pin.bi >> kEs), jl = (int)(pin.bj >> kEs);
         const uint4 ui = pin.ui, uj = pin.uj;
         long long qx, qy, qz, qe, qw;
         bool in;
-        if constexpr (F64)
+        if constexpr (F64) {
             in = pair_terms<true>(ui.x, ui.y, ui.z, uj.x, uj.y, uj.z, pp, qx, qy, qz, qe, qw, ovf);
-        else
-            in = pair_terms_fast<true>(ui, uj, pp, qx, qy, qz, qe, qw, ovf);
+        } else {
+            uint32_t o = 0u;  // the slow path raises the flag itself
+            in = pair_terms_fast<true>(ui, uj, pp, qx, qy, qz, qe, qw, o, a.flags);
+        }
         if (!in) return;
         // (FP32: biased energy and virial terms, corrected below)
         e_sum = (long long)((unsigned long long)e_sum + (unsigned long long)qe);
         w_sum = (long long)((unsigned long long)w_sum + (unsigned long long)qw);
         p_cnt += 1;
         if constexpr (STAGED && WMODE != 2) {
-            lds_sub64(&sh.acc[0][il], qx);  // ds_sub_u64: no negation
-            lds_sub64(&sh.acc[1][il], qy);
-            lds_sub64(&sh.acc[2][il], qz);
+            lds_sub64(acc_at(0, pin.bi), qx);  // ds_sub_u64: no negation
+            lds_sub64(acc_at(1, pin.bi), qy);
+            lds_sub64(acc_at(2, pin.bi), qz);
             if constexpr (WMODE != 4) {  // full shell: j gets its force from (j, i)
-                atomicAdd((unsigned long long *)&sh.acc[0][jl], (unsigned long long)qx);
-                atomicAdd((unsigned long long *)&sh.acc[1][jl], (unsigned long long)qy);
-                atomicAdd((unsigned long long *)&sh.acc[2][jl], (unsigned long long)qz);
+                atomicAdd((unsigned long long *)acc_at(0, pin.bj), (unsigned long long)qx);
+                atomicAdd((unsigned long long *)acc_at(1, pin.bj), (unsigned long long)qy);
+                atomicAdd((unsigned long long *)acc_at(2, pin.bj), (unsigned long long)qz);
             }
         } else {
             // global path: into F, or (buffer + reduce) into this group's
@@ -907,7 +929,7 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
         }
     };
     auto push = [&](bool in, int il, uint32_t jbits) {
-        push_ent(__ballot(in), in, (uint32_t)il | jbits);
+        push_ent(__ballot(in), in, ((uint32_t)il << kEs) | jbits);
     };
 
     const bool tables = nslot <= 64 * kMaxChunks;
@@ -940,7 +962,7 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
         const int bo = sh.tb[t];
         const bool intra = bo < 0;
         const int jl = (bo & 0x7fffffff) + jj;
-        const uint32_t jbits = (uint32_t)jl << 16;
+        const uint32_t jbits = (uint32_t)jl << (16 + kEs);
         const int ta = sh.ta[t];
         const int aoff = ta & 0xffff;
         // i runs over cell A; an intra task keeps each unordered pair once
@@ -960,7 +982,7 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             // intra: i before j (each unordered pair once), or, in the full
             // shell, every i but j itself
             const int lim = (intra && WMODE != 4) ? min(jj, na) : na;
-            const uint32_t rot = (uint32_t)jj & 31u;
+            const uint32_t rot = (uint32_t)jj & 31u, rot4 = rot << kEs;
             // one candidate row: 16-bit differences wrap modulo the box (the
             // minimum image up to one unit per axis); r2 - bound is negative
             // (sign bit set) inside, and the sign bit is shifted into m
@@ -999,16 +1021,18 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
                     if (intra && sj >= 0 && sj < kr) m &= ~(1u << (kr - 1 - sj));
                 }
                 m = __builtin_amdgcn_alignbit(m, m, rot);  // rotate right
-                // entry of the bit at (rotated) position p: (i | j << 16) with
-                // i = a0 + k0 + kr - 1 - ((p + rot) & 31), no borrow into j
-                const uint32_t ebase = (uint32_t)(a0 + k0 + kr - 1) | jbits;
+                // entry of the bit at (rotated) position p: (4 i | 4 j << 16)
+                // with i = a0 + k0 + kr - 1 - ((p + rot) & 31), no borrow
+                // into j
+                const uint32_t ebase = ((uint32_t)(a0 + k0 + kr - 1) << kEs) | jbits;
                 for (;;) {
                     const bool has = m != 0u;
                     const unsigned long long bal = __ballot(has);
                     if (!bal) break;
                     uint32_t e = 0u;
                     if (has) {
-                        e = ebase - (((uint32_t)__builtin_ctz(m) + rot) & 31u);
+                        e = ebase - ((((uint32_t)__builtin_ctz(m) << kEs) + rot4) &
+                                     (31u << kEs));
                         m &= m - 1u;
                     }
                     push_ent(bal, has, e);
@@ -1018,7 +1042,7 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
             // diagonal order: lane jj visits i = (k + jj) mod na, so lanes of
             // one task touch different i at each step (spreads the i-side
             // atomics); an intra task keeps a pair when i < j
-            const uint4 uj = valid ? load_u(jl) : make_uint4(0u, 0u, 0u, 0u);
+            const uint4 uj = valid ? load_u((uint32_t)jl << kEs) : make_uint4(0u, 0u, 0u, 0u);
             const int na = valid ? (ta >> 16) : 0;
             const int kdiag = tables ? kmax_c : wave_max32(na);
             int ik = na > 0 ? jj % na : 0;
@@ -1026,7 +1050,7 @@ __device__ __forceinline__ void sweep_pairs(SweepLDS<CAP, WMODE, FF> &sh, const 
                 const bool act = k < na && (!intra || (WMODE == 4 ? ik != jj : ik < jj));
                 bool in = false;
                 if (act) {
-                    const uint4 ui = load_u(aoff + ik);
+                    const uint4 ui = load_u((uint32_t)(aoff + ik) << kEs);
                     in = canon_r2(ui.x, ui.y, ui.z, uj.x, uj.y, uj.z, pp) < pp.rc2;
                 }
                 push(in, aoff + ik, jbits);
