@@ -1497,13 +1497,37 @@ __global__ __launch_bounds__(256) void k_reduce_parts(long long *__restrict__ pa
     reduce_parts_wg<NC>(part, out, half);
 }
 
+// Sum of particle p's replica slots 0 .. R-1 (slot r's three components at
+// pbuf[r 3n + c n + p]), two slots at a time, so that each thread has six
+// loads in flight.  Callers clamp R to the schedule's replica count, so a
+// stale count (from a group that gave up) cannot send the loads past the
+// buffer.
+__device__ __forceinline__ void sum_replicas(const long long *__restrict__ pbuf, int64_t n,
+                                             int64_t p, int R, long long f[3]) {
+    f[0] = f[1] = f[2] = 0;
+    int r = 0;
+    for (; r + 2 <= R; r += 2) {
+        const long long *P = pbuf + (int64_t)r * 3 * n, *Q = P + 3 * n;
+        const long long a0 = P[p], a1 = P[n + p], a2 = P[2 * n + p];
+        const long long b0 = Q[p], b1 = Q[n + p], b2 = Q[2 * n + p];
+        f[0] += a0 + b0;
+        f[1] += a1 + b1;
+        f[2] += a2 + b2;
+    }
+    if (r < R) {
+        const long long *P = pbuf + (int64_t)r * 3 * n;
+        f[0] += P[p];
+        f[1] += P[n + p];
+        f[2] += P[2 * n + p];
+    }
+}
+
 // Buffer + reduce: F of every particle = sum of its cell's replica slots.
 // With part != NULL one extra work-group (the first, dispatched before the
 // others, so its serial sums do not trail the launch) sums the energy slots
-// instead, which saves a launch.  The replicas are read two at a time, so
-// that each thread has six loads in flight.
+// instead, which saves a launch.
 __global__ __launch_bounds__(256) void k_gather_partials(
-    const long long *__restrict__ pbuf, const int *__restrict__ rcnt, int64_t n,
+    const long long *__restrict__ pbuf, const int *__restrict__ rcnt, int rmax, int64_t n,
     long long *__restrict__ F, long long *__restrict__ part, long long *__restrict__ ew) {
     if (part && blockIdx.x == 0) {
         reduce_parts_wg<3>(part, ew);
@@ -1511,26 +1535,11 @@ __global__ __launch_bounds__(256) void k_gather_partials(
     }
     const int64_t p = (int64_t)(blockIdx.x - (part ? 1 : 0)) * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const int R = rcnt[p];  // replicas of p's cell, recorded by the sweep
-    long long fx = 0, fy = 0, fz = 0;
-    int r = 0;
-    for (; r + 2 <= R; r += 2) {
-        const long long *P = pbuf + (int64_t)r * 3 * n, *Q = P + 3 * n;
-        const long long a0 = P[p], a1 = P[n + p], a2 = P[2 * n + p];
-        const long long b0 = Q[p], b1 = Q[n + p], b2 = Q[2 * n + p];
-        fx += a0 + b0;
-        fy += a1 + b1;
-        fz += a2 + b2;
-    }
-    if (r < R) {
-        const long long *P = pbuf + (int64_t)r * 3 * n;
-        fx += P[p];
-        fy += P[n + p];
-        fz += P[2 * n + p];
-    }
-    F[p] = fx;
-    F[n + p] = fy;
-    F[2 * n + p] = fz;
+    long long f[3];
+    sum_replicas(pbuf, n, p, min(rcnt[p], rmax), f);  // rcnt: p's cell's replicas (sweep)
+    F[p] = f[0];
+    F[n + p] = f[1];
+    F[2 * n + p] = f[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -2091,7 +2100,8 @@ static int forces_run(const lc_grid *g, const lc_schedule *s, const int32_t *cel
         if (gather) {
             hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((n + 255) / 256 + 1)),
                                dim3(256), 0, st, (const long long *)sc.pbuf,
-                               (const int *)a.rcnt, n, (long long *)F, sc.part, (long long *)ew);
+                               (const int *)a.rcnt, s->h.rmax, n, (long long *)F, sc.part,
+                               (long long *)ew);
             LAUNCHCHK("k_gather_partials");
         }
     } else {
@@ -2215,7 +2225,7 @@ __global__ __launch_bounds__(256) void k_kick_ke_drift(
 // energy slots into ew (as the gather launch's extra work-group does); the
 // kinetic energy goes to its own slots.
 __global__ __launch_bounds__(256) void k_gather_kick_ke_drift(
-    const long long *__restrict__ pbuf, const int *__restrict__ rcnt, int64_t n,
+    const long long *__restrict__ pbuf, const int *__restrict__ rcnt, int rmax, int64_t n,
     double *__restrict__ pos, double *__restrict__ vel, double hdt, double dt, int kick,
     const double *__restrict__ xref, double lim2, GridArgs ga, uint32_t *__restrict__ coord,
     uint32_t *__restrict__ flags, unsigned long long *__restrict__ kpart,
@@ -2228,14 +2238,8 @@ __global__ __launch_bounds__(256) void k_gather_kick_ke_drift(
     const int64_t i = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
     long long q = 0;
     if (i < n) {
-        const int R = rcnt[i];
-        long long f[3] = {0, 0, 0};
-        for (int r = 0; r < R; ++r) {
-            const long long *P = pbuf + (int64_t)r * 3 * n;
-            f[0] += P[i];
-            f[1] += P[n + i];
-            f[2] += P[2 * n + i];
-        }
+        long long f[3];
+        sum_replicas(pbuf, n, i, min(rcnt[i], rmax), f);
         double v[3], acc[3];
         for (int d = 0; d < 3; ++d) {
             const int64_t k = d * n + i;
@@ -3167,7 +3171,8 @@ extern "C" int lc_verlet_step(const lc_grid *g, const lc_schedule *s, double *po
         if (n > 0 && step < nsteps && fold) {
             hipLaunchKernelGGL(k_gather_kick_ke_drift, dim3(nbk + 1), dim3(256), 0, st,
                                (const long long *)ws->pbuf,
-                               (const int *)rcnt_of(ws, s->h.rmax, n), n, pos, vel, hdt, dt,
+                               (const int *)rcnt_of(ws, s->h.rmax, n), s->h.rmax, n, pos,
+                               vel, hdt, dt,
                                step > 0 ? 1 : 0, ws->xref, lim2, ga, coord, ws->flags,
                                (unsigned long long *)ws->kpart, (long long *)ws->part,
                                (long long *)ws->ew);
@@ -3584,8 +3589,8 @@ static int batch_forces_impl(const lc_batch *b, const int32_t *cell_start, const
         return rc;
     if (!atomic && b->ntot > 0) {
         hipLaunchKernelGGL(k_gather_partials, dim3((unsigned)((b->ntot + 255) / 256)), dim3(256), 0,
-                           st, (const long long *)ws->pbuf, (const int *)a.rcnt, b->ntot,
-                           (long long *)F, (long long *)nullptr, (long long *)nullptr);
+                           st, (const long long *)ws->pbuf, (const int *)a.rcnt, b->h.rmax,
+                           b->ntot, (long long *)F, (long long *)nullptr, (long long *)nullptr);
         LAUNCHCHK("k_gather_partials");
     }
     return LC_OK;
