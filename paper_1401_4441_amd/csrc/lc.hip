@@ -767,7 +767,7 @@ struct SweepLDS {
     unsigned long long cmask[kMaxChunks];
     int ckmax[kMaxChunks];
     long long w64[kNW + 1];
-    uint32_t q[kNW][kQ];    // per-wave queue of in-cutoff pairs (i | j << 16)
+    uint32_t q[kNW][kQ];    // per-wave queue of in-cutoff pairs (see sweep_pairs)
     long long red[kNW][3];
     int w[kNW + 1];
     int big;  // a footprint cell holds more than kFFCell particles
