@@ -31,7 +31,8 @@ BOX_KINDS_CONFLICT_FREE = ("block8", "buffer")
 # footprint is (bx + r)(by + r)(bz + r) cells at stencil reach r.  Shapes
 # whose footprint outgrows the LDS tile lose on their own (fewer work-groups
 # per compute unit), so they need no pruning here.
-BLOCKS = {"block8": ((1, 1, 1), (1, 1, 2), (1, 2, 2), (2, 2, 2), (1, 3, 3), (2, 3, 3)),
+BLOCKS = {"block8": ((1, 1, 1), (1, 1, 2), (1, 2, 2), (1, 2, 3), (2, 2, 2), (1, 3, 3),
+                     (2, 3, 3)),
           "uncoloured": ((1, 2, 2), (1, 2, 3), (1, 3, 3), (2, 2, 2), (2, 2, 3), (1, 3, 4),
                          (1, 4, 4), (2, 3, 3)),
           # cells of side rc/2 (reach 2): at most 8 cells per block (63
@@ -134,7 +135,7 @@ def tune_box(pos: torch.Tensor, L, rc: float, allow_atomics: bool = False,
     if kinds is None:
         kinds = BOX_KINDS_CONFLICT_FREE + (("atomic_tile",) if allow_atomics else ())
     kinds = tuple(kinds)
-    key = box_key(n, L, rc) + "|" + ",".join(kinds) + "|v5"
+    key = box_key(n, L, rc) + "|" + ",".join(kinds) + "|v6"
     cache = _load_cache() if use_cache else {}
     if key in cache:
         return cache[key]
